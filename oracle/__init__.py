@@ -1,0 +1,184 @@
+"""CPU oracle for the seed-count + approximate-edit-distance classifier.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg are the only users.  The product path (the HIP library and
+its Python binding) never imports, links or runs anything from here, and this
+package imports nothing from the product.
+
+The arithmetic lives in plain C (`oracle.c`, compiled with gcc); this module
+only marshals numpy arrays through ctypes.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_SO = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(out: str = _SO, extra_flags=()) -> str:
+    """Compiles oracle.c with gcc into a shared library."""
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", *extra_flags, "-o", out, _SRC]
+    subprocess.check_call(cmd)
+    return out
+
+
+def _p(a, t):
+    return a.ctypes.data_as(C.POINTER(t))
+
+
+def _declare(lib):
+    u8p, u16p, u32p, u64p, i64p = (C.POINTER(C.c_uint8), C.POINTER(C.c_uint16), C.POINTER(C.c_uint32),
+                                   C.POINTER(C.c_uint64), C.POINTER(C.c_int64))
+    lib.or_mix64.restype = C.c_uint64
+    lib.or_mix64.argtypes = [C.c_uint64]
+    lib.or_minimizers.restype = C.c_int64
+    lib.or_minimizers.argtypes = [u8p, C.c_int64, C.c_int, C.c_int, i64p, u64p]
+    lib.or_index_build.restype = C.c_void_p
+    lib.or_index_build.argtypes = [u8p, u64p, C.c_uint64, C.c_int, C.c_int, C.c_uint32, u32p, C.c_uint32]
+    lib.or_index_free.restype = None
+    lib.or_index_free.argtypes = [C.c_void_p]
+    lib.or_index_n_occ.restype = C.c_int64
+    lib.or_index_n_occ.argtypes = [C.c_void_p]
+    lib.or_approx.restype = C.c_int
+    lib.or_approx.argtypes = [u8p, C.c_int64, u8p, C.c_int64, C.c_int64, C.c_int]
+    lib.or_read_E.restype = C.c_int
+    lib.or_read_E.argtypes = [C.c_int64, C.c_uint32, C.c_uint32]
+    lib.or_classify.restype = C.c_void_p
+    lib.or_classify.argtypes = [C.c_void_p, u8p, u64p, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
+                                C.c_uint32]
+    lib.or_result_n_cands.restype = C.c_uint64
+    lib.or_result_n_cands.argtypes = [C.c_void_p]
+    lib.or_result_copy.restype = None
+    lib.or_result_copy.argtypes = [C.c_void_p, u64p, u8p, u16p, u32p, i64p, u32p, u16p, u8p, u64p, u64p, u64p]
+    lib.or_result_free.restype = None
+    lib.or_result_free.argtypes = [C.c_void_p]
+    lib.or_filter_pairs.restype = C.c_int
+    lib.or_filter_pairs.argtypes = [C.c_void_p, u8p, u64p, C.c_uint64, u32p, u32p, i64p, u16p, C.c_uint64,
+                                    u16p, u8p]
+    return lib
+
+
+def load(path: str | None = None):
+    """Loads the compiled oracle (building it first if it is not there)."""
+    global _lib
+    if path is not None:
+        return _declare(C.CDLL(path))
+    if _lib is None:
+        if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+            build()
+        _lib = _declare(C.CDLL(_SO))
+    return _lib
+
+
+def _u8(b) -> np.ndarray:
+    if isinstance(b, str):
+        b = b.encode()
+    if isinstance(b, (bytes, bytearray)):
+        return np.frombuffer(bytes(b) + b"\0", dtype=np.uint8)[:len(b)].copy()
+    return np.ascontiguousarray(b, dtype=np.uint8)
+
+
+def mix64(x: int, lib=None) -> int:
+    return int((lib or load()).or_mix64(C.c_uint64(x & (2**64 - 1))))
+
+
+def minimizers(seq, k: int, w: int, lib=None):
+    """Selected minimizer positions and their k-mer values (None on a bad byte)."""
+    lib = lib or load()
+    s = _u8(seq)
+    n = max(len(s) - k + 1, 1)
+    pos = np.zeros(n, np.int64)
+    x = np.zeros(n, np.uint64)
+    c = lib.or_minimizers(_p(s, C.c_uint8), len(s), k, w, _p(pos, C.c_int64), _p(x, C.c_uint64))
+    if c < 0:
+        return None
+    return pos[:c].copy(), x[:c].copy()
+
+
+def approx(q, ref, diag: int, E: int, lib=None) -> int:
+    """The filter on one pair: read q against reference ref at diagonal diag."""
+    lib = lib or load()
+    qa, ra = _u8(q), _u8(ref)
+    return int(lib.or_approx(_p(qa, C.c_uint8), len(qa), _p(ra, C.c_uint8), len(ra), int(diag), int(E)))
+
+
+def read_E(m: int, e_mode: int, e_value: int, lib=None) -> int:
+    return int((lib or load()).or_read_E(m, e_mode, e_value))
+
+
+class Index:
+    """Sorted-array seed index over genomes (ASCII SeqSet-like: .seq, .offsets)."""
+
+    def __init__(self, genomes, k: int, w: int, max_occ: int = 0, taxon=None, n_taxa=None, lib=None):
+        self.lib = lib or load()
+        self.seq = np.ascontiguousarray(genomes.seq, dtype=np.uint8)
+        self.offsets = np.ascontiguousarray(genomes.offsets, dtype=np.uint64)
+        n = len(self.offsets) - 1
+        self.n_genomes = n
+        if taxon is None:
+            taxon = np.arange(n, dtype=np.uint32)
+        self.taxon = np.ascontiguousarray(taxon, dtype=np.uint32)
+        self.n_taxa = int(n_taxa if n_taxa is not None else (int(self.taxon.max()) + 1 if n else 0))
+        self.k, self.w, self.max_occ = k, w, max_occ
+        h = self.lib.or_index_build(_p(self.seq, C.c_uint8), _p(self.offsets, C.c_uint64), n, k, w, max_occ,
+                                    _p(self.taxon, C.c_uint32), self.n_taxa)
+        if not h:
+            raise ValueError("oracle index build rejected its input")
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self.lib.or_index_free(self.h)
+            self.h = None
+
+    @property
+    def n_occ(self) -> int:
+        return int(self.lib.or_index_n_occ(self.h))
+
+    def classify(self, reads, min_hits=3, top_n=3, e_mode=0, e_value=7) -> dict:
+        seq = np.ascontiguousarray(reads.seq, dtype=np.uint8)
+        offs = np.ascontiguousarray(reads.offsets, dtype=np.uint64)
+        n = len(offs) - 1
+        r = self.lib.or_classify(self.h, _p(seq, C.c_uint8), _p(offs, C.c_uint64), n, min_hits, top_n,
+                                 e_mode, e_value)
+        if not r:
+            raise ValueError("oracle classify rejected its input")
+        nc = int(self.lib.or_result_n_cands(r))
+        out = dict(
+            cand_offsets=np.zeros(n + 1, np.uint64), read_accepted=np.zeros(n, np.uint8),
+            read_E=np.zeros(n, np.uint16), genome=np.zeros(nc, np.uint32), diag=np.zeros(nc, np.int64),
+            hits=np.zeros(nc, np.uint32), approx=np.zeros(nc, np.uint16), accept=np.zeros(nc, np.uint8),
+            unique=np.zeros(self.n_taxa, np.uint64), multi=np.zeros(self.n_taxa, np.uint64))
+        unm = np.zeros(1, np.uint64)
+        self.lib.or_result_copy(r, _p(out["cand_offsets"], C.c_uint64), _p(out["read_accepted"], C.c_uint8),
+                                _p(out["read_E"], C.c_uint16), _p(out["genome"], C.c_uint32),
+                                _p(out["diag"], C.c_int64), _p(out["hits"], C.c_uint32),
+                                _p(out["approx"], C.c_uint16), _p(out["accept"], C.c_uint8),
+                                _p(out["unique"], C.c_uint64), _p(out["multi"], C.c_uint64), _p(unm, C.c_uint64))
+        self.lib.or_result_free(r)
+        out["unmapped"] = int(unm[0])
+        return out
+
+    def filter_pairs(self, reads, pair_read, pair_genome, pair_diag, pair_E):
+        seq = np.ascontiguousarray(reads.seq, dtype=np.uint8)
+        offs = np.ascontiguousarray(reads.offsets, dtype=np.uint64)
+        pr = np.ascontiguousarray(pair_read, dtype=np.uint32)
+        pg = np.ascontiguousarray(pair_genome, dtype=np.uint32)
+        pd = np.ascontiguousarray(pair_diag, dtype=np.int64)
+        pe = np.ascontiguousarray(pair_E, dtype=np.uint16)
+        n = len(pr)
+        ap = np.zeros(n, np.uint16)
+        ac = np.zeros(n, np.uint8)
+        rc = self.lib.or_filter_pairs(self.h, _p(seq, C.c_uint8), _p(offs, C.c_uint64), len(offs) - 1,
+                                      _p(pr, C.c_uint32), _p(pg, C.c_uint32), _p(pd, C.c_int64),
+                                      _p(pe, C.c_uint16), n, _p(ap, C.c_uint16), _p(ac, C.c_uint8))
+        if rc != 0:
+            raise ValueError("oracle filter_pairs rejected its input")
+        return ap, ac

@@ -1,0 +1,534 @@
+/*
+ * CPU oracle for the seed-count + edit-distance-approximation read classifier
+ * of MetaTrinity (Gollwitzer et al., arXiv 2311.02029).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, obviously correct
+ * statement of what the GPU path computes.  Only the test suite, the smoke
+ * check and the benchmark's CPU-baseline leg may load it.  It shares no code,
+ * header, table or helper with the HIP library, and it includes none of it.
+ *
+ * Every step follows the paper's order:
+ *   stage 2a  a seed index over the (subset) reference database   (Fig. 1, 2a)
+ *   stage 2b  read seeding and seed matches                       (Fig. 1, 2b; "Alignment-free read-mapping")
+ *   stage 2c  drop locations below the seed-hit minimum, sort by
+ *             seed hits, keep the top locations                   (Fig. 1, 2c; "Empirically Determined Parameters")
+ *   stage 2d  approximate edit distance per (read, location) pair,
+ *             accept when it is within the threshold E            (Fig. 1, 2d; read-mapping Evaluation Methodology)
+ *   stage 3a  per-taxon unique / multi-mapped read counts         (Fig. 1, 3a)
+ * The approximation is the pigeonhole-family filter the paper rates best
+ * (SneakySnake, Table 1 and the Discussion of accuracy): the 2E+1 diagonals of
+ * the band around a location are turned into rows of mismatch bits ("obstacles")
+ * and a greedy walk from the read's first to its last base counts how many
+ * obstacles it has to cross, stopping once the count exceeds E.
+ *
+ * Readings where the paper is silent (each is listed in the design notes):
+ *   O1  codes A0 C1 G2 T3, N4, case-insensitive; any other byte is an error.
+ *       A k-mer containing N is never a seed.  N never matches anything (not
+ *       even N); a reference position outside the genome never matches.
+ *   O2  k-mer value x = sum code[i+t] * 4^(k-1-t) (first base most
+ *       significant); its hash is the splitmix64 finalizer (Steele, Lea and
+ *       Flood, OOPSLA 2014), a bijection of 64-bit words.
+ *   O3  minimizers: every window of w consecutive k-mer start positions picks
+ *       the valid position with the smallest (hash, position); the minimizer
+ *       set is the union of picks.  Fewer than w k-mers: one window over all.
+ *   O4  a mapping location is an exact diagonal (genome, q - p) of a seed
+ *       match; its seed-hit count is the number of (read minimizer, reference
+ *       minimizer occurrence) pairs with equal k-mer on that diagonal.  Keys
+ *       with more than max_occ occurrences are skipped (max_occ 0: no cap).
+ *   O5  keep hits >= min_hits; order by (hits desc, genome asc, diag asc);
+ *       keep the first top_n (0 keeps all).
+ *   O6  row d in [-E, E], column j in [0, m): obstacle iff Q[j] differs from
+ *       reference position diag + j + d (N / outside counts as different).
+ *       Walk: j = 0, c = 0; repeat { l = longest obstacle-free run starting at
+ *       column j over all rows (capped at m - j); j += l; stop if j >= m;
+ *       c += 1; stop if c > E; j += 1 }.  approx = min(c, E + 1).
+ *   O7  accept iff approx <= E.
+ *   O8  a read is accepted iff one of its candidates is.  Its mapped taxa are
+ *       the taxa of accepted candidates whose approx equals the smallest
+ *       accepted approx of the read; one taxon -> unique[t] += 1, several ->
+ *       multi[t] += 1 for each; none -> unmapped += 1.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_OK 0
+#define OR_EINVAL (-1)
+#define OR_ENOMEM (-2)
+
+#define MAX_READ_LEN 65535u
+
+/* ---------------------------------------------------------------- O1 ---- */
+
+static int base_code(uint8_t c)
+{
+    switch (c) {
+    case 'A': case 'a': return 0;
+    case 'C': case 'c': return 1;
+    case 'G': case 'g': return 2;
+    case 'T': case 't': return 3;
+    case 'N': case 'n': return 4;
+    default: return -1;
+    }
+}
+
+/* Codes of seq[0, len) into out; returns OR_EINVAL on a byte outside ACGTN. */
+static int encode(const uint8_t *seq, int64_t len, uint8_t *out)
+{
+    for (int64_t i = 0; i < len; i++) {
+        int c = base_code(seq[i]);
+        if (c < 0) return OR_EINVAL;
+        out[i] = (uint8_t)c;
+    }
+    return OR_OK;
+}
+
+/* ---------------------------------------------------------------- O2 ---- */
+
+uint64_t or_mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+/* ---------------------------------------------------------------- O3 ---- */
+
+/*
+ * Minimizers of one encoded sequence.  Writes the selected positions (in
+ * increasing order) and their k-mer values; returns how many were selected.
+ * pos_out / x_out must hold max(len - k + 1, 0) entries.
+ */
+static int64_t minimizers_of_codes(const uint8_t *code, int64_t len, int k, int w,
+                                   int64_t *pos_out, uint64_t *x_out)
+{
+    int64_t nk = len - k + 1;
+    if (nk <= 0) return 0;
+    uint64_t *x = malloc((size_t)nk * sizeof *x);
+    uint64_t *h = malloc((size_t)nk * sizeof *h);
+    uint8_t *valid = malloc((size_t)nk);
+    uint8_t *chosen = calloc((size_t)nk, 1);
+    for (int64_t i = 0; i < nk; i++) {
+        uint64_t v = 0;
+        int ok = 1;
+        for (int t = 0; t < k; t++) {
+            uint8_t c = code[i + t];
+            if (c == 4) ok = 0;
+            v = v * 4 + (c & 3);
+        }
+        x[i] = v;
+        h[i] = or_mix64(v);
+        valid[i] = (uint8_t)ok;
+    }
+    int64_t win = nk < w ? nk : w;           /* one window over all k-mers if fewer than w */
+    for (int64_t s = 0; s + win <= nk; s++) {
+        int64_t best = -1;
+        for (int64_t i = s; i < s + win; i++) {
+            if (!valid[i]) continue;
+            if (best < 0 || h[i] < h[best]) best = i;   /* strict '<': leftmost of equal hashes */
+        }
+        if (best >= 0) chosen[best] = 1;
+    }
+    int64_t n = 0;
+    for (int64_t i = 0; i < nk; i++) {
+        if (chosen[i]) {
+            pos_out[n] = i;
+            x_out[n] = x[i];
+            n++;
+        }
+    }
+    free(x); free(h); free(valid); free(chosen);
+    return n;
+}
+
+/* Minimizers of an ASCII sequence (returns -1 on an invalid byte). */
+int64_t or_minimizers(const uint8_t *seq, int64_t len, int k, int w,
+                      int64_t *pos_out, uint64_t *x_out)
+{
+    uint8_t *code = malloc((size_t)(len > 0 ? len : 1));
+    if (encode(seq, len, code) != OR_OK) { free(code); return -1; }
+    int64_t n = minimizers_of_codes(code, len, k, w, pos_out, x_out);
+    free(code);
+    return n;
+}
+
+/* ------------------------------------------------------ stage 2a index ---- */
+
+typedef struct {
+    uint64_t x;
+    uint32_t genome;
+    uint32_t pos;
+} occ_t;
+
+typedef struct or_index {
+    int k, w;
+    uint32_t max_occ;
+    uint64_t n_genomes;
+    uint8_t **gcode;          /* encoded genomes */
+    int64_t *glen;
+    uint32_t *taxon;          /* taxon of each genome */
+    uint32_t n_taxa;
+    occ_t *occ;               /* all reference minimizers, sorted by (x, genome, pos) */
+    int64_t n_occ;
+} or_index;
+
+static int cmp_occ(const void *a, const void *b)
+{
+    const occ_t *p = a, *q = b;
+    if (p->x != q->x) return p->x < q->x ? -1 : 1;
+    if (p->genome != q->genome) return p->genome < q->genome ? -1 : 1;
+    if (p->pos != q->pos) return p->pos < q->pos ? -1 : 1;
+    return 0;
+}
+
+void or_index_free(or_index *ix)
+{
+    if (!ix) return;
+    if (ix->gcode)
+        for (uint64_t g = 0; g < ix->n_genomes; g++) free(ix->gcode[g]);
+    free(ix->gcode); free(ix->glen); free(ix->taxon); free(ix->occ);
+    free(ix);
+}
+
+/*
+ * Builds the index over genomes given as ASCII with offsets[n+1].
+ * taxon: n entries (NULL = genome i is taxon i).  Returns NULL on error
+ * (bad byte, k outside 1..31, w outside 1..255, genome length >= 2^32 - 2^16).
+ */
+or_index *or_index_build(const uint8_t *seq, const uint64_t *offsets, uint64_t n,
+                         int k, int w, uint32_t max_occ,
+                         const uint32_t *taxon, uint32_t n_taxa)
+{
+    if (k < 1 || k > 31 || w < 1 || w > 255) return NULL;
+    or_index *ix = calloc(1, sizeof *ix);
+    ix->k = k; ix->w = w; ix->max_occ = max_occ; ix->n_genomes = n;
+    ix->gcode = calloc(n ? n : 1, sizeof *ix->gcode);
+    ix->glen = calloc(n ? n : 1, sizeof *ix->glen);
+    ix->taxon = calloc(n ? n : 1, sizeof *ix->taxon);
+    ix->n_taxa = n_taxa;
+    int64_t cap = 0;
+    for (uint64_t g = 0; g < n; g++) {
+        int64_t len = (int64_t)(offsets[g + 1] - offsets[g]);
+        if (len >= (int64_t)4294901760LL) { or_index_free(ix); return NULL; }
+        ix->glen[g] = len;
+        ix->gcode[g] = malloc((size_t)(len > 0 ? len : 1));
+        if (encode(seq + offsets[g], len, ix->gcode[g]) != OR_OK) { or_index_free(ix); return NULL; }
+        ix->taxon[g] = taxon ? taxon[g] : (uint32_t)g;
+        if (ix->taxon[g] >= n_taxa) { or_index_free(ix); return NULL; }
+        cap += len;
+    }
+    ix->occ = malloc((size_t)(cap > 0 ? cap : 1) * sizeof *ix->occ);
+    int64_t maxlen = 1;
+    for (uint64_t g = 0; g < n; g++) if (ix->glen[g] > maxlen) maxlen = ix->glen[g];
+    int64_t *pos = malloc((size_t)maxlen * sizeof *pos);
+    uint64_t *x = malloc((size_t)maxlen * sizeof *x);
+    for (uint64_t g = 0; g < n; g++) {
+        int64_t c = minimizers_of_codes(ix->gcode[g], ix->glen[g], k, w, pos, x);
+        for (int64_t i = 0; i < c; i++) {
+            occ_t o = { x[i], (uint32_t)g, (uint32_t)pos[i] };
+            ix->occ[ix->n_occ++] = o;
+        }
+    }
+    free(pos); free(x);
+    qsort(ix->occ, (size_t)ix->n_occ, sizeof *ix->occ, cmp_occ);
+    return ix;
+}
+
+int64_t or_index_n_occ(const or_index *ix) { return ix->n_occ; }
+
+/* First index in occ with occ.x >= x. */
+static int64_t lower_bound(const occ_t *occ, int64_t n, uint64_t x)
+{
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = lo + (hi - lo) / 2;
+        if (occ[mid].x < x) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+/* -------------------------------------------------------- O6 filter ---- */
+
+/* Is reference position p of genome g a mismatch for read code qc? */
+static int obstacle(uint8_t qc, const uint8_t *gcode, int64_t glen, int64_t p)
+{
+    if (qc == 4) return 1;
+    if (p < 0 || p >= glen) return 1;
+    uint8_t rc = gcode[p];
+    if (rc == 4) return 1;
+    return qc != rc;
+}
+
+/*
+ * Approximate edit distance of read q[0,m) at location (genome, diag) with
+ * threshold E: the obstacle count of O6, saturated at E + 1.
+ */
+static int approx_codes(const uint8_t *q, int64_t m, const uint8_t *gcode, int64_t glen,
+                        int64_t diag, int E)
+{
+    int64_t rows = 2 * (int64_t)E + 1;
+    uint8_t *M = malloc((size_t)(rows * (m > 0 ? m : 1)));
+    for (int64_t r = 0; r < rows; r++) {
+        int64_t d = r - E;
+        for (int64_t j = 0; j < m; j++)
+            M[r * m + j] = (uint8_t)obstacle(q[j], gcode, glen, diag + j + d);
+    }
+    int64_t j = 0;
+    int c = 0;
+    for (;;) {
+        int64_t best = 0;
+        for (int64_t r = 0; r < rows; r++) {
+            int64_t run = 0;
+            while (j + run < m && M[r * m + j + run] == 0) run++;
+            if (run > best) best = run;
+        }
+        j += best;
+        if (j >= m) break;
+        c += 1;
+        if (c > E) break;
+        j += 1;
+    }
+    free(M);
+    return c < E + 1 ? c : E + 1;
+}
+
+/* The filter on ASCII inputs: read q[0,m), reference ref[0,L).  -1 on a bad byte. */
+int or_approx(const uint8_t *q, int64_t m, const uint8_t *ref, int64_t L, int64_t diag, int E)
+{
+    uint8_t *qc = malloc((size_t)(m > 0 ? m : 1));
+    uint8_t *rc = malloc((size_t)(L > 0 ? L : 1));
+    int r = -1;
+    if (encode(q, m, qc) == OR_OK && encode(ref, L, rc) == OR_OK)
+        r = approx_codes(qc, m, rc, L, diag, E);
+    free(qc); free(rc);
+    return r;
+}
+
+/* ---------------------------------------------------- classification ---- */
+
+/* E of a read of length m: mode 0 fixed, 1 ceil(m*v/1000), 2 floor(m*v/1000). */
+int or_read_E(int64_t m, uint32_t e_mode, uint32_t e_value)
+{
+    if (e_mode == 0) return (int)e_value;
+    uint64_t num = (uint64_t)m * e_value;
+    if (e_mode == 1) return (int)((num + 999) / 1000);
+    return (int)(num / 1000);
+}
+
+typedef struct { uint32_t genome; int64_t diag; } hit_t;
+typedef struct { uint32_t genome; int64_t diag; uint32_t hits; } cand_t;
+
+static int cmp_hit(const void *a, const void *b)
+{
+    const hit_t *p = a, *q = b;
+    if (p->genome != q->genome) return p->genome < q->genome ? -1 : 1;
+    if (p->diag != q->diag) return p->diag < q->diag ? -1 : 1;
+    return 0;
+}
+
+/* O5 order: hits descending, then genome ascending, then diagonal ascending. */
+static int cmp_cand(const void *a, const void *b)
+{
+    const cand_t *p = a, *q = b;
+    if (p->hits != q->hits) return p->hits > q->hits ? -1 : 1;
+    if (p->genome != q->genome) return p->genome < q->genome ? -1 : 1;
+    if (p->diag != q->diag) return p->diag < q->diag ? -1 : 1;
+    return 0;
+}
+
+typedef struct or_result {
+    uint64_t n_reads;
+    uint64_t *cand_offsets;    /* n_reads + 1 */
+    uint8_t *read_accepted;    /* n_reads */
+    uint16_t *read_E;          /* n_reads */
+    uint64_t n_cands;
+    uint32_t *genome;
+    int64_t *diag;
+    uint32_t *hits;
+    uint16_t *approx;
+    uint8_t *accept;
+    uint32_t n_taxa;
+    uint64_t *unique_reads;
+    uint64_t *multi_reads;
+    uint64_t unmapped;
+    uint64_t cap;
+} or_result;
+
+void or_result_free(or_result *r)
+{
+    if (!r) return;
+    free(r->cand_offsets); free(r->read_accepted); free(r->read_E);
+    free(r->genome); free(r->diag); free(r->hits); free(r->approx); free(r->accept);
+    free(r->unique_reads); free(r->multi_reads);
+    free(r);
+}
+
+static void push_cand(or_result *r, const cand_t *c)
+{
+    if (r->n_cands == r->cap) {
+        r->cap = r->cap ? 2 * r->cap : 1024;
+        r->genome = realloc(r->genome, r->cap * sizeof *r->genome);
+        r->diag = realloc(r->diag, r->cap * sizeof *r->diag);
+        r->hits = realloc(r->hits, r->cap * sizeof *r->hits);
+        r->approx = realloc(r->approx, r->cap * sizeof *r->approx);
+        r->accept = realloc(r->accept, r->cap * sizeof *r->accept);
+    }
+    r->genome[r->n_cands] = c->genome;
+    r->diag[r->n_cands] = c->diag;
+    r->hits[r->n_cands] = c->hits;
+    r->n_cands++;
+}
+
+/*
+ * Classifies reads (ASCII + offsets[n+1]).  Returns NULL on an invalid input
+ * (bad byte, read longer than 65535, E above 65534).
+ */
+or_result *or_classify(const or_index *ix, const uint8_t *seq, const uint64_t *offsets, uint64_t n,
+                       uint32_t min_hits, uint32_t top_n, uint32_t e_mode, uint32_t e_value)
+{
+    or_result *res = calloc(1, sizeof *res);
+    res->n_reads = n;
+    res->cand_offsets = calloc(n + 1, sizeof *res->cand_offsets);
+    res->read_accepted = calloc(n ? n : 1, 1);
+    res->read_E = calloc(n ? n : 1, sizeof *res->read_E);
+    res->n_taxa = ix->n_taxa;
+    res->unique_reads = calloc(ix->n_taxa ? ix->n_taxa : 1, sizeof(uint64_t));
+    res->multi_reads = calloc(ix->n_taxa ? ix->n_taxa : 1, sizeof(uint64_t));
+    uint8_t *taxon_seen = calloc(ix->n_taxa ? ix->n_taxa : 1, 1);
+
+    for (uint64_t r = 0; r < n; r++) {
+        int64_t m = (int64_t)(offsets[r + 1] - offsets[r]);
+        int E = or_read_E(m, e_mode, e_value);
+        if (m > (int64_t)MAX_READ_LEN || E > 65534) { free(taxon_seen); or_result_free(res); return NULL; }
+        res->read_E[r] = (uint16_t)E;
+        uint8_t *q = malloc((size_t)(m > 0 ? m : 1));
+        if (encode(seq + offsets[r], m, q) != OR_OK) {
+            free(q); free(taxon_seen); or_result_free(res); return NULL;
+        }
+
+        /* stage 2b: read minimizers and their seed matches -> (genome, diag) hits */
+        int64_t nk = m - ix->k + 1 > 0 ? m - ix->k + 1 : 0;
+        int64_t *mpos = malloc((size_t)(nk ? nk : 1) * sizeof *mpos);
+        uint64_t *mx = malloc((size_t)(nk ? nk : 1) * sizeof *mx);
+        int64_t nmin = minimizers_of_codes(q, m, ix->k, ix->w, mpos, mx);
+        int64_t nh = 0, hcap = 64;
+        hit_t *hit = malloc((size_t)hcap * sizeof *hit);
+        for (int64_t i = 0; i < nmin; i++) {
+            int64_t lo = lower_bound(ix->occ, ix->n_occ, mx[i]);
+            int64_t hi = lo;
+            while (hi < ix->n_occ && ix->occ[hi].x == mx[i]) hi++;
+            if (ix->max_occ > 0 && hi - lo > (int64_t)ix->max_occ) continue;
+            for (int64_t o = lo; o < hi; o++) {
+                if (nh == hcap) { hcap *= 2; hit = realloc(hit, (size_t)hcap * sizeof *hit); }
+                hit[nh].genome = ix->occ[o].genome;
+                hit[nh].diag = (int64_t)ix->occ[o].pos - mpos[i];
+                nh++;
+            }
+        }
+        free(mpos); free(mx);
+
+        /* stage 2b/2c: seed hits per location, minimum, order, top N */
+        qsort(hit, (size_t)nh, sizeof *hit, cmp_hit);
+        cand_t *cand = malloc((size_t)(nh ? nh : 1) * sizeof *cand);
+        int64_t nc = 0;
+        for (int64_t i = 0; i < nh;) {
+            int64_t j = i;
+            while (j < nh && hit[j].genome == hit[i].genome && hit[j].diag == hit[i].diag) j++;
+            if ((uint64_t)(j - i) >= min_hits) {
+                cand[nc].genome = hit[i].genome;
+                cand[nc].diag = hit[i].diag;
+                cand[nc].hits = (uint32_t)(j - i);
+                nc++;
+            }
+            i = j;
+        }
+        free(hit);
+        qsort(cand, (size_t)nc, sizeof *cand, cmp_cand);
+        if (top_n > 0 && nc > (int64_t)top_n) nc = top_n;
+
+        /* stage 2d: approximate edit distance + accept per pair */
+        uint64_t first = res->n_cands;
+        int best = -1;
+        for (int64_t c = 0; c < nc; c++) {
+            push_cand(res, &cand[c]);
+            uint32_t g = cand[c].genome;
+            int a = approx_codes(q, m, ix->gcode[g], ix->glen[g], cand[c].diag, E);
+            res->approx[res->n_cands - 1] = (uint16_t)a;
+            res->accept[res->n_cands - 1] = (uint8_t)(a <= E);
+            if (a <= E && (best < 0 || a < best)) best = a;
+        }
+        res->cand_offsets[r + 1] = res->n_cands;
+        free(cand);
+        free(q);
+
+        /* stage 3a: per-taxon unique / multi-mapped counts */
+        if (best < 0) {
+            res->unmapped++;
+            continue;
+        }
+        res->read_accepted[r] = 1;
+        uint32_t ntax = 0, only = 0;
+        for (uint64_t c = first; c < res->n_cands; c++) {
+            if (!res->accept[c] || res->approx[c] != best) continue;
+            uint32_t t = ix->taxon[res->genome[c]];
+            if (!taxon_seen[t]) { taxon_seen[t] = 1; ntax++; only = t; }
+        }
+        for (uint64_t c = first; c < res->n_cands; c++) {
+            if (!res->accept[c] || res->approx[c] != best) continue;
+            uint32_t t = ix->taxon[res->genome[c]];
+            if (taxon_seen[t]) {
+                taxon_seen[t] = 0;
+                if (ntax > 1) res->multi_reads[t]++;
+            }
+        }
+        if (ntax == 1) res->unique_reads[only]++;
+    }
+    free(taxon_seen);
+    return res;
+}
+
+uint64_t or_result_n_cands(const or_result *r) { return r->n_cands; }
+
+/* Copies a result into caller arrays (sizes from or_result_n_cands / n_reads / n_taxa). */
+void or_result_copy(const or_result *r, uint64_t *cand_offsets, uint8_t *read_accepted, uint16_t *read_E,
+                    uint32_t *genome, int64_t *diag, uint32_t *hits, uint16_t *approx, uint8_t *accept,
+                    uint64_t *unique_reads, uint64_t *multi_reads, uint64_t *unmapped)
+{
+    memcpy(cand_offsets, r->cand_offsets, (r->n_reads + 1) * sizeof *cand_offsets);
+    memcpy(read_accepted, r->read_accepted, r->n_reads);
+    memcpy(read_E, r->read_E, r->n_reads * sizeof *read_E);
+    if (r->n_cands) {
+        memcpy(genome, r->genome, r->n_cands * sizeof *genome);
+        memcpy(diag, r->diag, r->n_cands * sizeof *diag);
+        memcpy(hits, r->hits, r->n_cands * sizeof *hits);
+        memcpy(approx, r->approx, r->n_cands * sizeof *approx);
+        memcpy(accept, r->accept, r->n_cands);
+    }
+    memcpy(unique_reads, r->unique_reads, r->n_taxa * sizeof *unique_reads);
+    memcpy(multi_reads, r->multi_reads, r->n_taxa * sizeof *multi_reads);
+    *unmapped = r->unmapped;
+}
+
+/*
+ * The filter alone over explicit pairs (pair_read indexes the reads).  Used to
+ * check a filter kernel on pair lists.  Returns OR_EINVAL on a bad byte or an
+ * out-of-range genome / read index.
+ */
+int or_filter_pairs(const or_index *ix, const uint8_t *seq, const uint64_t *offsets, uint64_t n_reads,
+                    const uint32_t *pair_read, const uint32_t *pair_genome, const int64_t *pair_diag,
+                    const uint16_t *pair_E, uint64_t n_pairs, uint16_t *approx_out, uint8_t *accept_out)
+{
+    for (uint64_t p = 0; p < n_pairs; p++) {
+        if (pair_read[p] >= n_reads || pair_genome[p] >= ix->n_genomes) return OR_EINVAL;
+        uint64_t r = pair_read[p];
+        int64_t m = (int64_t)(offsets[r + 1] - offsets[r]);
+        uint8_t *q = malloc((size_t)(m > 0 ? m : 1));
+        if (encode(seq + offsets[r], m, q) != OR_OK) { free(q); return OR_EINVAL; }
+        uint32_t g = pair_genome[p];
+        int a = approx_codes(q, m, ix->gcode[g], ix->glen[g], pair_diag[p], pair_E[p]);
+        approx_out[p] = (uint16_t)a;
+        accept_out[p] = (uint8_t)(a <= pair_E[p]);
+        free(q);
+    }
+    return OR_OK;
+}

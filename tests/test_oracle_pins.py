@@ -1,0 +1,514 @@
+"""Pins of the CPU oracle against things other than itself.
+
+Each test checks the oracle against what the paper and the mathematics fix,
+never against a retyped copy of the oracle's own code:
+  * the published SplitMix64 outputs (the k-mer hash) and the hash's inverse;
+  * Python's own base-4 integer parsing for k-mer values;
+  * a second formulation of minimizer selection;
+  * brute-force all-pairs seed matching for hit counts and candidate lists;
+  * textbook banded edit-distance DPs (semi-global, global) and Hamming
+    distance, which the obstacle count may never exceed;
+  * an independent minimum-cover DP the greedy walk must equal;
+  * exact in-band occurrence <=> zero; E = 0 <=> capped Hamming; a planted
+    single edit <=> exactly one;
+  * hand-worked filter cases and brute-force per-taxon counts.
+"""
+import os
+import random
+from collections import Counter
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+M64 = (1 << 64) - 1
+CODE = {"A": 0, "C": 1, "G": 2, "T": 3, "N": 4}
+
+
+# ----------------------------------------------------------------- hashing ---
+
+def _golden_lines(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return [ln.split("#")[0].strip() for ln in f if ln.split("#")[0].strip()]
+
+
+def test_mix64_published_splitmix64_outputs():
+    lines = _golden_lines("splitmix64_seed0.txt")
+    gamma = int(lines[0].split()[1], 16)
+    state = 0
+    for want in lines[1:]:
+        state = (state + gamma) & M64
+        assert oracle.mix64(state) == int(want, 16)
+
+
+def _unxorshift(y, s):
+    x = y
+    for _ in range(64 // s + 1):
+        x = y ^ (x >> s)
+    return x & M64
+
+
+def _mix64_inverse(z):
+    z = _unxorshift(z, 31)
+    z = (z * pow(0x94d049bb133111eb, -1, 1 << 64)) & M64
+    z = _unxorshift(z, 27)
+    z = (z * pow(0xbf58476d1ce4e5b9, -1, 1 << 64)) & M64
+    return _unxorshift(z, 30)
+
+
+def test_mix64_is_a_bijection():
+    rnd = random.Random(5)
+    for _ in range(2000):
+        x = rnd.getrandbits(64)
+        assert _mix64_inverse(oracle.mix64(x)) == x
+    for x in (0, 1, M64, 1 << 63):
+        assert _mix64_inverse(oracle.mix64(x)) == x
+
+
+# -------------------------------------------------------------- minimizers ---
+
+def _kmers(seq, k):
+    """(x, valid) per k-mer start, x from Python's base-4 parser."""
+    out = []
+    for i in range(len(seq) - k + 1):
+        s = seq[i:i + k].upper()
+        if "N" in s:
+            out.append((None, False))
+        else:
+            out.append((int(s.translate(str.maketrans("ACGT", "0123")), 4), True))
+    return out
+
+
+def _minimizers_second_form(seq, k, w):
+    """Position i is a minimizer iff some window of w k-mer starts (or the single
+    window over all k-mers when there are fewer than w) contains i and (h_i, i)
+    is the smallest (hash, position) over the valid k-mers of that window."""
+    km = _kmers(seq, k)
+    nk = len(km)
+    if nk <= 0:
+        return [], []
+    win = min(w, nk)
+    h = [oracle.mix64(x) if v else None for x, v in km]
+    pos, xs = [], []
+    for i in range(nk):
+        if not km[i][1]:
+            continue
+        for s in range(max(0, i - win + 1), min(i, nk - win) + 1):
+            if all((h[i], i) <= (h[t], t) for t in range(s, s + win) if km[t][1]):
+                pos.append(i)
+                xs.append(km[i][0])
+                break
+    return pos, xs
+
+
+def test_kmer_value_is_base4_first_base_most_significant():
+    pos, x = oracle.minimizers("ACGT", 4, 1)
+    assert list(pos) == [0] and int(x[0]) == 0 * 64 + 1 * 16 + 2 * 4 + 3
+    pos, x = oracle.minimizers("TTTTTTTTTTTTTTTTTTTTTTTTTTTTTTT", 31, 1)
+    assert int(x[0]) == 4 ** 31 - 1
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_minimizers_match_second_formulation(seed):
+    rnd = random.Random(seed)
+    for _ in range(150):
+        n = rnd.randint(0, 60)
+        alpha = rnd.choice(["ACGT", "AC", "ACGTN", "ACGTTTTN", "acgt"])
+        seq = "".join(rnd.choice(alpha) for _ in range(n))
+        k = rnd.randint(1, 8)
+        w = rnd.randint(1, 12)
+        got = oracle.minimizers(seq, k, w)
+        want = _minimizers_second_form(seq, k, w)
+        assert list(got[0]) == want[0], (seq, k, w)
+        assert [int(v) for v in got[1]] == want[1], (seq, k, w)
+
+
+def test_minimizer_edge_cases():
+    assert len(oracle.minimizers("ACG", 4, 3)[0]) == 0            # shorter than k
+    assert len(oracle.minimizers("NNNNNNNN", 3, 2)[0]) == 0       # every k-mer has N
+    assert oracle.minimizers("ACGX", 2, 2) is None                # bad byte
+    # fewer k-mers than w: exactly one window, so exactly one minimizer
+    assert len(oracle.minimizers("ACGTAC", 3, 10)[0]) == 1
+    # w = 1 selects every valid k-mer
+    assert list(oracle.minimizers("ACGTNACGT", 3, 1)[0]) == [0, 1, 5, 6]
+
+
+# ------------------------------------------------- seed hits & candidates ---
+
+def _brute_candidates(genomes, reads, k, w, min_hits, top_n, max_occ=0):
+    """All-pairs seed matching: every read minimizer against every reference
+    minimizer occurrence; a location is (genome, q - p)."""
+    occ = {}
+    for g, gs in enumerate(genomes):
+        for q, x in zip(*_minimizers_second_form(gs, k, w)):
+            occ.setdefault(x, []).append((g, q))
+    out = []
+    for rs in reads:
+        cnt = Counter()
+        for p, x in zip(*_minimizers_second_form(rs, k, w)):
+            lst = occ.get(x, [])
+            if max_occ and len(lst) > max_occ:
+                continue
+            for g, q in lst:
+                cnt[(g, q - p)] += 1
+        cands = sorted(((h, g, d) for (g, d), h in cnt.items() if h >= min_hits),
+                       key=lambda t: (-t[0], t[1], t[2]))
+        if top_n:
+            cands = cands[:top_n]
+        out.append(cands)
+    return out
+
+
+def _oracle_cands(res, n):
+    co = res["cand_offsets"].astype(np.int64)
+    return [[(int(res["hits"][c]), int(res["genome"][c]), int(res["diag"][c])) for c in range(co[r], co[r + 1])]
+            for r in range(n)]
+
+
+def _repetitive_case(rnd, n_gen, glen, n_reads, motif_len):
+    motifs = ["".join(rnd.choice("ACGT") for _ in range(motif_len)) for _ in range(3)]
+    genomes = []
+    for _ in range(n_gen):
+        s = ""
+        while len(s) < glen:
+            s += rnd.choice(motifs) if rnd.random() < 0.6 else rnd.choice("ACGT")
+        genomes.append(s[:glen])
+    reads = []
+    for _ in range(n_reads):
+        g = rnd.choice(genomes)
+        m = rnd.randint(0, 30)
+        st = rnd.randint(-3, max(0, len(g) - m))
+        r = list(g[max(st, 0):max(st, 0) + m])
+        for i in range(len(r)):
+            if rnd.random() < 0.05:
+                r[i] = rnd.choice("ACGTN")
+        reads.append("".join(r))
+    return genomes, reads
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_candidates_match_brute_force(seed):
+    rnd = random.Random(100 + seed)
+    genomes, reads = _repetitive_case(rnd, rnd.randint(1, 4), rnd.randint(20, 120), 40, rnd.randint(3, 7))
+    k, w = rnd.randint(2, 6), rnd.randint(1, 5)
+    min_hits = rnd.choice([1, 2, 3])
+    top_n = rnd.choice([0, 1, 3])
+    max_occ = rnd.choice([0, 0, 3])
+    ix = oracle.Index(synth.SeqSet.from_list(genomes), k, w, max_occ=max_occ)
+    rs = synth.SeqSet.from_list(reads)
+    res = ix.classify(rs, min_hits=min_hits, top_n=top_n, e_mode=0, e_value=2)
+    assert _oracle_cands(res, len(reads)) == _brute_candidates(genomes, reads, k, w, min_hits, top_n, max_occ)
+
+
+def test_candidate_threshold_is_inclusive_and_topn_zero_keeps_all():
+    genome = "ACGTTGCAAGGCTTACCGTAGGATCCATGACGTTAGC" * 2
+    ix = oracle.Index(synth.SeqSet.from_list([genome]), 4, 1)
+    read = genome[5:25]
+    rs = synth.SeqSet.from_list([read])
+    full = _brute_candidates([genome], [read], 4, 1, 1, 0)[0]
+    top_hits = full[0][0]
+    res = ix.classify(rs, min_hits=top_hits, top_n=0, e_mode=0, e_value=0)
+    assert _oracle_cands(res, 1)[0] == [c for c in full if c[0] >= top_hits]
+    res = ix.classify(rs, min_hits=top_hits + 1, top_n=0, e_mode=0, e_value=0)
+    assert _oracle_cands(res, 1)[0] == []
+
+
+# ------------------------------------------------------------------ filter ---
+
+def _obstacles(q, ref, diag, E):
+    """rows[d + E][j] = 1 iff read base j cannot match reference diag + j + d."""
+    rows = []
+    for d in range(-E, E + 1):
+        row = []
+        for j, c in enumerate(q.upper()):
+            p = diag + j + d
+            rc = ref[p].upper() if 0 <= p < len(ref) else None
+            row.append(int(c == "N" or rc is None or rc == "N" or c != rc))
+        rows.append(row)
+    return rows
+
+
+def _window(ref, diag, E, m):
+    """W[i] = reference base diag - E + i, None outside the genome."""
+    return [ref[p].upper() if 0 <= p < len(ref) else None for p in range(diag - E, diag + m + E)]
+
+
+def _eq(a, b):
+    return a is not None and b is not None and a != "N" and b != "N" and a == b
+
+
+def semi_global_banded(q, ref, diag, E):
+    """Sellers-style DP: free start in the first 2E+1 window columns, free end,
+    cells restricted to 0 <= i - j <= 2E (i window prefix, j read prefix)."""
+    q = q.upper()
+    m = len(q)
+    W = _window(ref, diag, E, m)
+    INF = 1 << 30
+    prev = {i: 0 for i in range(0, 2 * E + 1)}
+    for j in range(1, m + 1):
+        cur = {}
+        for i in range(j, j + 2 * E + 1):
+            best = INF
+            if i - 1 in prev:
+                best = min(best, prev[i - 1] + (0 if _eq(q[j - 1], W[i - 1]) else 1))
+            if i in prev:
+                best = min(best, prev[i] + 1)
+            if i - 1 in cur:
+                best = min(best, cur[i - 1] + 1)
+            cur[i] = best
+        prev = cur
+    return min(prev.values())
+
+
+def global_banded(q, ref, diag, E):
+    """Ukkonen-band global distance from window column E to column m + E."""
+    q = q.upper()
+    m = len(q)
+    W = _window(ref, diag, E, m)
+    INF = 1 << 30
+    prev = {i: (i - E if i >= E else INF) for i in range(0, 2 * E + 1)}
+    for j in range(1, m + 1):
+        cur = {}
+        for i in range(j, j + 2 * E + 1):
+            best = INF
+            if i - 1 in prev:
+                best = min(best, prev[i - 1] + (0 if _eq(q[j - 1], W[i - 1]) else 1))
+            if i in prev:
+                best = min(best, prev[i] + 1)
+            if i - 1 in cur:
+                best = min(best, cur[i - 1] + 1)
+            cur[i] = best
+        prev = cur
+    return prev[m + E]
+
+
+def hamming0(q, ref, diag):
+    return sum(_obstacles(q, ref, diag, 0)[0])
+
+
+def min_cover(rows, m):
+    """Fewest skipped columns over covers of [0, m) by alternating obstacle-free
+    runs (any row, any length >= 0) and single skipped columns."""
+    C = [0] * (m + 1)
+    for j in range(m - 1, -1, -1):
+        best = 1 << 30
+        for row in rows:
+            run = 0
+            while j + run < m and row[j + run] == 0:
+                run += 1
+            for ln in range(run + 1):
+                best = min(best, 0 if j + ln >= m else 1 + C[j + ln + 1])
+        C[j] = best
+    return C[0]
+
+
+def exact_in_band(q, ref, diag, E):
+    return any(all(v == 0 for v in row) for row in _obstacles(q, ref, diag, E))
+
+
+def _rand_pair(rnd, max_m=40, max_E=6):
+    L = rnd.randint(1, 70)
+    alpha = rnd.choice(["ACGT", "AC", "ACGTN"])
+    ref = "".join(rnd.choice(alpha) for _ in range(L))
+    m = rnd.randint(0, max_m)
+    st = rnd.randint(-4, L)
+    q = list(ref[max(st, 0):max(st, 0) + m])
+    while len(q) < m:
+        q.append(rnd.choice("ACGT"))
+    i = 0
+    while i < len(q):
+        u = rnd.random()
+        if u < 0.06:
+            q[i] = rnd.choice("ACGTN")
+        elif u < 0.09:
+            q.insert(i, rnd.choice("ACGT"))
+        elif u < 0.12:
+            del q[i]
+        i += 1
+    q = "".join(q[:m])
+    diag = st + rnd.randint(-2, 2)
+    E = rnd.randint(0, max_E)
+    return q, ref, diag, E
+
+
+def test_filter_handworked_golden():
+    for ln in _golden_lines("approx_handworked.txt"):
+        q, ref, diag, E, want = ln.split()
+        assert oracle.approx(q, ref, int(diag), int(E)) == int(want), ln
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_filter_never_exceeds_banded_edit_distance(seed):
+    """approx <= min(SG_E, E+1), and SG_E <= GL_E <= Hamming on row 0."""
+    rnd = random.Random(1000 + seed)
+    for _ in range(1500):
+        q, ref, diag, E = _rand_pair(rnd)
+        a = oracle.approx(q, ref, diag, E)
+        sg = semi_global_banded(q, ref, diag, E)
+        gl = global_banded(q, ref, diag, E)
+        assert 0 <= a <= E + 1
+        assert a <= min(sg, E + 1), (q, ref, diag, E, a, sg)
+        assert sg <= gl <= hamming0(q, ref, diag)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_filter_equals_min_cover_dp(seed):
+    rnd = random.Random(2000 + seed)
+    for _ in range(1500):
+        q, ref, diag, E = _rand_pair(rnd)
+        a = oracle.approx(q, ref, diag, E)
+        assert a == min(min_cover(_obstacles(q, ref, diag, E), len(q)), E + 1), (q, ref, diag, E)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_filter_zero_iff_exact_occurrence_in_band(seed):
+    rnd = random.Random(3000 + seed)
+    for _ in range(2000):
+        q, ref, diag, E = _rand_pair(rnd)
+        assert (oracle.approx(q, ref, diag, E) == 0) == exact_in_band(q, ref, diag, E), (q, ref, diag, E)
+    for _ in range(300):     # identical strings give zero
+        ref = "".join(rnd.choice("ACGT") for _ in range(rnd.randint(1, 60)))
+        st = rnd.randint(0, len(ref) - 1)
+        q = ref[st:st + rnd.randint(1, len(ref) - st)]
+        assert oracle.approx(q, ref, st, rnd.randint(0, 5)) == 0
+
+
+def test_filter_E0_is_capped_hamming():
+    rnd = random.Random(4000)
+    for _ in range(3000):
+        q, ref, diag, _ = _rand_pair(rnd)
+        assert oracle.approx(q, ref, diag, 0) == min(hamming0(q, ref, diag), 1)
+
+
+def test_filter_planted_single_edit_is_one():
+    rnd = random.Random(5000)
+    seen = Counter()
+    while sum(seen.values()) < 1500:
+        ref = "".join(rnd.choice("ACGT") for _ in range(rnd.randint(20, 80)))
+        st = rnd.randint(0, len(ref) - 12)
+        m = rnd.randint(10, len(ref) - st - 1)
+        q = list(ref[st:st + m])
+        kind = rnd.choice(["sub", "ins", "del"])
+        i = rnd.randint(0, m - 1)
+        if kind == "sub":
+            q[i] = rnd.choice([c for c in "ACGT" if c != q[i]])
+        elif kind == "ins":
+            q.insert(i, rnd.choice("ACGT"))
+            q = q[:m]
+        else:
+            del q[i]
+            q.append(ref[st + m])
+        q = "".join(q)
+        E = rnd.randint(1, 5)
+        if exact_in_band(q, ref, st, E):
+            continue
+        assert oracle.approx(q, ref, st, E) == 1, (q, ref, st, E, kind)
+        seen[kind] += 1
+    assert min(seen.values()) > 300
+
+
+def test_filter_sparse_substitutions_statistics():
+    """Not parity: on random sequences with sparse substitutions the count is
+    almost always the number of substitutions."""
+    rnd = random.Random(6000)
+    agree = 0
+    N = 400
+    for _ in range(N):
+        ref = "".join(rnd.choice("ACGT") for _ in range(200))
+        q = list(ref[20:170])
+        ns = rnd.randint(0, 4)
+        for i in rnd.sample(range(150), ns):
+            q[i] = rnd.choice([c for c in "ACGT" if c != q[i]])
+        agree += oracle.approx("".join(q), ref, 20, 7) == ns
+    assert agree >= 0.9 * N
+
+
+# ------------------------------------------------------- E, reads, taxa ---
+
+def test_read_E_modes():
+    assert oracle.read_E(150, 0, 7) == 7
+    assert oracle.read_E(150, 1, 50) == 8     # ceil(7.5)
+    assert oracle.read_E(150, 2, 50) == 7     # floor(7.5)
+    assert oracle.read_E(100, 1, 50) == 5 and oracle.read_E(100, 2, 50) == 5
+    assert oracle.read_E(0, 1, 50) == 0
+    assert oracle.read_E(10000, 1, 50) == 500
+
+
+def _brute_taxa(res, taxon, n_taxa, n):
+    co = res["cand_offsets"].astype(np.int64)
+    uni = np.zeros(n_taxa, np.uint64)
+    mul = np.zeros(n_taxa, np.uint64)
+    unm = 0
+    acc = np.zeros(n, np.uint8)
+    for r in range(n):
+        ap = [(int(res["approx"][c]), int(taxon[res["genome"][c]])) for c in range(co[r], co[r + 1])
+              if res["approx"][c] <= res["read_E"][r]]
+        if not ap:
+            unm += 1
+            continue
+        acc[r] = 1
+        best = min(a for a, _ in ap)
+        ts = {t for a, t in ap if a == best}
+        if len(ts) == 1:
+            uni[ts.pop()] += 1
+        else:
+            for t in ts:
+                mul[t] += 1
+    return acc, uni, mul, unm
+
+
+def test_taxa_brute_force_and_conservation():
+    rnd = random.Random(7000)
+    root = "".join(rnd.choice("ACGT") for _ in range(3000))
+    genomes = []
+    for _ in range(6):      # near-duplicate strains so reads map to several genomes
+        s = list(root)
+        for i in rnd.sample(range(len(s)), 30):
+            s[i] = rnd.choice("ACGT")
+        genomes.append("".join(s))
+    taxon = np.array([0, 0, 1, 2, 2, 3], np.uint32)
+    reads = []
+    for _ in range(300):
+        g = rnd.choice(genomes)
+        st = rnd.randint(0, len(g) - 100)
+        r = list(g[st:st + 100])
+        for i in rnd.sample(range(100), rnd.randint(0, 6)):
+            r[i] = rnd.choice("ACGT")
+        reads.append("".join(r))
+    reads += ["".join(rnd.choice("ACGT") for _ in range(100)) for _ in range(20)]
+    ix = oracle.Index(synth.SeqSet.from_list(genomes), 9, 5, taxon=taxon, n_taxa=4)
+    rs = synth.SeqSet.from_list(reads)
+    for top_n, e in ((3, 3), (0, 5), (1, 2)):
+        res = ix.classify(rs, min_hits=2, top_n=top_n, e_mode=0, e_value=e)
+        acc, uni, mul, unm = _brute_taxa(res, taxon, 4, len(reads))
+        assert np.array_equal(res["read_accepted"], acc)
+        assert np.array_equal(res["unique"], uni) and np.array_equal(res["multi"], mul)
+        assert res["unmapped"] == unm
+        n_multi_reads = int(acc.sum()) - int(uni.sum())
+        assert int(uni.sum()) + n_multi_reads + unm == len(reads)
+        assert int(mul.sum()) >= 2 * n_multi_reads
+        assert np.array_equal(res["accept"], (res["approx"] <= np.repeat(
+            res["read_E"], np.diff(res["cand_offsets"].astype(np.int64)))).astype(np.uint8))
+
+
+def test_read_permutation_invariance():
+    gen, reads, _ = synth.workload_small(400)
+    ix = oracle.Index(gen.ascii(), 15, 10)
+    base = ix.classify(reads, 3, 3, 0, 7)
+    perm = np.random.default_rng(9).permutation(reads.n)
+    sh = ix.classify(reads.subset(perm), 3, 3, 0, 7)
+    a = _oracle_cands(base, reads.n)
+    b = _oracle_cands(sh, reads.n)
+    assert [a[i] for i in perm] == b
+    assert np.array_equal(base["unique"], sh["unique"]) and base["unmapped"] == sh["unmapped"]
+
+
+def test_invalid_bytes_rejected():
+    with pytest.raises(ValueError):
+        oracle.Index(synth.SeqSet.from_list(["ACGTX"]), 3, 2)
+    ix = oracle.Index(synth.SeqSet.from_list(["ACGTACGTACGT"]), 3, 2)
+    with pytest.raises(ValueError):
+        ix.classify(synth.SeqSet.from_list(["ACG-T"]))
