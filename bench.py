@@ -1,0 +1,174 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the seed-count + approximate-edit-distance path.
+
+Workload: 200 synthetic genomes totalling 500 Mbp (per-genome GC ~ U(0.3, 0.7)),
+1M reads of 150 bp with 0.1-1% substitutions and 0.01-0.1% indels, k=21,
+w=11, >= 3 seed hits, top 3 locations, E = 7 (5% of 150).  One step is one
+classification of the whole read batch (seeding, lookup, hit counting, top-N,
+filter, per-taxon counts) with the reads and the index already in HBM.
+
+Prints one JSON line.  The CPU baseline is the plain C oracle timed on a
+bounded sample of the same reads (its index build is not timed).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "read×candidate pairs/s and reads/s at E=5%, bit-exact; p50/p99 latency served"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes per work unit of each stage (see the design notes):
+#   lookup: per minimizer  8 B k-mer in + 16 B table slot + 8 B value out + 4 B count out
+#   fused:  per read       its ASCII bases + 16 B slot per minimizer + 16 B reference
+#                          planes per 64 window bases + 19 B per candidate out + 11 B per read out
+LOOKUP_BYTES_PER_MIN = 8 + 16 + 8 + 4
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--mode", default="fused", choices=["fused", "per_stage"])
+    ap.add_argument("--E", type=int, default=7)
+    ap.add_argument("--reads", type=int, default=1_000_000)
+    ap.add_argument("--cpu-reads", type=int, default=200_000,
+                    help="reads in the oracle's timed sample (0 skips the CPU baseline)")
+    ap.add_argument("--no-timing", action="store_true", help="do not record per-stage HIP events")
+    ap.add_argument("--genomes", type=int, default=200, help="genomes of 2.5 Mbp in the database")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(reads are independent; see the design notes for how it would shard).", file=sys.stderr)
+        return 2
+
+    import torch
+    import paper_2311_02029_amd as mt
+    import synth
+
+    torch.cuda.set_device(0)
+    t = time.time()
+    db = synth.workload_batched_db(n_genomes=args.genomes)
+    reads = synth.workload_batched_reads(db, args.reads)
+    log(f"[bench] data generated in {time.time() - t:.1f}s: {db.n} genomes, {reads.n} reads")
+    ga = db.ascii()
+    dgen = mt.to_device(ga)
+    dreads = mt.to_device(reads)
+    del db
+    torch.cuda.synchronize()
+    log(f"[bench] inputs on the device")
+    mt.mt_set_timing(True)
+    t = time.time()
+    ix = mt.Index(dgen, 21, 11)
+    torch.cuda.synchronize()
+    index_s = time.time() - t
+    log(f"[bench] index stages (ms): {mt.last_timings()}")
+    mt.mt_set_timing(False)
+    info = ix.info()
+    log(f"[bench] index built in {index_s:.2f}s: {info['n_minimizers']} minimizers, {info['n_keys']} keys, "
+        f"{info['device_bytes'] / 2**30:.2f} GiB")
+    del dgen
+
+    mode = mt.MT_MODE_FUSED if args.mode == "fused" else mt.MT_MODE_PER_STAGE
+    q = dict(min_hits=3, top_n=3, e_mode=mt.MT_E_FIXED, e_value=args.E, mode=mode)
+
+    for i in range(args.warmup):
+        t = time.time()
+        r = ix.classify(dreads, **q)
+        n_cands = r.n_cands
+        r.free()
+        log(f"[bench] warmup step {i}: {time.time() - t:.3f}s")
+    log(f"[bench] warmup done ({args.warmup} steps), {n_cands} candidates per step")
+
+    mt.mt_set_timing(not args.no_timing)
+    stage_ms: dict[str, float] = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        r = ix.classify(dreads, **q)
+        n_cands = r.n_cands
+        r.free()
+        if not args.no_timing:
+            for name, ms in mt.last_timings():
+                stage_ms[name] = stage_ms.get(name, 0.0) + ms
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    mt.mt_set_timing(False)
+    ms_per_step = (t1 - t0) * 1000.0 / args.steps
+    pairs_s = n_cands / (ms_per_step / 1000.0)
+    reads_s = reads.n / (ms_per_step / 1000.0)
+    stages = {k: v / args.steps for k, v in stage_ms.items()}
+    log(f"[bench] {ms_per_step:.3f} ms/step, {pairs_s:.3e} pairs/s, {reads_s:.3e} reads/s")
+    log(f"[bench] stages (ms/step): {json.dumps({k: round(v, 4) for k, v in stages.items()})}")
+
+    # Roofline of the dominant kernel from the live HIP-event timings.
+    roofline = None
+    stats = mt.last_stats() if hasattr(mt, "last_stats") else {}
+    if stages:
+        dom = max(stages, key=stages.get)
+        dur_s = stages[dom] / 1000.0
+        if dom == "lookup" and stats.get("n_minimizers"):
+            alg = stats["n_minimizers"] * LOOKUP_BYTES_PER_MIN
+        elif dom == "fused" and stats.get("n_minimizers"):
+            alg = (stats["fused_bases"] + 16 * stats["fused_minimizers"] + 16 * stats["fused_window_blocks"]
+                   + 19 * stats["fused_cands"] + 11 * stats["fused_reads"])
+        else:
+            alg = None
+        if alg is not None and dur_s > 0:
+            ach = alg / dur_s / 1e9
+            roofline = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                        "avg_ms": round(stages[dom], 4), "algorithmic_bytes": int(alg)}
+        else:
+            roofline = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": None, "traffic": None, "avg_ms": round(stages[dom], 4)}
+
+    cpu = None
+    if args.cpu_reads > 0:
+        import oracle
+        t = time.time()
+        oix = oracle.Index(ga, 21, 11)
+        log(f"[bench] oracle index built in {time.time() - t:.1f}s (not timed)")
+        sample = reads.subset(np.arange(min(args.cpu_reads, reads.n)))
+        t = time.perf_counter()
+        out = oix.classify(sample, 3, 3, 0, args.E)
+        dt = time.perf_counter() - t
+        cpu = {"value": round(len(out["genome"]) / dt, 1), "unit": "pairs/s", "cores": 1, "kind": "oracle",
+               "reads_per_s": round(sample.n / dt, 1),
+               "sample": f"first {sample.n} reads of the batch, single-threaded C oracle, {dt:.1f}s"}
+        log(f"[bench] oracle: {cpu['value']:.3e} pairs/s on {sample.n} reads in {dt:.1f}s")
+
+    out = {
+        "metric": METRIC, "value": round(pairs_s, 1), "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": "500 Mbp / 200 genomes, 1M x 150 bp reads, k=21 w=11, min_hits=3, top_n=3, "
+                               f"E={args.E}", "reads": reads.n, "pairs_per_step": int(n_cands),
+                   "mode": args.mode, "parallelism": "single GPU"},
+        "reads_per_s": round(reads_s, 1),
+        "index_build_s": round(index_s, 3),
+        "stages_ms": {k: round(v, 4) for k, v in stages.items()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,219 @@
+/*
+ * metatrinity.h — C ABI of the MI355X (gfx950) seed-count + approximate edit
+ * distance read classifier (MetaTrinity, Gollwitzer et al., arXiv 2311.02029,
+ * stage 2 "Heuristic read mapping" and the read counts of stage 3a).
+ *
+ * The problem (Methods, problem statement): given reference sequences R and
+ * query reads Q over {A, C, G, T, N}, find the mapping locations of each Q.
+ * The library does it the paper's heuristic way (Fig. 1, steps 2a-2d; read
+ * mapping Evaluation Methodology; Empirically Determined Parameters):
+ *   2a  an HBM-resident minimizer seed index over the reference genomes,
+ *   2b  minimizer seeds of every read looked up in the index; every seed match
+ *       votes for a location (genome, diagonal),
+ *   2c  locations with fewer than min_hits votes are dropped, the rest sorted
+ *       by votes and cut to the top_n,
+ *   2d  each surviving (read, location) pair gets an approximate edit count
+ *       (the obstacle count of the pigeonhole filter family of Table 1) and is
+ *       accepted when the count is at most the read's threshold E,
+ *   3a  accepted reads are counted per taxon as unique or multi-mapped.
+ *
+ * Conventions for every entry point:
+ *   - Every call returns an mt_status; MT_OK is 0.  Nothing aborts and no
+ *     exception crosses the ABI.  mt_last_error() describes the last failure
+ *     on the calling thread.
+ *   - "device" arguments are pointers to GPU memory on the current HIP device
+ *     (hipMalloc, or a torch CUDA tensor's data_ptr()).  "host" arguments are
+ *     ordinary CPU memory.  All inputs are borrowed for the duration of the
+ *     call and never retained.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     device work of a call is enqueued on it, and the call synchronizes that
+ *     stream before it returns (device-side input validation is reported
+ *     through the return code), so on return every output is complete.
+ *   - Handles (mt_index, mt_result) are owned by the library and released
+ *     with their *_free call.  Device pointers returned by accessors stay valid
+ *     until their handle is freed.  Free a result only once no device work
+ *     that reads its arrays is pending on any stream.
+ *   - An mt_index is immutable after mt_index_build and may be used from
+ *     several host threads (each with its own stream) at once.
+ *   - Bases are ASCII A, C, G, T, N in either case; any other byte makes the
+ *     call fail with MT_EINVAL.  A k-mer containing N is never a seed, and an
+ *     N (in a read or the reference) never matches anything, not even an N.
+ *   - Limits: 1 <= k <= 31, 1 <= w <= 255; read length <= 65535; genome
+ *     length < 2^32 - 2^16; fewer than 2^31 genomes; E <= 65534; at most
+ *     2^23 - 1 occurrences of one k-mer in the index (use max_occ above that).
+ */
+#ifndef METATRINITY_H
+#define METATRINITY_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MT_ABI_VERSION 1
+
+typedef enum mt_status {
+    MT_OK = 0,
+    MT_EINVAL = -1,      /* bad argument or input byte; limits exceeded */
+    MT_ENOMEM = -2,      /* device or host allocation failed */
+    MT_EDEVICE = -3,     /* a HIP runtime call failed */
+    MT_EAGAIN = -4,      /* reserved: admission refused, try later */
+    MT_ETIMEDOUT = -5,   /* reserved: wait timed out */
+    MT_ECANCELED = -6,   /* reserved: request canceled */
+    MT_EINTERNAL = -7    /* library bug: an internal invariant failed */
+} mt_status;
+
+/* A set of sequences: concatenated ASCII plus CSR offsets. */
+typedef struct mt_seqs {
+    const char *seq;          /* device: all bases back to back */
+    const uint64_t *offsets;  /* device: n + 1 non-decreasing offsets, offsets[0] = 0 */
+    uint64_t n;               /* number of sequences */
+    uint64_t total;           /* host copy of offsets[n] (sizes device buffers) */
+} mt_seqs;
+
+typedef struct mt_index_params {
+    uint32_t k;        /* k-mer length of the seeds */
+    uint32_t w;        /* minimizer window: w consecutive k-mer starts */
+    uint32_t max_occ;  /* k-mers occurring more than this often are never seeds; 0 = no cap */
+    uint32_t reserved; /* must be 0 */
+} mt_index_params;
+
+/* How a read's edit threshold E follows from its length m. */
+enum {
+    MT_E_FIXED = 0,          /* E = e_value */
+    MT_E_CEIL_PERMILLE = 1,  /* E = ceil(m * e_value / 1000)  (e.g. 50 = 5%) */
+    MT_E_FLOOR_PERMILLE = 2  /* E = floor(m * e_value / 1000) */
+};
+
+/* Execution form; every form gives bit-identical results. */
+enum {
+    MT_MODE_PER_STAGE = 0,   /* one kernel launch per step of the path */
+    MT_MODE_FUSED = 1        /* one fused seed-count + filter kernel for short reads,
+                                per-stage kernels for the rest */
+};
+
+typedef struct mt_query_params {
+    uint32_t min_hits;   /* keep locations with at least this many seed hits (paper: 3) */
+    uint32_t top_n;      /* keep the top_n locations per read (paper: 3); 0 keeps all */
+    uint32_t e_mode;     /* MT_E_* */
+    uint32_t e_value;    /* E, or permille of the read length */
+    uint32_t mode;       /* MT_MODE_* */
+    uint32_t reserved[3];/* must be 0 */
+} mt_query_params;
+
+typedef struct mt_index_info {
+    uint64_t n_genomes;
+    uint64_t total_bases;
+    uint64_t n_minimizers;   /* reference minimizer occurrences (all genomes) */
+    uint64_t n_keys;         /* distinct k-mers among them */
+    uint64_t n_slots;        /* hash-table slots (16 bytes each) */
+    uint64_t n_multi_occ;    /* entries in the multi-occurrence array */
+    uint64_t device_bytes;   /* HBM held by the index */
+    uint32_t k, w, max_occ, n_taxa;
+} mt_index_info;
+
+typedef struct mt_index mt_index;
+typedef struct mt_result mt_result;
+
+/*
+ * Builds the seed index (Fig. 1 step 2a) over `genomes` on the device:
+ * 2-bit packed reference planes, the minimizers of every genome, and a
+ * bucketed hash table from k-mer to its occurrences (genome, position).
+ *   params          host; k, w, max_occ as above.
+ *   genomes         host struct with device seq/offsets.
+ *   taxon_of_genome host array of genomes->n entries, each < n_taxa; NULL
+ *                   maps genome i to taxon i (then n_taxa must be >= n).
+ *   out             receives the handle (owned; release with mt_index_free).
+ * Errors: MT_EINVAL (bad parameters, byte, or limit), MT_ENOMEM, MT_EDEVICE.
+ */
+int mt_index_build(const mt_index_params *params, const mt_seqs *genomes,
+                   const uint32_t *taxon_of_genome, uint32_t n_taxa,
+                   void *stream, mt_index **out);
+int mt_index_free(mt_index *index);
+int mt_index_get_info(const mt_index *index, mt_index_info *info);
+
+/*
+ * Classifies `reads` against the index (Fig. 1 steps 2b-2d and 3a).
+ *   params  host; min_hits, top_n, E rule and execution mode.
+ *   reads   host struct with device seq/offsets.
+ *   out     receives the result handle (owned; release with mt_result_free).
+ * Candidates of each read appear in the canonical order: seed hits
+ * descending, then genome ascending, then diagonal ascending.
+ * Errors: MT_EINVAL (bad parameter or byte, read > 65535 bases, E > 65534),
+ * MT_ENOMEM, MT_EDEVICE.
+ */
+int mt_classify(const mt_index *index, const mt_query_params *params,
+                const mt_seqs *reads, void *stream, mt_result **out);
+
+/* Per-read outputs (device arrays of n_reads entries, cand_offsets n_reads+1):
+ * cand_offsets  CSR into the candidate arrays;
+ * read_accepted 1 if at least one candidate of the read is accepted;
+ * read_E        the read's threshold E. */
+int mt_result_reads(const mt_result *res, uint64_t *n_reads, const uint64_t **cand_offsets,
+                    const uint8_t **read_accepted, const uint16_t **read_E);
+
+/* Per-candidate outputs (device arrays of n_cands entries):
+ * genome, diag (reference position of read base 0; may be negative),
+ * hits (seed hits on that diagonal), approx (obstacle count, saturated at
+ * E + 1), accept (approx <= E). */
+int mt_result_cands(const mt_result *res, uint64_t *n_cands, const uint32_t **genome,
+                    const int64_t **diag, const uint32_t **hits, const uint16_t **approx,
+                    const uint8_t **accept);
+
+/* Per-taxon read counts (device arrays of n_taxa entries, unmapped: one entry):
+ * a read's mapped taxa are the taxa of its accepted candidates with the
+ * smallest approx; one such taxon counts as unique, several as multi-mapped
+ * for each; a read with no accepted candidate is unmapped. */
+int mt_result_taxa(const mt_result *res, uint32_t *n_taxa, const uint64_t **unique_reads,
+                   const uint64_t **multi_reads, const uint64_t **unmapped);
+int mt_result_free(mt_result *res);
+
+/* Per-launch kernel timings of the last mt_classify on this thread (ms,
+ * measured with HIP events on the call's stream).  names/ms: host arrays of
+ * `cap` entries; *n receives the number of entries written. */
+int mt_last_timings(const char **names, float *ms, uint32_t cap, uint32_t *n);
+/* Enables (1) or disables (0, default) the event timing above. */
+int mt_set_timing(int enabled);
+
+/* Work counts of the last mt_classify on this thread. */
+typedef struct mt_stats {
+    uint64_t n_reads;
+    uint64_t n_minimizers;        /* read minimizers looked up */
+    uint64_t n_hits;              /* (minimizer, occurrence) seed matches */
+    uint64_t n_cands;             /* (read, location) pairs filtered */
+    uint64_t fused_reads;         /* reads the fused kernel finished */
+    uint64_t fused_bases;         /* their bases */
+    uint64_t fused_minimizers;    /* their minimizers */
+    uint64_t fused_window_blocks; /* 64-base reference blocks their filter read */
+    uint64_t fused_cands;         /* their candidates */
+} mt_stats;
+int mt_last_stats(mt_stats *out);
+
+/*
+ * The filter alone (Fig. 1 step 2d) over explicit (read, location) pairs.
+ *   reads        host struct with device seq/offsets.
+ *   pair_read    device, n_pairs read indices (< reads->n).
+ *   pair_genome  device, n_pairs genome indices (< number of genomes).
+ *   pair_diag    device, n_pairs diagonals (reference position of read base 0).
+ *   pair_E       device, n_pairs thresholds.
+ *   approx_out   device, n_pairs outputs: obstacle count saturated at E + 1.
+ *   accept_out   device, n_pairs outputs: approx <= E.
+ * Errors: MT_EINVAL (index out of range, bad byte, read > 65535, E > 65534).
+ */
+int mt_filter_pairs(const mt_index *index, const mt_seqs *reads, const uint32_t *pair_read,
+                    const uint32_t *pair_genome, const int64_t *pair_diag, const uint16_t *pair_E,
+                    uint64_t n_pairs, uint16_t *approx_out, uint8_t *accept_out, void *stream);
+
+/* Releases device memory cached by the library's allocator (not held by any handle). */
+int mt_trim(void);
+/* Description of the last error on the calling thread ("" if none). */
+const char *mt_last_error(void);
+int mt_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* METATRINITY_H */

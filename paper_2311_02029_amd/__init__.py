@@ -1,0 +1,222 @@
+"""MI355X (gfx950) seed-count + approximate-edit-distance read classifier.
+
+Python binding of the C ABI (include/metatrinity.h).  The functions here only
+marshal arguments: torch provides device memory and streams, and every step of
+the classifier runs in the HIP kernels of libmetatrinity.so.  There is no CPU
+fallback: without the built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import _abi
+from ._abi import (MT_E_CEIL_PERMILLE, MT_E_FIXED, MT_E_FLOOR_PERMILLE, MT_MODE_FUSED,  # noqa: F401
+                   MT_MODE_PER_STAGE, MT_OK)
+
+__all__ = ["MTError", "DeviceSeqs", "Index", "Result", "to_device", "mt_set_timing", "last_timings"]
+
+
+class MTError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"[{status}] {msg}")
+        self.status = status
+
+
+def _check(rc: int, lib) -> None:
+    if rc != MT_OK:
+        raise MTError(rc, lib.mt_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+@dataclass
+class DeviceSeqs:
+    """A sequence set in device memory: ASCII bytes + n+1 offsets (torch tensors)."""
+    seq: object       # torch.uint8 cuda tensor
+    offsets: object   # torch.int64 cuda tensor (bit-identical to uint64 offsets)
+    n: int
+    total: int
+
+    def abi(self) -> _abi.mt_seqs:
+        return _abi.mt_seqs(self.seq.data_ptr(), self.offsets.data_ptr(), self.n, self.total)
+
+
+def to_device(seqset, device="cuda") -> DeviceSeqs:
+    """Copies a host sequence set (.seq uint8 ASCII, .offsets n+1) to the GPU."""
+    torch = _torch()
+    seq = np.ascontiguousarray(seqset.seq, dtype=np.uint8)
+    offs = np.ascontiguousarray(seqset.offsets, dtype=np.uint64).view(np.int64)
+    ts = torch.from_numpy(seq if len(seq) else np.zeros(1, np.uint8)).to(device)
+    to = torch.from_numpy(offs).to(device)
+    return DeviceSeqs(ts, to, int(len(offs) - 1), int(offs[-1]) if len(offs) else 0)
+
+
+def _copy_to_host(ptr: int, n: int, dtype) -> np.ndarray:
+    """Device -> host copy of n elements at a device pointer (HIP runtime memcpy)."""
+    out = np.empty(n, dtype=dtype)
+    if n:
+        _check_hip(_hip().hipMemcpy(out.ctypes.data_as(C.c_void_p), C.c_void_p(ptr), C.c_size_t(out.nbytes), 2))
+    return out
+
+
+_hiprt = None
+
+
+def _hip():
+    global _hiprt
+    if _hiprt is None:
+        _hiprt = C.CDLL("libamdhip64.so")
+        _hiprt.hipMemcpy.restype = C.c_int
+        _hiprt.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+    return _hiprt
+
+
+def _check_hip(rc: int) -> None:
+    if rc != 0:
+        raise MTError(_abi.MT_EDEVICE, f"hipMemcpy failed with {rc}")
+
+
+def mt_set_timing(enabled: bool) -> None:
+    lib = _abi.load()
+    _check(lib.mt_set_timing(1 if enabled else 0), lib)
+
+
+def last_stats() -> dict:
+    """Work counts of the last classification on this thread."""
+    lib = _abi.load()
+    st = _abi.mt_stats()
+    _check(lib.mt_last_stats(C.byref(st)), lib)
+    return {f: getattr(st, f) for f, _ in st._fields_}
+
+
+def last_timings() -> list[tuple[str, float]]:
+    """(stage, ms) of the last classification on this thread (timing enabled)."""
+    lib = _abi.load()
+    cap = 64
+    names = (C.c_char_p * cap)()
+    ms = (C.c_float * cap)()
+    n = C.c_uint32()
+    _check(lib.mt_last_timings(names, ms, cap, C.byref(n)), lib)
+    return [(names[i].decode(), float(ms[i])) for i in range(n.value)]
+
+
+class Result:
+    """Owns an mt_result; arrays are device pointers until to_host()."""
+
+    def __init__(self, handle: int, lib):
+        self.h = handle
+        self.lib = lib
+
+    def _reads(self):
+        n = C.c_uint64()
+        co, ra, re = C.c_void_p(), C.c_void_p(), C.c_void_p()
+        _check(self.lib.mt_result_reads(self.h, C.byref(n), C.byref(co), C.byref(ra), C.byref(re)), self.lib)
+        return n.value, co.value, ra.value, re.value
+
+    def _cands(self):
+        n = C.c_uint64()
+        ps = [C.c_void_p() for _ in range(5)]
+        _check(self.lib.mt_result_cands(self.h, C.byref(n), *[C.byref(p) for p in ps]), self.lib)
+        return n.value, [p.value for p in ps]
+
+    def _taxa(self):
+        n = C.c_uint32()
+        ps = [C.c_void_p() for _ in range(3)]
+        _check(self.lib.mt_result_taxa(self.h, C.byref(n), *[C.byref(p) for p in ps]), self.lib)
+        return n.value, [p.value for p in ps]
+
+    @property
+    def n_cands(self) -> int:
+        return self._cands()[0]
+
+    def to_host(self) -> dict:
+        nr, co, ra, re = self._reads()
+        nc, (g, d, h, a, ac) = self._cands()
+        nt, (u, mu, un) = self._taxa()
+        return dict(
+            cand_offsets=_copy_to_host(co, nr + 1, np.uint64), read_accepted=_copy_to_host(ra, nr, np.uint8),
+            read_E=_copy_to_host(re, nr, np.uint16), genome=_copy_to_host(g, nc, np.uint32),
+            diag=_copy_to_host(d, nc, np.int64), hits=_copy_to_host(h, nc, np.uint32),
+            approx=_copy_to_host(a, nc, np.uint16), accept=_copy_to_host(ac, nc, np.uint8),
+            unique=_copy_to_host(u, nt, np.uint64), multi=_copy_to_host(mu, nt, np.uint64),
+            unmapped=int(_copy_to_host(un, 1, np.uint64)[0]))
+
+    def free(self) -> None:
+        if self.h:
+            self.lib.mt_result_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+class Index:
+    """Device-resident seed index (mt_index_build)."""
+
+    def __init__(self, genomes, k: int, w: int, max_occ: int = 0, taxon=None, n_taxa=None, stream=None):
+        self.lib = _abi.load()
+        dg = genomes if isinstance(genomes, DeviceSeqs) else to_device(genomes)
+        n = dg.n
+        if taxon is None:
+            taxon = np.arange(n, dtype=np.uint32)
+        self.taxon = np.ascontiguousarray(taxon, dtype=np.uint32)
+        n_taxa = int(n_taxa if n_taxa is not None else (int(self.taxon.max()) + 1 if n else 0))
+        p = _abi.mt_index_params(k, w, max_occ, 0)
+        h = C.c_void_p()
+        rc = self.lib.mt_index_build(C.byref(p), C.byref(dg.abi()), self.taxon.ctypes.data_as(C.c_void_p),
+                                     n_taxa, _stream_ptr(stream), C.byref(h))
+        _check(rc, self.lib)
+        self.h = h.value
+        self.n_taxa = n_taxa
+
+    def info(self) -> dict:
+        inf = _abi.mt_index_info()
+        _check(self.lib.mt_index_get_info(self.h, C.byref(inf)), self.lib)
+        return {f: getattr(inf, f) for f, _ in inf._fields_}
+
+    def classify(self, reads: DeviceSeqs, min_hits=3, top_n=3, e_mode=MT_E_FIXED, e_value=7,
+                 mode=MT_MODE_PER_STAGE, stream=None) -> Result:
+        q = _abi.mt_query_params(min_hits, top_n, e_mode, e_value, mode)
+        h = C.c_void_p()
+        rc = self.lib.mt_classify(self.h, C.byref(q), C.byref(reads.abi()), _stream_ptr(stream), C.byref(h))
+        _check(rc, self.lib)
+        return Result(h.value, self.lib)
+
+    def filter_pairs(self, reads: DeviceSeqs, pair_read, pair_genome, pair_diag, pair_E, stream=None):
+        """Device tensors in (uint32/int32 read and genome, int64 diag, int16/uint16 E); returns
+        device tensors (approx int16 holding uint16 bits, accept uint8)."""
+        torch = _torch()
+        n = int(pair_read.numel())
+        approx = torch.empty(max(n, 1), dtype=torch.int16, device=pair_read.device)
+        accept = torch.empty(max(n, 1), dtype=torch.uint8, device=pair_read.device)
+        rc = self.lib.mt_filter_pairs(self.h, C.byref(reads.abi()), pair_read.data_ptr(), pair_genome.data_ptr(),
+                                      pair_diag.data_ptr(), pair_E.data_ptr(), n, approx.data_ptr(),
+                                      accept.data_ptr(), _stream_ptr(stream))
+        _check(rc, self.lib)
+        return approx[:n], accept[:n]
+
+    def free(self) -> None:
+        if getattr(self, "h", None):
+            self.lib.mt_index_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass

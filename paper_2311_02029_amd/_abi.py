@@ -1,0 +1,87 @@
+"""ctypes declarations of the C ABI in include/metatrinity.h (same names).
+
+Argument marshalling only: every step of the classifier runs in the HIP
+library.  Loading fails loudly when libmetatrinity.so has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmetatrinity.so")
+
+MT_OK, MT_EINVAL, MT_ENOMEM, MT_EDEVICE, MT_EAGAIN, MT_ETIMEDOUT, MT_ECANCELED, MT_EINTERNAL = 0, -1, -2, -3, -4, -5, -6, -7
+MT_E_FIXED, MT_E_CEIL_PERMILLE, MT_E_FLOOR_PERMILLE = 0, 1, 2
+MT_MODE_PER_STAGE, MT_MODE_FUSED = 0, 1
+
+# Every function the header declares; a test checks the library exports them.
+ABI_FUNCTIONS = (
+    "mt_index_build", "mt_index_free", "mt_index_get_info", "mt_classify", "mt_result_reads",
+    "mt_result_cands", "mt_result_taxa", "mt_result_free", "mt_last_timings", "mt_set_timing",
+    "mt_filter_pairs", "mt_trim", "mt_last_error", "mt_abi_version", "mt_last_stats",
+)
+
+
+class mt_seqs(C.Structure):
+    _fields_ = [("seq", C.c_void_p), ("offsets", C.c_void_p), ("n", C.c_uint64), ("total", C.c_uint64)]
+
+
+class mt_index_params(C.Structure):
+    _fields_ = [("k", C.c_uint32), ("w", C.c_uint32), ("max_occ", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+class mt_query_params(C.Structure):
+    _fields_ = [("min_hits", C.c_uint32), ("top_n", C.c_uint32), ("e_mode", C.c_uint32), ("e_value", C.c_uint32),
+                ("mode", C.c_uint32), ("reserved", C.c_uint32 * 3)]
+
+
+class mt_index_info(C.Structure):
+    _fields_ = [("n_genomes", C.c_uint64), ("total_bases", C.c_uint64), ("n_minimizers", C.c_uint64),
+                ("n_keys", C.c_uint64), ("n_slots", C.c_uint64), ("n_multi_occ", C.c_uint64),
+                ("device_bytes", C.c_uint64), ("k", C.c_uint32), ("w", C.c_uint32), ("max_occ", C.c_uint32),
+                ("n_taxa", C.c_uint32)]
+
+
+class mt_stats(C.Structure):
+    _fields_ = [(f, C.c_uint64) for f in ("n_reads", "n_minimizers", "n_hits", "n_cands", "fused_reads",
+                                          "fused_bases", "fused_minimizers", "fused_window_blocks", "fused_cands")]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Loads the HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None and path == LIB_PATH:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build() "
+                           "(the classifier has no CPU fallback)")
+    lib = C.CDLL(path)
+    vp, u64, u32, i32 = C.c_void_p, C.c_uint64, C.c_uint32, C.c_int
+    pp = C.POINTER(C.c_void_p)
+    sig = {
+        "mt_index_build": (i32, [C.POINTER(mt_index_params), C.POINTER(mt_seqs), vp, u32, vp, pp]),
+        "mt_index_free": (i32, [vp]),
+        "mt_index_get_info": (i32, [vp, C.POINTER(mt_index_info)]),
+        "mt_classify": (i32, [vp, C.POINTER(mt_query_params), C.POINTER(mt_seqs), vp, pp]),
+        "mt_result_reads": (i32, [vp, C.POINTER(u64), pp, pp, pp]),
+        "mt_result_cands": (i32, [vp, C.POINTER(u64), pp, pp, pp, pp, pp]),
+        "mt_result_taxa": (i32, [vp, C.POINTER(u32), pp, pp, pp]),
+        "mt_result_free": (i32, [vp]),
+        "mt_last_timings": (i32, [C.POINTER(C.c_char_p), C.POINTER(C.c_float), u32, C.POINTER(u32)]),
+        "mt_set_timing": (i32, [i32]),
+        "mt_filter_pairs": (i32, [vp, C.POINTER(mt_seqs), vp, vp, vp, vp, u64, vp, vp, vp]),
+        "mt_trim": (i32, []),
+        "mt_last_error": (C.c_char_p, []),
+        "mt_abi_version": (i32, []),
+        "mt_last_stats": (i32, [C.POINTER(mt_stats)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    if path == LIB_PATH:
+        _lib = lib
+    return lib

@@ -1,0 +1,702 @@
+// Read classification, one kernel launch per step of the path (Fig. 1 steps
+// 2b-2d, 3a):
+//   setup     read lengths and thresholds E
+//   pack      ASCII -> bit planes
+//   seed      minimizers of every read (count pass, then emit)
+//   lookup    one hash-table probe per minimizer -> occurrence count
+//   gather    every (minimizer, occurrence) pair -> location key (genome, diag)
+//   count     per read: sort keys, count hits per location, keep >= min_hits,
+//             order by (hits desc, genome, diag), keep top_n
+//   compact   CSR of candidates
+//   filter    obstacle count per (read, location) pair, accept if <= E
+//   reduce    read accepted flag, per-taxon unique / multi / unmapped counts
+#include <algorithm>
+#include <cstring>
+
+#include "classify.hpp"
+
+namespace mt {
+
+// ------------------------------------------------------------------ setup --
+
+__global__ void k_read_setup(const u64 *__restrict__ off, u64 n, u32 e_mode, u32 e_value, u16 *__restrict__ read_E,
+                             u32 *__restrict__ flags, u32 *__restrict__ max_E) {
+    u64 r = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    u64 m = off[r + 1] - off[r];
+    u64 E = e_mode == MT_E_FIXED ? e_value
+            : e_mode == MT_E_CEIL_PERMILLE ? (m * e_value + 999) / 1000
+                                           : (m * e_value) / 1000;
+    u32 f = 0;
+    if (m > 65535) f |= ERR_READ_TOO_LONG;
+    if (E > 65534) f |= ERR_E_TOO_LARGE;
+    if (f) atomicOr(flags, f);
+    u32 e = E > 65535 ? 65535u : (u32)E;
+    read_E[r] = (u16)e;
+    atomicMax(max_E, e);
+}
+
+// ----------------------------------------------------------------- lookup --
+
+__global__ void k_lookup(const u64 *__restrict__ min_x, u64 n_min, const u64x2 *__restrict__ table, u64 nbuckets,
+                         u64 *__restrict__ min_val, u32 *__restrict__ min_nocc) {
+    u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_min) return;
+    u64 x = min_x[i];
+    u64 v = table_lookup(table, nbuckets, x);
+    min_val[i] = v;
+    min_nocc[i] = v == SLOT_NONE ? 0u : slot_count(v);
+}
+
+__global__ void k_gather(const u32 *__restrict__ min_pos, const u64 *__restrict__ min_val,
+                         const u64 *__restrict__ hit_off, u64 n_min, const u64 *__restrict__ occ,
+                         u64 *__restrict__ hit_key) {
+    u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_min) return;
+    u64 v = min_val[i];
+    u64 o = hit_off[i], e = hit_off[i + 1];
+    if (o == e) return;
+    i64 p = (i64)min_pos[i];
+    if (!(v & SLOT_MULTI)) {
+        hit_key[o] = cand_key((u32)(v >> 32), (i64)(u32)v - p);
+        return;
+    }
+    u64 st = slot_start(v);
+    for (u64 t = 0; o + t < e; t++) {
+        u64 gp = occ[st + t];
+        hit_key[o + t] = cand_key((u32)(gp >> 32), (i64)(u32)gp - p);
+    }
+}
+
+// First hit of every read (n + 1 entries): through the read's first tile and
+// that tile's first minimizer.
+__global__ void k_read_hits(const u64 *__restrict__ tile_off, const u64 *__restrict__ min_off,
+                            const u64 *__restrict__ hit_off, u64 n, u64 *__restrict__ read_hs) {
+    u64 r = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r > n) return;
+    read_hs[r] = hit_off[min_off[tile_off[r]]];
+}
+
+// ------------------------------------------------------------------ count --
+
+// Pair index t of a bitonic sub-step -> the two positions compared (i < l).
+// Every comparison puts the smaller element first ("all ascending" form),
+// so positions past the segment act as +infinity and are never touched.
+__device__ inline void bitonic_pair(u64 t, u64 k, u64 j, bool mirror, u64 &i, u64 &l) {
+    if (mirror) {
+        u64 half = k >> 1, blk = t / half, off = t % half;
+        i = blk * k + off;
+        l = blk * k + k - 1 - off;
+    } else {
+        i = (t / j) * 2 * j + (t % j);
+        l = i + j;
+    }
+}
+
+__device__ inline bool cand_before(u32 ha, u64 ka, u32 hb, u64 kb) { return ha > hb || (ha == hb && ka < kb); }
+
+constexpr int COUNT_TPB = 256;
+constexpr int COUNT_CAP = 2048;
+
+// One block per read whose hits fit in LDS; larger reads are queued for
+// k_count_large.
+__global__ __launch_bounds__(COUNT_TPB) void k_count_small(const u64 *__restrict__ hit_key,
+                                                           const u64 *__restrict__ read_hs, u64 n, u32 min_hits,
+                                                           u32 top_n, u64 *__restrict__ stage_key,
+                                                           u32 *__restrict__ stage_hits, u32 *__restrict__ ncand,
+                                                           u32 *__restrict__ large_list, u32 *__restrict__ n_large) {
+    __shared__ u64 key[COUNT_CAP];
+    __shared__ u64 ck[COUNT_CAP];
+    __shared__ u32 ch[COUNT_CAP];
+    __shared__ u32 nc;
+    u64 r = blockIdx.x;
+    if (r >= n) return;
+    u64 hs = read_hs[r], he = read_hs[r + 1];
+    u64 H = he - hs;
+    if (H == 0) {
+        if (threadIdx.x == 0) ncand[r] = 0;
+        return;
+    }
+    if (H > COUNT_CAP) {
+        if (threadIdx.x == 0) large_list[atomicAdd(n_large, 1u)] = (u32)r;
+        return;
+    }
+    for (u64 i = threadIdx.x; i < H; i += COUNT_TPB) key[i] = hit_key[hs + i];
+    if (threadIdx.x == 0) nc = 0;
+    u64 P = 1;
+    while (P < H) P <<= 1;
+    __syncthreads();
+    for (u64 k = 2; k <= P; k <<= 1) {
+        for (u64 j = k >> 1; j > 0; j >>= 1) {
+            bool mirror = j == (k >> 1);
+            for (u64 t = threadIdx.x; t < P / 2; t += COUNT_TPB) {
+                u64 i, l;
+                bitonic_pair(t, k, j, mirror, i, l);
+                if (l < H && key[i] > key[l]) {
+                    u64 tmp = key[i];
+                    key[i] = key[l];
+                    key[l] = tmp;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    u32 T = min_hits ? min_hits : 1;
+    for (u64 i = threadIdx.x; i < H; i += COUNT_TPB) {
+        if (i > 0 && key[i] == key[i - 1]) continue;
+        u64 j = i + 1;
+        while (j < H && key[j] == key[i]) j++;
+        u32 c = (u32)(j - i);
+        if (c >= T) {
+            u32 s = atomicAdd(&nc, 1u);
+            ck[s] = key[i];
+            ch[s] = c;
+        }
+    }
+    __syncthreads();
+    u32 C = nc;
+    for (u32 a = threadIdx.x; a < C; a += COUNT_TPB) {
+        u32 rank = 0;
+        for (u32 b = 0; b < C; b++) rank += cand_before(ch[b], ck[b], ch[a], ck[a]);
+        if (top_n == 0 || rank < top_n) {
+            stage_key[hs + rank] = ck[a];
+            stage_hits[hs + rank] = ch[a];
+        }
+    }
+    if (threadIdx.x == 0) ncand[r] = top_n && C > top_n ? top_n : C;
+}
+
+// Reads with more hits than fit in LDS: sort in global memory, one block per
+// read (rare: long reads against repetitive references).
+__global__ __launch_bounds__(COUNT_TPB) void k_count_large(u64 *__restrict__ hit_key, const u64 *__restrict__ read_hs,
+                                                           u32 min_hits, u32 top_n, u64 *__restrict__ stage_key,
+                                                           u32 *__restrict__ stage_hits, u32 *__restrict__ ncand,
+                                                           const u32 *__restrict__ large_list,
+                                                           const u32 *__restrict__ n_large) {
+    u32 nl = *n_large;
+    for (u32 li = blockIdx.x; li < nl; li += gridDim.x) {
+        u64 r = large_list[li];
+        u64 hs = read_hs[r], H = read_hs[r + 1] - hs;
+        u64 *key = hit_key + hs;
+        u64 P = 1;
+        while (P < H) P <<= 1;
+        for (u64 k = 2; k <= P; k <<= 1)
+            for (u64 j = k >> 1; j > 0; j >>= 1) {
+                bool mirror = j == (k >> 1);
+                for (u64 t = threadIdx.x; t < P / 2; t += COUNT_TPB) {
+                    u64 i, l;
+                    bitonic_pair(t, k, j, mirror, i, l);
+                    if (l < H && key[i] > key[l]) {
+                        u64 tmp = key[i];
+                        key[i] = key[l];
+                        key[l] = tmp;
+                    }
+                }
+                __syncthreads();
+            }
+        u32 T = min_hits ? min_hits : 1;
+        u64 C = 0;
+        for (u64 c0 = 0; c0 < H; c0 += COUNT_TPB) {
+            u64 i = c0 + threadIdx.x;
+            u32 is_c = 0, c = 0;
+            if (i < H && (i == 0 || key[i] != key[i - 1])) {
+                u64 j = i + 1;
+                while (j < H && key[j] == key[i]) j++;
+                c = (u32)(j - i);
+                is_c = c >= T;
+            }
+            u32 tot;
+            u32 pre = block_exclusive_sum<COUNT_TPB, u32>(is_c, &tot);
+            if (is_c) {
+                stage_key[hs + C + pre] = key[i];
+                stage_hits[hs + C + pre] = c;
+            }
+            C += tot;
+        }
+        __syncthreads();
+        u64 *sk = stage_key + hs;
+        u32 *sh = stage_hits + hs;
+        P = 1;
+        while (P < C) P <<= 1;
+        for (u64 k = 2; k <= P; k <<= 1)
+            for (u64 j = k >> 1; j > 0; j >>= 1) {
+                bool mirror = j == (k >> 1);
+                for (u64 t = threadIdx.x; t < P / 2; t += COUNT_TPB) {
+                    u64 i, l;
+                    bitonic_pair(t, k, j, mirror, i, l);
+                    if (l < C && cand_before(sh[l], sk[l], sh[i], sk[i])) {
+                        u64 tk = sk[i];
+                        sk[i] = sk[l];
+                        sk[l] = tk;
+                        u32 th = sh[i];
+                        sh[i] = sh[l];
+                        sh[l] = th;
+                    }
+                }
+                __syncthreads();
+            }
+        if (threadIdx.x == 0) ncand[r] = (u32)(top_n && C > top_n ? top_n : C);
+        __syncthreads();
+    }
+}
+
+__global__ void k_compact(const u64 *__restrict__ read_hs, const u32 *__restrict__ ncand,
+                          const u64 *__restrict__ cand_off, u64 n, const u64 *__restrict__ stage_key,
+                          const u32 *__restrict__ stage_hits, u32 *__restrict__ genome, i64 *__restrict__ diag,
+                          u32 *__restrict__ hits, u32 *__restrict__ pair_read) {
+    u64 r = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    u64 hs = read_hs[r], o = cand_off[r];
+    for (u32 i = 0; i < ncand[r]; i++) {
+        u64 key = stage_key[hs + i];
+        genome[o + i] = key_genome(key);
+        diag[o + i] = key_diag(key);
+        hits[o + i] = stage_hits[hs + i];
+        pair_read[o + i] = (u32)r;
+    }
+}
+
+// ----------------------------------------------------------------- filter --
+
+struct FilterArgs {
+    const u32 *pair_read;
+    const u32 *pair_genome;
+    const i64 *pair_diag;
+    const u16 *pair_E;   // per-pair E, or null to use read_E
+    const u16 *read_E;
+    const u64 *n_dev;    // pair count on the device, or null to use n_host
+    u64 n_host;
+    u64 n_reads;
+    const u64 *read_off;  // ASCII offsets (lengths)
+    const u64 *read_blk;
+    const u64x2 *read_lohi;
+    const u64 *read_nb;
+    u64 n_genomes;
+    const u64 *ref_blk;
+    const u64x2 *ref_lohi;
+    const u64 *ref_nb;
+    const u64 *glen;
+    const u32 *has_n;
+    u16 *approx;
+    u8 *accept;
+    u32 *flags;
+};
+
+// G lanes per pair, 256 / G pairs per block of 256 threads.
+template <int G>
+__global__ __launch_bounds__(256) void k_filter(FilterArgs a) {
+    u64 tid = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    u64 p = tid / G;
+    int lane = (int)(tid % G);
+    u64 np = a.n_dev ? *a.n_dev : a.n_host;
+    if (p >= np) return;
+    u32 r = a.pair_read[p], g = a.pair_genome[p];
+    if (r >= a.n_reads || g >= a.n_genomes) {
+        if (lane == 0) {
+            atomicOr(a.flags, ERR_PAIR_RANGE);
+            a.approx[p] = 0xFFFF;
+            a.accept[p] = 0;
+        }
+        return;
+    }
+    int E = a.pair_E ? a.pair_E[p] : a.read_E[r];
+    if (E > 65534) {
+        if (lane == 0) {
+            atomicOr(a.flags, ERR_E_TOO_LARGE);
+            a.approx[p] = 0xFFFF;
+            a.accept[p] = 0;
+        }
+        return;
+    }
+    PairView v;
+    v.qlohi = a.read_lohi + a.read_blk[r];
+    v.qnb = a.read_nb + a.read_blk[r];
+    v.m = (int)(a.read_off[r + 1] - a.read_off[r]);
+    v.rlohi = a.ref_lohi + a.ref_blk[g];
+    v.rnb = a.ref_nb + a.ref_blk[g];
+    v.L = (i64)a.glen[g];
+    v.has_n = a.has_n[g] != 0;
+    v.diag = a.pair_diag[p];
+    int approx = obstacle_walk<G>(v, E, lane);
+    if (lane == 0) {
+        a.approx[p] = (u16)approx;
+        a.accept[p] = approx <= E;
+    }
+}
+
+static void launch_filter(const FilterArgs &a, u64 n_cap, u32 max_E, hipStream_t s) {
+    if (n_cap == 0) return;
+    u32 rows = 2 * max_E + 1;
+    if (rows <= 16)
+        k_filter<16><<<grid_for(n_cap * 16, 256), 256, 0, s>>>(a);
+    else if (rows <= 32)
+        k_filter<32><<<grid_for(n_cap * 32, 256), 256, 0, s>>>(a);
+    else
+        k_filter<64><<<grid_for(n_cap * 64, 256), 256, 0, s>>>(a);
+    MT_HIP(hipGetLastError());
+}
+
+// ----------------------------------------------------------------- reduce --
+
+__global__ void k_reduce(const u64 *__restrict__ cand_off, u64 n, const u32 *__restrict__ genome,
+                         const u16 *__restrict__ approx, const u16 *__restrict__ read_E,
+                         const u32 *__restrict__ taxon, u8 *__restrict__ read_accepted,
+                         unsigned long long *__restrict__ uniq, unsigned long long *__restrict__ multi,
+                         unsigned long long *__restrict__ unmapped) {
+    u64 r = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    u64 cs = cand_off[r], ce = cand_off[r + 1];
+    u32 E = read_E[r];
+    u32 best = 0xFFFFFFFFu;
+    for (u64 c = cs; c < ce; c++)
+        if (approx[c] <= E && approx[c] < best) best = approx[c];
+    if (best == 0xFFFFFFFFu) {
+        read_accepted[r] = 0;
+        atomicAdd(unmapped, 1ull);
+        return;
+    }
+    read_accepted[r] = 1;
+    // Distinct taxa of the accepted candidates at the best count.
+    u32 ntax = 0, first = 0;
+    for (u64 c = cs; c < ce; c++) {
+        if (approx[c] != best) continue;
+        u32 t = taxon[genome[c]];
+        bool seen = false;
+        for (u64 d = cs; d < c; d++)
+            if (approx[d] == best && taxon[genome[d]] == t) seen = true;
+        if (seen) continue;
+        if (ntax == 0) first = t;
+        ntax++;
+    }
+    if (ntax == 1) {
+        atomicAdd(&uniq[first], 1ull);
+        return;
+    }
+    for (u64 c = cs; c < ce; c++) {
+        if (approx[c] != best) continue;
+        u32 t = taxon[genome[c]];
+        bool seen = false;
+        for (u64 d = cs; d < c; d++)
+            if (approx[d] == best && taxon[genome[d]] == t) seen = true;
+        if (!seen) atomicAdd(&multi[t], 1ull);
+    }
+}
+
+// ----------------------------------------------------------------- driver --
+
+void ReadBatch::prepare(const mt_seqs &reads, u32 e_mode, u32 e_value, hipStream_t s) {
+    n = reads.n;
+    flags.alloc(1);
+    maxE.alloc(1);
+    MT_HIP(hipMemsetAsync(flags.p, 0, sizeof(u32), s));
+    MT_HIP(hipMemsetAsync(maxE.p, 0, sizeof(u32), s));
+    read_E.alloc(n);
+    if (n) {
+        k_read_setup<<<grid_for(n, 256), 256, 0, s>>>(reads.offsets, n, e_mode, e_value, read_E.p, flags.p,
+                                                      maxE.p);
+        MT_HIP(hipGetLastError());
+    }
+    pack_sequences(reads, 65535, ERR_READ_TOO_LONG, "read longer than 65535 bases", planes, flags.p, nullptr, s);
+}
+
+void validate_query(const mt_query_params &q) {
+    MT_REQUIRE(q.e_mode <= MT_E_FLOOR_PERMILLE, "unknown e_mode");
+    MT_REQUIRE(q.e_mode != MT_E_FIXED || q.e_value <= 65534, "E must be at most 65534");
+    MT_REQUIRE(q.mode <= MT_MODE_FUSED, "unknown mode");
+    MT_REQUIRE(q.reserved[0] == 0 && q.reserved[1] == 0 && q.reserved[2] == 0, "reserved fields must be 0");
+}
+
+void classify_per_stage(const mt_index &ix, const mt_query_params &q, const mt_seqs &reads, ReadBatch &rb,
+                        mt_result &res, Timer &tm, hipStream_t s) {
+    u64 n = reads.n;
+    // seeds
+    MinimizerPlan mp;
+    minimizer_plan(reads, rb.planes, ix.k, ix.w, 256, mp, s);
+    tm.mark("seed_count");
+    u32 hf[2];
+    u64 n_min = 0;
+    MT_HIP(hipMemcpyAsync(&hf[0], rb.flags.p, sizeof(u32), hipMemcpyDeviceToHost, s));
+    MT_HIP(hipMemcpyAsync(&hf[1], rb.maxE.p, sizeof(u32), hipMemcpyDeviceToHost, s));
+    read_back(s, mp.min_off.p + mp.tiles_cap, &n_min, sizeof(u64));
+    check_flags(hf[0]);
+    u32 max_E = hf[1];
+    DBuf<u64> min_x(n_min), min_val(n_min);
+    DBuf<u32> min_seq(n_min), min_pos(n_min), min_nocc(n_min);
+    minimizer_emit(reads, rb.planes, ix.k, ix.w, mp, min_x.p, min_seq.p, min_pos.p, s);
+    tm.mark("seed_emit");
+    // lookup + gather
+    if (n_min) {
+        k_lookup<<<grid_for(n_min, 256), 256, 0, s>>>(min_x.p, n_min, ix.table.p, ix.nbuckets, min_val.p,
+                                                      min_nocc.p);
+        MT_HIP(hipGetLastError());
+    }
+    tm.mark("lookup");
+    DBuf<u64> hit_off(n_min + 1);
+    scan_u32(min_nocc.p, hit_off.p, n_min, s);
+    u64 H = 0;
+    read_back(s, hit_off.p + n_min, &H, sizeof(u64));
+    DBuf<u64> hit_key(H), read_hs(n + 1);
+    if (n_min) {
+        k_gather<<<grid_for(n_min, 256), 256, 0, s>>>(min_pos.p, min_val.p, hit_off.p, n_min, ix.occ.p, hit_key.p);
+        MT_HIP(hipGetLastError());
+    }
+    k_read_hits<<<grid_for(n + 1, 256), 256, 0, s>>>(mp.tile_off.p, mp.min_off.p, hit_off.p, n, read_hs.p);
+    MT_HIP(hipGetLastError());
+    tm.mark("gather");
+    // count + select
+    DBuf<u64> stage_key(H);
+    DBuf<u32> stage_hits(H), ncand(n), large_list(n), n_large(1);
+    MT_HIP(hipMemsetAsync(n_large.p, 0, sizeof(u32), s));
+    last_stats().n_minimizers += n_min;
+    last_stats().n_hits += H;
+    if (n) {
+        k_count_small<<<grid_for(n, 1), COUNT_TPB, 0, s>>>(hit_key.p, read_hs.p, n, q.min_hits, q.top_n,
+                                                           stage_key.p, stage_hits.p, ncand.p, large_list.p,
+                                                           n_large.p);
+        MT_HIP(hipGetLastError());
+        k_count_large<<<256, COUNT_TPB, 0, s>>>(hit_key.p, read_hs.p, q.min_hits, q.top_n, stage_key.p,
+                                                stage_hits.p, ncand.p, large_list.p, n_large.p);
+        MT_HIP(hipGetLastError());
+    }
+    tm.mark("count_select");
+    // candidates
+    u64 cap = q.top_n ? std::min<u64>(H, n * (u64)q.top_n) : H;
+    res.alloc_cands(cap);
+    scan_u32(ncand.p, res.cand_off.p, n, s);
+    DBuf<u32> pair_read(cap);
+    if (n) {
+        k_compact<<<grid_for(n, 256), 256, 0, s>>>(read_hs.p, ncand.p, res.cand_off.p, n, stage_key.p,
+                                                   stage_hits.p, res.genome.p, res.diag.p, res.hits.p, pair_read.p);
+        MT_HIP(hipGetLastError());
+    }
+    tm.mark("compact");
+    // filter
+    FilterArgs fa{};
+    fa.pair_read = pair_read.p;
+    fa.pair_genome = res.genome.p;
+    fa.pair_diag = res.diag.p;
+    fa.pair_E = nullptr;
+    fa.read_E = rb.read_E.p;
+    fa.n_dev = res.cand_off.p + n;
+    fa.n_host = cap;
+    fa.n_reads = n;
+    fa.read_off = reads.offsets;
+    fa.read_blk = rb.planes.blk_off.p;
+    fa.read_lohi = rb.planes.lohi.p;
+    fa.read_nb = rb.planes.nb.p;
+    fa.n_genomes = ix.n_genomes;
+    fa.ref_blk = ix.ref.blk_off.p;
+    fa.ref_lohi = ix.ref.lohi.p;
+    fa.ref_nb = ix.ref.nb.p;
+    fa.glen = ix.glen.p;
+    fa.has_n = ix.has_n.p;
+    fa.approx = res.approx.p;
+    fa.accept = res.accept.p;
+    fa.flags = rb.flags.p;
+    launch_filter(fa, cap, max_E, s);
+    tm.mark("filter");
+    // reduce
+    if (n) {
+        k_reduce<<<grid_for(n, 256), 256, 0, s>>>(res.cand_off.p, n, res.genome.p, res.approx.p, rb.read_E.p,
+                                                  ix.taxon.p, res.read_accepted.p,
+                                                  (unsigned long long *)res.uniq.p,
+                                                  (unsigned long long *)res.multi.p,
+                                                  (unsigned long long *)res.unmapped.p);
+        MT_HIP(hipGetLastError());
+    }
+    tm.mark("reduce");
+}
+
+void mt_result_init(mt_result &res, u64 n, u32 n_taxa, hipStream_t s) {
+    res.n_reads = n;
+    res.n_taxa = n_taxa;
+    res.cand_off.alloc(n + 1);
+    res.read_accepted.alloc(n);
+    res.read_E.alloc(n);
+    res.uniq.alloc(n_taxa);
+    res.multi.alloc(n_taxa);
+    res.unmapped.alloc(1);
+    MT_HIP(hipMemsetAsync(res.uniq.p, 0, (n_taxa ? n_taxa : 1) * sizeof(u64), s));
+    MT_HIP(hipMemsetAsync(res.multi.p, 0, (n_taxa ? n_taxa : 1) * sizeof(u64), s));
+    MT_HIP(hipMemsetAsync(res.unmapped.p, 0, sizeof(u64), s));
+    if (n == 0) MT_HIP(hipMemsetAsync(res.cand_off.p, 0, sizeof(u64), s));
+}
+
+}  // namespace mt
+
+void mt_result::alloc_cands(mt::u64 c) {
+    cap = c;
+    genome.alloc(c);
+    diag.alloc(c);
+    hits.alloc(c);
+    approx.alloc(c);
+    accept.alloc(c);
+}
+
+// ---------------------------------------------------------------------- ABI --
+
+using mt::Error;
+
+template <class F>
+static int guarded(const char *what, F &&f) {
+    try {
+        f();
+        mt::set_last_error("");
+        return MT_OK;
+    } catch (const Error &e) {
+        mt::set_last_error(std::string(what) + ": " + e.what());
+        return e.status;
+    } catch (const std::bad_alloc &) {
+        mt::set_last_error(std::string(what) + ": host allocation failed");
+        return MT_ENOMEM;
+    } catch (const std::exception &e) {
+        mt::set_last_error(std::string(what) + ": " + e.what());
+        return MT_EINTERNAL;
+    }
+}
+
+extern "C" int mt_classify(const mt_index *index, const mt_query_params *params, const mt_seqs *reads,
+                           void *stream, mt_result **out) {
+    if (!index || !params || !reads || !out) {
+        mt::set_last_error("mt_classify: null argument");
+        return MT_EINVAL;
+    }
+    *out = nullptr;
+    mt_result *res = new (std::nothrow) mt_result();
+    if (!res) return MT_ENOMEM;
+    hipStream_t s = (hipStream_t)stream;
+    int rc = guarded("mt_classify", [&] {
+        mt::validate_query(*params);
+        MT_REQUIRE(reads->n == 0 || (reads->seq && reads->offsets), "null read arrays");
+        mt::Timer tm;
+        mt::last_stats() = mt_stats{};
+        mt::last_stats().n_reads = reads->n;
+        {
+            mt::CallScope scope(s);
+            tm.begin(s);
+            mt::mt_result_init(*res, reads->n, index->n_taxa, s);
+            mt::ReadBatch rb;
+            rb.prepare(*reads, params->e_mode, params->e_value, s);
+            MT_HIP(hipMemcpyAsync(res->read_E.p, rb.read_E.p, (reads->n ? reads->n : 1) * sizeof(mt::u16),
+                                  hipMemcpyDeviceToDevice, s));
+            tm.mark("pack");
+            if (params->mode == MT_MODE_FUSED)
+                mt::classify_fused(*index, *params, *reads, rb, *res, tm, s);
+            else
+                mt::classify_per_stage(*index, *params, *reads, rb, *res, tm, s);
+            mt::u32 f = 0;
+            mt::read_back(s, rb.flags.p, &f, sizeof f);
+            mt::check_flags(f);
+            mt::read_back(s, res->cand_off.p + reads->n, &res->n_cands, sizeof(mt::u64));
+            mt::last_stats().n_cands = res->n_cands;
+        }
+        tm.finish();
+    });
+    if (rc != MT_OK) {
+        delete res;
+        return rc;
+    }
+    *out = res;
+    return MT_OK;
+}
+
+extern "C" int mt_result_reads(const mt_result *res, uint64_t *n_reads, const uint64_t **cand_offsets,
+                               const uint8_t **read_accepted, const uint16_t **read_E) {
+    if (!res) {
+        mt::set_last_error("mt_result_reads: null result");
+        return MT_EINVAL;
+    }
+    if (n_reads) *n_reads = res->n_reads;
+    if (cand_offsets) *cand_offsets = res->cand_off.p;
+    if (read_accepted) *read_accepted = res->read_accepted.p;
+    if (read_E) *read_E = res->read_E.p;
+    return MT_OK;
+}
+
+extern "C" int mt_result_cands(const mt_result *res, uint64_t *n_cands, const uint32_t **genome,
+                               const int64_t **diag, const uint32_t **hits, const uint16_t **approx,
+                               const uint8_t **accept) {
+    if (!res) {
+        mt::set_last_error("mt_result_cands: null result");
+        return MT_EINVAL;
+    }
+    if (n_cands) *n_cands = res->n_cands;
+    if (genome) *genome = res->genome.p;
+    if (diag) *diag = res->diag.p;
+    if (hits) *hits = res->hits.p;
+    if (approx) *approx = res->approx.p;
+    if (accept) *accept = res->accept.p;
+    return MT_OK;
+}
+
+extern "C" int mt_result_taxa(const mt_result *res, uint32_t *n_taxa, const uint64_t **unique_reads,
+                              const uint64_t **multi_reads, const uint64_t **unmapped) {
+    if (!res) {
+        mt::set_last_error("mt_result_taxa: null result");
+        return MT_EINVAL;
+    }
+    if (n_taxa) *n_taxa = res->n_taxa;
+    if (unique_reads) *unique_reads = res->uniq.p;
+    if (multi_reads) *multi_reads = res->multi.p;
+    if (unmapped) *unmapped = res->unmapped.p;
+    return MT_OK;
+}
+
+extern "C" int mt_result_free(mt_result *res) {
+    delete res;
+    return MT_OK;
+}
+
+extern "C" int mt_filter_pairs(const mt_index *index, const mt_seqs *reads, const uint32_t *pair_read,
+                               const uint32_t *pair_genome, const int64_t *pair_diag, const uint16_t *pair_E,
+                               uint64_t n_pairs, uint16_t *approx_out, uint8_t *accept_out, void *stream) {
+    if (!index || !reads) {
+        mt::set_last_error("mt_filter_pairs: null argument");
+        return MT_EINVAL;
+    }
+    if (n_pairs && (!pair_read || !pair_genome || !pair_diag || !pair_E || !approx_out || !accept_out)) {
+        mt::set_last_error("mt_filter_pairs: null pair array");
+        return MT_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    return guarded("mt_filter_pairs", [&] {
+        MT_REQUIRE(reads->n == 0 || (reads->seq && reads->offsets), "null read arrays");
+        mt::CallScope scope(s);
+        mt::ReadBatch rb;
+        rb.prepare(*reads, MT_E_FIXED, 0, s);
+        mt::DBuf<mt::u32> maxE(1);
+        MT_HIP(hipMemsetAsync(maxE.p, 0, sizeof(mt::u32), s));
+        if (n_pairs) {
+            mt::launch_max_u16(pair_E, n_pairs, maxE.p, s);
+        }
+        mt::u32 max_E = 0;
+        mt::read_back(s, maxE.p, &max_E, sizeof max_E);
+        if (max_E > 65534) max_E = 65534;
+        mt::FilterArgs fa{};
+        fa.pair_read = pair_read;
+        fa.pair_genome = pair_genome;
+        fa.pair_diag = pair_diag;
+        fa.pair_E = pair_E;
+        fa.read_E = rb.read_E.p;
+        fa.n_dev = nullptr;
+        fa.n_host = n_pairs;
+        fa.n_reads = reads->n;
+        fa.read_off = reads->offsets;
+        fa.read_blk = rb.planes.blk_off.p;
+        fa.read_lohi = rb.planes.lohi.p;
+        fa.read_nb = rb.planes.nb.p;
+        fa.n_genomes = index->n_genomes;
+        fa.ref_blk = index->ref.blk_off.p;
+        fa.ref_lohi = index->ref.lohi.p;
+        fa.ref_nb = index->ref.nb.p;
+        fa.glen = index->glen.p;
+        fa.has_n = index->has_n.p;
+        fa.approx = approx_out;
+        fa.accept = accept_out;
+        fa.flags = rb.flags.p;
+        mt::launch_filter(fa, n_pairs, max_E, s);
+        mt::u32 f = 0;
+        mt::read_back(s, rb.flags.p, &f, sizeof f);
+        mt::check_flags(f);
+    });
+}

@@ -1,0 +1,262 @@
+// Device helpers for the gfx950 kernels: base codes, the k-mer hash, 2-bit
+// plane fetches, mismatch words and the wavefront-group obstacle walk.
+//
+// Sequence layout in HBM ("planes"): a sequence of length L owns
+// ceil(L/64) + 1 blocks; block b holds bases [64b, 64b + 64) as three 64-bit
+// words, base i at bit (i mod 64):
+//   lo  bit 0 of the base code   (A=0, C=1, G=2, T=3)
+//   hi  bit 1 of the base code
+//   nb  1 where the base is N, or lies past the end of the sequence
+// lo and hi of a block are stored together as one 16-byte word (u64x2) so a
+// single load brings both; nb sits in its own array.  The extra block at the
+// end lets a 64-bit funnel fetch at any position < L read block b + 1 without
+// a bounds check.  With bit planes, one XOR per plane and one OR compare 64
+// bases at once, so the neighbourhood map of the filter costs a handful of
+// 64-bit VALU operations per 64 columns.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mt {
+typedef uint8_t u8;
+typedef uint16_t u16;
+typedef uint32_t u32;
+typedef uint64_t u64;
+typedef int64_t i64;
+}  // namespace mt
+using namespace mt;
+
+struct alignas(16) u64x2 {
+    u64 lo, hi;
+};
+
+// Input-validation flags raised by kernels (OR-ed into one device word).
+enum : u32 {
+    ERR_BAD_BYTE = 1u,
+    ERR_READ_TOO_LONG = 2u,
+    ERR_E_TOO_LARGE = 4u,
+    ERR_PAIR_RANGE = 8u,
+    ERR_KEY_OVERFLOW = 16u,
+    ERR_INTERNAL = 32u,
+    ERR_OFFSETS = 64u,
+};
+
+// Offset added to a diagonal so that (genome, diagonal) packs into one
+// unsigned 64-bit key: diagonal = q - p > -65536 for reads of <= 65535 bases.
+constexpr i64 DIAG_BIAS = 65536;
+constexpr u64 DIAG_MASK = (1ull << 33) - 1;
+
+__host__ __device__ inline u64 cand_key(u32 genome, i64 diag) {
+    return ((u64)genome << 33) | (u64)(diag + DIAG_BIAS);
+}
+__host__ __device__ inline u32 key_genome(u64 key) { return (u32)(key >> 33); }
+__host__ __device__ inline i64 key_diag(u64 key) { return (i64)(key & DIAG_MASK) - DIAG_BIAS; }
+
+// ASCII -> code: 0..3 for ACGT, 4 for N, 5 for any other byte (either case).
+__device__ inline u32 base_code(u32 c) {
+    u32 u = c & 0xDFu;  // upper-case letters
+    u32 two = ((c >> 1) ^ (c >> 2)) & 3u;  // A->0, C->1, G->2, T->3
+    bool acgt = (u == 'A') | (u == 'C') | (u == 'G') | (u == 'T');
+    return acgt ? two : (u == 'N' ? 4u : 5u);
+}
+
+// splitmix64 finalizer (Steele, Lea and Flood 2014), a bijection on 64-bit words.
+__host__ __device__ inline u64 mix64(u64 z) {
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+// Spreads the low 32 bits of x to the even bit positions of a 64-bit word.
+__device__ inline u64 spread_even(u64 x) {
+    x = (x | (x << 16)) & 0x0000FFFF0000FFFFull;
+    x = (x | (x << 8)) & 0x00FF00FF00FF00FFull;
+    x = (x | (x << 4)) & 0x0F0F0F0F0F0F0F0Full;
+    x = (x | (x << 2)) & 0x3333333333333333ull;
+    x = (x | (x << 1)) & 0x5555555555555555ull;
+    return x;
+}
+
+// k-mer value sum code[t] * 4^(k-1-t) (first base most significant) from the
+// lo / hi plane bits of bases t = 0..k-1 at bits 0..k-1 (k <= 31).
+__device__ inline u64 kmer_value(u64 lo, u64 hi, u32 k) {
+    u32 l = __brev((u32)lo) >> (32 - k);
+    u32 h = __brev((u32)hi) >> (32 - k);
+    return spread_even(l) | (spread_even(h) << 1);
+}
+
+__device__ inline u64 funnel(u64 a, u64 b, u32 s) {
+    return s ? (a >> s) | (b << (64 - s)) : a;
+}
+
+// 64 bases from position p >= 0 of a sequence whose planes start at block 0
+// of the given arrays (p must be < the sequence length, or < its padded
+// length for the nb plane, so block p/64 + 1 exists).
+struct Bits64 {
+    u64 lo, hi, nb;
+};
+
+__device__ inline Bits64 fetch_planes(const u64x2 *__restrict__ lohi, const u64 *__restrict__ nb, i64 p) {
+    u64 b = (u64)p >> 6;
+    u32 s = (u32)p & 63u;
+    u64x2 a = lohi[b], c = lohi[b + 1];
+    Bits64 r;
+    r.lo = funnel(a.lo, c.lo, s);
+    r.hi = funnel(a.hi, c.hi, s);
+    r.nb = funnel(nb[b], nb[b + 1], s);
+    return r;
+}
+
+// 64 reference bases from signed position p of a genome of length L:
+// bits of positions outside [0, L) come back with nb = 1 (never a match).
+// has_n = 0 skips the N plane for genomes without N.
+__device__ inline Bits64 fetch_ref(const u64x2 *__restrict__ lohi, const u64 *__restrict__ nb, i64 L, bool has_n,
+                                   i64 p) {
+    Bits64 r;
+    if (p >= L || p <= -64) {
+        r.lo = r.hi = 0;
+        r.nb = ~0ull;
+        return r;
+    }
+    i64 q = p < 0 ? 0 : p;
+    u64 b = (u64)q >> 6;
+    u32 s = (u32)q & 63u;
+    u64x2 a = lohi[b], c = lohi[b + 1];
+    r.lo = funnel(a.lo, c.lo, s);
+    r.hi = funnel(a.hi, c.hi, s);
+    r.nb = has_n ? funnel(nb[b], nb[b + 1], s) : 0ull;
+    if (p < 0) {
+        u32 sh = (u32)(-p);
+        r.lo <<= sh;
+        r.hi <<= sh;
+        r.nb = (r.nb << sh) | ((1ull << sh) - 1);
+    }
+    i64 room = L - p;  // bases of the genome at or after p within this word
+    if (room < 64) r.nb |= ~0ull << room;
+    return r;
+}
+
+// Mismatch ("obstacle") bits of 64 columns: 1 where the read base cannot match.
+__device__ inline u64 mismatch(const Bits64 &q, const Bits64 &w) {
+    return (q.lo ^ w.lo) | (q.hi ^ w.hi) | q.nb | w.nb;
+}
+
+// Max over the G lanes of a group (G a power of two <= 64).
+template <int G>
+__device__ inline int group_max(int v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, G));
+    return v;
+}
+
+// Read planes + reference planes of one (read, location) pair.
+struct PairView {
+    const u64x2 *qlohi;
+    const u64 *qnb;
+    int m;
+    const u64x2 *rlohi;
+    const u64 *rnb;
+    i64 L;
+    bool has_n;
+    i64 diag;
+};
+
+// Length of the obstacle-free run of row d from column j (capped at m - j).
+// The read's nb plane is 1 past its end, so the run always stops by column m.
+__device__ inline int row_run(const PairView &v, int d, int j) {
+    int run = 0;
+    while (j + run < v.m) {
+        Bits64 q = fetch_planes(v.qlohi, v.qnb, j + run);
+        Bits64 w = fetch_ref(v.rlohi, v.rnb, v.L, v.has_n, v.diag + d + j + run);
+        u64 mm = mismatch(q, w);
+        if (mm) {
+            run += (int)__builtin_ctzll(mm);
+            break;
+        }
+        run += 64;
+    }
+    return min(run, v.m - j);
+}
+
+// The obstacle walk of one pair by a group of G lanes (lane = lane index in
+// the group; all G lanes call it together).  Rows d = -E..E are dealt to the
+// lanes round-robin; each step takes the longest run over all rows, then
+// counts and skips the obstacle that ends it.  Returns min(count, E + 1).
+template <int G>
+__device__ inline int obstacle_walk(const PairView &v, int E, int lane) {
+    int rows = 2 * E + 1;
+    int j = 0, c = 0;
+    for (;;) {
+        int best = 0;
+        for (int r = lane; r < rows; r += G) best = max(best, row_run(v, r - E, j));
+        best = group_max<G>(best);
+        j += best;
+        if (j >= v.m) break;
+        c += 1;
+        if (c > E) break;
+        j += 1;
+    }
+    return c < E + 1 ? c : E + 1;
+}
+
+// Table slot value: a single occurrence is (genome << 32 | position) with the
+// top bit clear; several occurrences are MULTI | count << 40 | start into the
+// occurrence array; count 0 marks a k-mer dropped by max_occ.
+constexpr u64 SLOT_EMPTY_KEY = ~0ull;  // k-mer values are < 4^31
+constexpr u64 SLOT_MULTI = 1ull << 63;
+constexpr u64 SLOT_NONE = ~0ull;       // value of a slot still being built
+constexpr u32 MAX_KEY_OCC = (1u << 23) - 1;
+
+__device__ inline u32 slot_count(u64 val) { return (val & SLOT_MULTI) ? (u32)((val >> 40) & MAX_KEY_OCC) : 1u; }
+__device__ inline u64 slot_start(u64 val) { return val & ((1ull << 40) - 1); }
+
+// Bucket of k-mer x: 4 slots (64 bytes) per bucket, chosen by the top 32 bits
+// of a salted second hash scaled to the bucket count (no power-of-two
+// restriction).  The minimizer hash itself must not place keys: minimizers
+// are window minima of it, so their hashes crowd toward zero and would pile
+// into the first buckets.
+__host__ __device__ inline u64 bucket_of(u64 x, u64 nbuckets) {
+    return ((mix64(x ^ 0x632be59bd9b4e019ull) >> 32) * nbuckets) >> 32;
+}
+
+// Looks k-mer x up; returns the slot value or SLOT_NONE if absent.
+__device__ inline u64 table_lookup(const u64x2 *__restrict__ table, u64 nbuckets, u64 x) {
+    u64 b = bucket_of(x, nbuckets);
+    for (;;) {
+        const u64x2 *bk = table + b * 4;
+#pragma unroll
+        for (int s = 0; s < 4; s++) {
+            u64x2 e = bk[s];
+            if (e.lo == x) return e.hi;
+            if (e.lo == SLOT_EMPTY_KEY) return SLOT_NONE;
+        }
+        b = (b + 1 == nbuckets) ? 0 : b + 1;
+    }
+}
+
+// Exclusive prefix sum of one value per thread over a block of TPB threads
+// (TPB a multiple of 64); *total receives the block sum.  Contains barriers:
+// every thread of the block must call it.
+template <int TPB, class T>
+__device__ inline T block_exclusive_sum(T v, T *total) {
+    __shared__ T wave_tot[TPB / 64];
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    T x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        T y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) wave_tot[wid] = x;
+    __syncthreads();
+    T before = 0, all = 0;
+#pragma unroll
+    for (int i = 0; i < TPB / 64; i++) {
+        if (i < wid) before += wave_tot[i];
+        all += wave_tot[i];
+    }
+    __syncthreads();
+    *total = all;
+    return before + x - v;
+}

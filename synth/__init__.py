@@ -138,6 +138,10 @@ def _reads_one_length(rng, genomes: Genomes, n: int, m: int, p_sub, p_indel, pad
     goff = genomes.offsets[:-1].astype(np.int64)
     out = np.empty((n, m), dtype=np.uint8)
     origin = np.empty((n, 2), dtype=np.int64)
+    if m == 0:
+        origin[:, 0] = rng.integers(0, genomes.n, size=n)
+        origin[:, 1] = 0
+        return out, origin
     done = np.zeros(n, dtype=bool)
     while not done.all():
         rows = np.flatnonzero(~done)

@@ -1,0 +1,60 @@
+"""The C-ABI library loads and exports every function include/*.h declares,
+and the binding's struct layouts match the header's (CPU only: no compute)."""
+import ctypes as C
+import glob
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2311_02029_amd import _abi
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        src = open(h).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names |= set(re.findall(r"\b(mt_[a-z_0-9]+)\s*\(", src))
+    return names
+
+
+def test_library_exports_every_declared_function():
+    lib = C.CDLL(_abi.LIB_PATH)
+    declared = _declared_functions()
+    assert declared, "no declarations found"
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert declared == set(_abi.ABI_FUNCTIONS)
+    assert _abi.load().mt_abi_version() == 1
+
+
+def test_struct_layouts_match_header(tmp_path):
+    prog = tmp_path / "sizes.c"
+    prog.write_text(r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "metatrinity.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(mt_seqs), sizeof(mt_index_params), sizeof(mt_query_params),
+         sizeof(mt_index_info), offsetof(mt_query_params, mode), offsetof(mt_index_info, k));
+  return 0;
+}''')
+    exe = tmp_path / "sizes"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)])
+    got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
+    want = [C.sizeof(_abi.mt_seqs), C.sizeof(_abi.mt_index_params), C.sizeof(_abi.mt_query_params),
+            C.sizeof(_abi.mt_index_info), _abi.mt_query_params.mode.offset, _abi.mt_index_info.k.offset]
+    assert got == want
+
+
+def test_null_arguments_are_errors_not_crashes():
+    lib = _abi.load()
+    h = C.c_void_p()
+    assert lib.mt_index_build(None, None, None, 0, None, C.byref(h)) == _abi.MT_EINVAL
+    assert b"null" in lib.mt_last_error()
+    assert lib.mt_classify(None, None, None, None, C.byref(h)) == _abi.MT_EINVAL
+    assert lib.mt_result_reads(None, None, None, None, None) == _abi.MT_EINVAL

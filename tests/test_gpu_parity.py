@@ -1,0 +1,179 @@
+"""GPU (HIP, gfx950) vs CPU oracle, element by element, bit-exact.
+
+Candidate lists (genome, diagonal, seed hits, canonical order), approximate
+edit counts, accept bits, read flags and per-taxon counts must be identical:
+the whole path is integer work.
+"""
+import random
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("cand_offsets", "read_accepted", "read_E", "genome", "diag", "hits", "approx", "accept", "unique",
+          "multi")
+
+
+@pytest.fixture(scope="module")
+def mt():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2311_02029_amd as mt_
+    return mt_
+
+
+def assert_same(gpu: dict, ref: dict, ctx=""):
+    for f in FIELDS:
+        a, b = np.asarray(gpu[f]), np.asarray(ref[f])
+        assert a.shape == b.shape, (ctx, f, a.shape, b.shape)
+        if not np.array_equal(a, b):
+            bad = np.flatnonzero(a != b)[:10]
+            raise AssertionError(f"{ctx} {f} differs at {bad.tolist()}: gpu {a[bad].tolist()} oracle {b[bad].tolist()}")
+    assert gpu["unmapped"] == ref["unmapped"], ctx
+
+
+def run_both(mt, genomes, reads, k, w, max_occ=0, taxon=None, n_taxa=None, mode=0, **q):
+    ix = mt.Index(genomes, k, w, max_occ=max_occ, taxon=taxon, n_taxa=n_taxa)
+    dr = mt.to_device(reads)
+    res = ix.classify(dr, mode=mode, **q)
+    got = res.to_host()
+    res.free()
+    ref = oracle.Index(genomes, k, w, max_occ=max_occ, taxon=taxon, n_taxa=n_taxa).classify(
+        reads, q.get("min_hits", 3), q.get("top_n", 3), q.get("e_mode", 0), q.get("e_value", 7))
+    return got, ref
+
+
+@pytest.mark.parametrize("top_n", [3, 0])
+@pytest.mark.parametrize("E", [0, 3, 7, 15])
+def test_small_workload_bit_exact(mt, top_n, E):
+    gen, reads, p = synth.workload_small()
+    got, ref = run_both(mt, gen.ascii(), reads, p["k"], p["w"], min_hits=3, top_n=top_n, e_value=E)
+    assert_same(got, ref, f"small top_n={top_n} E={E}")
+    assert len(ref["genome"]) > 9000
+
+
+def _random_case(rnd):
+    motif = "".join(rnd.choice("ACGT") for _ in range(rnd.randint(3, 9)))
+    genomes = []
+    for _ in range(rnd.randint(1, 5)):
+        s = []
+        L = rnd.randint(1, 700)
+        while len(s) < L:
+            u = rnd.random()
+            s.extend(motif if u < 0.3 else rnd.choice(["A", "C", "G", "T", "N"] if u < 0.32 else "ACGT"))
+        genomes.append("".join(s[:L]))
+    reads = []
+    for _ in range(rnd.randint(0, 60)):
+        g = rnd.choice(genomes)
+        m = rnd.choice([0, 1, 5, rnd.randint(10, 70), rnd.randint(60, 300)])
+        st = rnd.randint(-5, max(0, len(g) - 1))
+        r = list(g[max(st, 0):max(st, 0) + m])
+        while len(r) < m:
+            r.append(rnd.choice("ACGT"))
+        for i in range(len(r)):
+            u = rnd.random()
+            if u < 0.03:
+                r[i] = rnd.choice("ACGTN")
+            elif u < 0.04:
+                r[i] = r[i].lower()
+        if rnd.random() < 0.1 and len(r) > 3:
+            del r[rnd.randrange(len(r))]
+        reads.append("".join(r))
+    return genomes, reads
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_small_cases_bit_exact(mt, seed):
+    rnd = random.Random(seed)
+    genomes, reads = _random_case(rnd)
+    k, w = rnd.randint(3, 16), rnd.randint(1, 12)
+    n_tax = max(1, len(genomes) // 2)
+    taxon = np.array([rnd.randrange(n_tax) for _ in genomes], np.uint32)
+    q = dict(min_hits=rnd.choice([1, 2, 3]), top_n=rnd.choice([0, 1, 3]), e_mode=rnd.choice([0, 1, 2]),
+             e_value=rnd.choice([0, 2, 50, 120]) if True else 0)
+    if q["e_mode"] == 0:
+        q["e_value"] = rnd.randint(0, 9)
+    got, ref = run_both(mt, synth.SeqSet.from_list(genomes), synth.SeqSet.from_list(reads), k, w,
+                        max_occ=rnd.choice([0, 0, 4]), taxon=taxon, n_taxa=n_tax, **q)
+    assert_same(got, ref, f"seed {seed}")
+
+
+def test_many_hits_per_read_uses_large_path(mt):
+    """Reads with more seed hits than one block holds in LDS (repetitive reference)."""
+    rnd = random.Random(77)
+    unit = "".join(rnd.choice("ACGT") for _ in range(40))
+    genome = "".join(unit if rnd.random() < 0.9 else rnd.choice("ACGT") * 40 for _ in range(300))
+    reads = [genome[i:i + 400] for i in range(0, 4000, 397)]
+    got, ref = run_both(mt, synth.SeqSet.from_list([genome, genome[::-1]]), synth.SeqSet.from_list(reads), 8, 3,
+                        min_hits=2, top_n=0, e_value=10)
+    assert_same(got, ref, "large")
+    co = ref["cand_offsets"].astype(np.int64)
+    assert np.diff(co).max() > 100
+
+
+def test_long_reads_large_E_bit_exact(mt):
+    rnd = np.random.default_rng(5)
+    gen = synth.make_genomes(rnd, 3, 60_000, 0.5)
+    lens = rnd.integers(1000, 6000, 40)
+    reads, _ = synth.make_reads(rnd, gen, lens, 0.02, 0.03)
+    got, ref = run_both(mt, gen.ascii(), reads, 15, 10, min_hits=3, top_n=3, e_mode=1, e_value=50)
+    assert_same(got, ref, "long")
+    assert ref["read_E"].max() >= 100
+
+
+def test_empty_read_set(mt):
+    gen, _, p = synth.workload_small(10)
+    got, ref = run_both(mt, gen.ascii(), synth.SeqSet.from_list([]), p["k"], p["w"])
+    assert_same(got, ref, "empty")
+
+
+def test_invalid_byte_rejected(mt):
+    gen, _, p = synth.workload_small(10)
+    ix = mt.Index(gen.ascii(), p["k"], p["w"])
+    with pytest.raises(mt.MTError) as e:
+        ix.classify(mt.to_device(synth.SeqSet.from_list(["ACGTACGTAC", "ACGT*ACG"])))
+    assert e.value.status == -1
+    with pytest.raises(mt.MTError):
+        mt.Index(synth.SeqSet.from_list(["ACGTXACGT"]), 4, 2)
+
+
+def test_filter_pairs_against_oracle(mt):
+    import torch
+    rnd = np.random.default_rng(11)
+    gen = synth.make_genomes(rnd, 4, 20_000, (0.3, 0.7))
+    lens = np.concatenate([rnd.integers(0, 300, 300), rnd.integers(300, 1500, 20)])
+    reads, origin = synth.make_reads(rnd, gen, lens, 0.01, 0.01)
+    reads = synth.inject_n(rnd, reads, 0.002)
+    n = 4000
+    pr = rnd.integers(0, reads.n, n).astype(np.uint32)
+    pg = np.where(rnd.random(n) < 0.7, origin[pr, 0], rnd.integers(0, 4, n)).astype(np.uint32)
+    pdg = (origin[pr, 1] + rnd.integers(-20, 21, n)).astype(np.int64)
+    pdg[:50] = rnd.integers(-400, 0, 50)
+    pdg[50:100] = 20_000 + rnd.integers(-300, 50, 50)
+    pe = rnd.integers(0, 40, n).astype(np.uint16)
+    ga = gen.ascii()
+    ix = mt.Index(ga, 15, 10)
+    dev = lambda a, t: torch.from_numpy(a.view(t) if a.dtype.itemsize == np.dtype(t).itemsize else a).cuda()
+    ap, ac = ix.filter_pairs(mt.to_device(reads), torch.from_numpy(pr.view(np.int32)).cuda(),
+                             torch.from_numpy(pg.view(np.int32)).cuda(), torch.from_numpy(pdg).cuda(),
+                             torch.from_numpy(pe.view(np.int16)).cuda())
+    ap = ap.cpu().numpy().view(np.uint16)
+    ac = ac.cpu().numpy()
+    oap, oac = oracle.Index(ga, 15, 10).filter_pairs(reads, pr, pg, pdg, pe)
+    assert np.array_equal(ap, oap), np.flatnonzero(ap != oap)[:10]
+    assert np.array_equal(ac, oac)
+    assert (oap <= pe).mean() > 0.3 and (oap > pe).mean() > 0.05
+
+
+def test_repeat_calls_identical(mt):
+    gen, reads, p = synth.workload_small(3000)
+    ix = mt.Index(gen.ascii(), p["k"], p["w"])
+    dr = mt.to_device(reads)
+    a = ix.classify(dr).to_host()
+    b = ix.classify(dr).to_host()
+    assert_same(a, b, "repeat")
