@@ -576,14 +576,15 @@ extern "C" int mt_classify(const mt_index *index, const mt_query_params *params,
             tm.begin(s);
             mt::mt_result_init(*res, reads->n, index->n_taxa, s);
             mt::ReadBatch rb;
-            rb.prepare(*reads, params->e_mode, params->e_value, s);
-            MT_HIP(hipMemcpyAsync(res->read_E.p, rb.read_E.p, (reads->n ? reads->n : 1) * sizeof(mt::u16),
-                                  hipMemcpyDeviceToDevice, s));
-            tm.mark("pack");
-            if (params->mode == MT_MODE_FUSED)
+            if (params->mode == MT_MODE_FUSED) {
                 mt::classify_fused(*index, *params, *reads, rb, *res, tm, s);
-            else
+            } else {
+                rb.prepare(*reads, params->e_mode, params->e_value, s);
+                MT_HIP(hipMemcpyAsync(res->read_E.p, rb.read_E.p, (reads->n ? reads->n : 1) * sizeof(mt::u16),
+                                      hipMemcpyDeviceToDevice, s));
+                tm.mark("pack");
                 mt::classify_per_stage(*index, *params, *reads, rb, *res, tm, s);
+            }
             mt::u32 f = 0;
             mt::read_back(s, rb.flags.p, &f, sizeof f);
             mt::check_flags(f);

@@ -1,4 +1,25 @@
-// Fused seed-count + filter path (placeholder until the fused kernel lands).
+// Fused seed-count + filter path for short reads (Fig. 1 steps 2b-2d and 3a
+// in one kernel).  One wavefront owns one read at a time:
+//   1. its bytes are loaded one per lane and turned into lo / hi / N bit
+//      planes with ballots (wave-uniform words, held in scalar registers);
+//   2. lane i hashes the k-mer at position i (per 64-position round); hashes
+//      and k-mer values go to a per-wave LDS tile;
+//   3. lane s scans window s for its smallest valid (hash, position); picks
+//      are marked in LDS and compacted with ballot + popcount;
+//   4. each minimizer lane probes one 64-byte table bucket (all four slots
+//      loaded at once) and writes its (genome, diagonal) hits to LDS;
+//   5. lane j counts how many hits share hit j's location and whether j is
+//      the first of them; locations with >= min_hits become candidates, and
+//      each candidate's rank in (hits desc, genome, diagonal) order picks the
+//      top_n;
+//   6. each kept candidate is filtered by a group of G lanes (G = 16, 32 or
+//      64 by E), one row d of the band per lane: the row's mismatch words for
+//      the whole read stay in registers and the obstacle walk advances by
+//      ctz of the row bits plus a max over the group;
+//   7. the read's accept flag and its per-taxon unique / multi count.
+// Reads beyond the kernel's limits (longer than 256 bases, E above 31, more
+// than 256 seed hits) are queued and finished by the per-stage kernels, so
+// every read gets the same result as in per-stage mode.
 #include "classify.hpp"
 
 namespace mt {
@@ -13,9 +34,629 @@ void launch_max_u16(const u16 *v, u64 n, u32 *out, hipStream_t s) {
     MT_HIP(hipGetLastError());
 }
 
-void classify_fused(const mt_index &, const mt_query_params &, const mt_seqs &, ReadBatch &, mt_result &, Timer &,
-                    hipStream_t) {
-    throw Error(MT_EINVAL, "fused mode is not available in this build");
+constexpr int F_WPB = 4;         // wavefronts per block
+constexpr int F_MAX_M = 256;     // longest read the fused kernel takes
+constexpr int F_HIT_CAP = 256;   // seed hits per read held in LDS
+constexpr int F_MAX_E = 31;      // 2E + 1 rows fit one wavefront
+constexpr int F_MAX_TOPN = 4;
+
+enum : u32 { ST_READS, ST_BASES, ST_MINS, ST_WBLOCKS, ST_CANDS, ST_COUNT };
+
+struct FusedArgs {
+    const u8 *seq;
+    const u64 *off;
+    u64 n;
+    u32 k, w, min_hits, top_n, e_mode, e_value;
+    const u64x2 *table;
+    u64 nbuckets;
+    const u64 *occ;
+    const u64 *ref_blk;
+    const u64x2 *ref_lohi;
+    const u64 *ref_nb;
+    const u64 *glen;
+    const u32 *has_n;
+    const u32 *taxon;
+    // staging: top_n slots per read
+    u32 *st_genome;
+    i64 *st_diag;
+    u32 *st_hits;
+    u16 *st_approx;
+    u8 *st_accept;
+    u32 *ncand;
+    u8 *read_accepted;
+    u16 *read_E;
+    unsigned long long *uniq, *multi, *unmapped;
+    u32 *fb_list;
+    u32 *fb_count;
+    u32 *flags;
+    unsigned long long *stats;
+};
+
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ inline u64 ballot64(bool p) { return __ballot(p); }
+
+// Number of set bits of m below this lane.
+__device__ inline u32 lanes_below(u64 m, int lane) {
+    return (u32)__popcll(lane ? m & ((~0ull) >> (64 - lane)) : 0ull);
+}
+
+// mm[w] for a wave-uniform or per-lane word index w in 0..4 (mm[4] is all ones).
+__device__ inline u64 pick5(const u64 (&mm)[5], int w) {
+    u64 v = mm[4];
+    v = w == 3 ? mm[3] : v;
+    v = w == 2 ? mm[2] : v;
+    v = w == 1 ? mm[1] : v;
+    v = w == 0 ? mm[0] : v;
+    return v;
+}
+
+// Obstacle-free run of a row from column j, from the row's mismatch words
+// (bits past the read's end are set, so the run stops by the end).
+__device__ inline int reg_run(const u64 (&mm)[5], int j) {
+    int w = j >> 6;
+    u32 s = (u32)j & 63u;
+    int run = 0;
+    for (;;) {
+        u64 v = funnel(pick5(mm, w), pick5(mm, w + 1), s);
+        if (v) return run + (int)__builtin_ctzll(v);
+        run += 64;
+        w += 1;
+    }
+}
+
+// The 4-slot bucket probe: all four slots are loaded before any compare.
+__device__ inline u64 bucket_lookup(const u64x2 *__restrict__ table, u64 nbuckets, u64 x) {
+    u64 b = bucket_of(x, nbuckets);
+    for (;;) {
+        const u64x2 *bk = table + b * 4;
+        u64x2 e0 = bk[0], e1 = bk[1], e2 = bk[2], e3 = bk[3];
+        if (e0.lo == x) return e0.hi;
+        if (e0.lo == SLOT_EMPTY_KEY) return SLOT_NONE;
+        if (e1.lo == x) return e1.hi;
+        if (e1.lo == SLOT_EMPTY_KEY) return SLOT_NONE;
+        if (e2.lo == x) return e2.hi;
+        if (e2.lo == SLOT_EMPTY_KEY) return SLOT_NONE;
+        if (e3.lo == x) return e3.hi;
+        if (e3.lo == SLOT_EMPTY_KEY) return SLOT_NONE;
+        b = (b + 1 == nbuckets) ? 0 : b + 1;
+    }
+}
+
+template <int G>
+__device__ inline int filter_group(const FusedArgs &a, const u64 (&Qlo)[5], const u64 (&Qhi)[5],
+                                   const u64 (&Qn)[5], int m, int E, u32 g, i64 diag, int lane_g) {
+    u64 mm[5];
+    mm[4] = ~0ull;
+    int rows = 2 * E + 1;
+    if (lane_g < rows) {
+        int d = lane_g - E;
+        const u64x2 *rl = a.ref_lohi + a.ref_blk[g];
+        const u64 *rn = a.ref_nb + a.ref_blk[g];
+        i64 L = (i64)a.glen[g];
+        bool hn = a.has_n[g] != 0;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            Bits64 wv = fetch_ref(rl, rn, L, hn, diag + d + 64 * q);
+            mm[q] = (Qlo[q] ^ wv.lo) | (Qhi[q] ^ wv.hi) | Qn[q] | wv.nb;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 4; q++) mm[q] = ~0ull;
+    }
+    int j = 0, c = 0;
+    for (;;) {
+        int run = reg_run(mm, j);
+        run = group_max<G>(run);
+        j += run;
+        if (j >= m) break;
+        c += 1;
+        if (c > E) break;
+        j += 1;
+    }
+    return c < E + 1 ? c : E + 1;
+}
+
+__global__ __launch_bounds__(64 * F_WPB) void k_fused(FusedArgs a) {
+    __shared__ u64 sh_h[F_WPB][F_MAX_M];     // k-mer hashes; later candidate keys
+    __shared__ u64 sh_x[F_WPB][F_MAX_M];     // k-mer values
+    __shared__ u64 sh_hit[F_WPB][F_HIT_CAP]; // (genome, diagonal) keys of the seed hits
+    __shared__ u32 sh_cnt[F_WPB][F_HIT_CAP]; // candidate hit counts
+    __shared__ u16 sh_pos[F_WPB][F_MAX_M];   // minimizer positions
+    __shared__ u8 sh_pick[F_WPB][F_MAX_M];   // window picks
+    __shared__ u8 sh_ok[F_WPB][F_MAX_M];     // k-mer has no N
+    __shared__ u32 sh_sel[F_WPB][F_MAX_TOPN];
+    __shared__ u16 sh_apx[F_WPB][F_MAX_TOPN];
+
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    u64 *hh = sh_h[wid];
+    u64 *xx = sh_x[wid];
+    u64 *hits = sh_hit[wid];
+    u32 *cnts = sh_cnt[wid];
+    u16 *mpos = sh_pos[wid];
+    u8 *pick = sh_pick[wid];
+    u8 *okk = sh_ok[wid];
+    u32 *sel = sh_sel[wid];
+    u16 *apx = sh_apx[wid];
+
+    const u32 k = a.k, T = a.min_hits ? a.min_hits : 1u, N = a.top_n;
+    const u64 kmask = (1ull << k) - 1;
+    u64 st_reads = 0, st_bases = 0, st_mins = 0, st_wblk = 0, st_cands = 0;
+    u32 wflags = 0;
+
+    for (u64 r = (u64)blockIdx.x * F_WPB + wid; r < a.n; r += (u64)gridDim.x * F_WPB) {
+        const u64 beg = a.off[r];
+        const int m = (int)(a.off[r + 1] - beg);
+        const u64 mm_ = (u64)m;
+        u64 Ewide = a.e_mode == MT_E_FIXED ? a.e_value
+                    : a.e_mode == MT_E_CEIL_PERMILLE ? (mm_ * a.e_value + 999) / 1000
+                                                     : (mm_ * a.e_value) / 1000;
+        if (Ewide > 65534) wflags |= ERR_E_TOO_LARGE;
+        const int E = Ewide > 65535 ? 65535 : (int)Ewide;
+        if (lane == 0) a.read_E[r] = (u16)E;
+        if (m > F_MAX_M || E > F_MAX_E) {
+            if (lane == 0) a.fb_list[atomicAdd(a.fb_count, 1u)] = (u32)r;
+            continue;
+        }
+
+        // 1. bit planes of the read (bases past m are N)
+        u64 Qlo[5], Qhi[5], Qn[5];
+        bool bad = false;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            int i = 64 * q + lane;
+            u32 c = i < m ? base_code(a.seq[beg + i]) : 4u;
+            bad |= c == 5;
+            Qlo[q] = ballot64(c < 4 && (c & 1u));
+            Qhi[q] = ballot64(c < 4 && (c & 2u));
+            Qn[q] = ballot64(c >= 4);
+        }
+        Qlo[4] = Qhi[4] = 0;
+        Qn[4] = ~0ull;
+        if (ballot64(bad)) {
+            wflags |= ERR_BAD_BYTE;
+            continue;
+        }
+
+        // 2. k-mer values and hashes
+        const int nk = m - (int)k + 1;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            int i = 64 * q + lane;
+            bool ok = false;
+            if (i < nk) {
+                u64 lo = funnel(Qlo[q], Qlo[q + 1], (u32)lane);
+                u64 hi = funnel(Qhi[q], Qhi[q + 1], (u32)lane);
+                u64 nb = funnel(Qn[q], Qn[q + 1], (u32)lane);
+                u64 x = kmer_value(lo, hi, k);
+                xx[i] = x;
+                hh[i] = mix64(x);
+                ok = (nb & kmask) == 0;
+            }
+            okk[i] = ok;
+            pick[i] = 0;
+        }
+        wave_sync();
+
+        // 3. window minima
+        int nmin = 0;
+        if (nk > 0) {
+            const int win = nk < (int)a.w ? nk : (int)a.w;
+            const int nws = nk - win + 1;
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                int ws = 64 * q + lane;
+                if (ws < nws) {
+                    int best = -1;
+                    u64 bh = 0;
+                    for (int i = ws; i < ws + win; i++) {
+                        if (!okk[i]) continue;
+                        u64 hv = hh[i];
+                        if (best < 0 || hv < bh) {
+                            best = i;
+                            bh = hv;
+                        }
+                    }
+                    if (best >= 0) pick[best] = 1;
+                }
+            }
+            wave_sync();
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                int i = 64 * q + lane;
+                bool chosen = i < nk && pick[i];
+                u64 cm = ballot64(chosen);
+                if (chosen) mpos[nmin + lanes_below(cm, lane)] = (u16)i;
+                nmin += __popcll(cm);
+            }
+            wave_sync();
+        }
+
+        // 4. table probes -> seed hits in LDS
+        int H = 0;
+        bool overflow = false;
+        for (int t0 = 0; t0 < nmin; t0 += 64) {
+            int j = t0 + lane;
+            u64 v = SLOT_NONE;
+            int p = 0;
+            u32 cnt = 0;
+            if (j < nmin) {
+                p = mpos[j];
+                v = bucket_lookup(a.table, a.nbuckets, xx[p]);
+                cnt = v == SLOT_NONE ? 0u : slot_count(v);
+            }
+            // exclusive prefix of cnt over the wave
+            u32 pre = cnt;
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                u32 y = __shfl_up(pre, o, 64);
+                if (lane >= o) pre += y;
+            }
+            u32 tot = __shfl(pre, 63, 64);
+            pre -= cnt;
+            if (H + (int)tot > F_HIT_CAP) {
+                overflow = true;
+                break;
+            }
+            if (cnt) {
+                int base = H + (int)pre;
+                if (!(v & SLOT_MULTI)) {
+                    hits[base] = cand_key((u32)(v >> 32), (i64)(u32)v - p);
+                } else {
+                    u64 st = slot_start(v);
+                    for (u32 u = 0; u < cnt; u++) {
+                        u64 gp = a.occ[st + u];
+                        hits[base + u] = cand_key((u32)(gp >> 32), (i64)(u32)gp - p);
+                    }
+                }
+            }
+            H += (int)tot;
+        }
+        if (overflow) {
+            if (lane == 0) a.fb_list[atomicAdd(a.fb_count, 1u)] = (u32)r;
+            continue;
+        }
+        wave_sync();
+
+        // 5. hits per location, candidates, top_n by rank
+        int C = 0;
+        for (int t0 = 0; t0 < H; t0 += 64) {
+            int j = t0 + lane;
+            bool is_c = false;
+            u64 key = 0;
+            u32 c = 0;
+            if (j < H) {
+                key = hits[j];
+                bool first = true;
+                for (int u = 0; u < H; u++) {
+                    u64 ku = hits[u];
+                    bool eq = ku == key;
+                    c += eq;
+                    first &= !(eq && u < j);
+                }
+                is_c = first && c >= T;
+            }
+            u64 cm = ballot64(is_c);
+            if (is_c) {
+                int s = C + (int)lanes_below(cm, lane);
+                hh[s] = key;
+                cnts[s] = c;
+            }
+            C += __popcll(cm);
+        }
+        wave_sync();
+        const int nc = C < (int)N ? C : (int)N;
+        for (int t0 = 0; t0 < C; t0 += 64) {
+            int cidx = t0 + lane;
+            if (cidx < C) {
+                u64 kc = hh[cidx];
+                u32 hc = cnts[cidx];
+                int rank = 0;
+                for (int b = 0; b < C; b++) {
+                    u32 hb = cnts[b];
+                    rank += hb > hc || (hb == hc && hh[b] < kc);
+                }
+                if (rank < nc) sel[rank] = (u32)cidx;
+            }
+        }
+        wave_sync();
+
+        // 6. filter the kept candidates
+        const int rows = 2 * E + 1;
+        const int G = rows <= 16 ? 16 : rows <= 32 ? 32 : 64;
+        const int per = 64 / G;
+        for (int c0 = 0; c0 < nc; c0 += per) {
+            int cidx = c0 + lane / G;
+            int lane_g = lane % G;
+            if (cidx < nc) {
+                u64 key = hh[sel[cidx]];
+                u32 g = key_genome(key);
+                i64 diag = key_diag(key);
+                int ap;
+                if (G == 16)
+                    ap = filter_group<16>(a, Qlo, Qhi, Qn, m, E, g, diag, lane_g);
+                else if (G == 32)
+                    ap = filter_group<32>(a, Qlo, Qhi, Qn, m, E, g, diag, lane_g);
+                else
+                    ap = filter_group<64>(a, Qlo, Qhi, Qn, m, E, g, diag, lane_g);
+                if (lane_g == 0) {
+                    apx[cidx] = (u16)ap;
+                    u64 o = r * N + (u64)cidx;
+                    a.st_genome[o] = g;
+                    a.st_diag[o] = diag;
+                    a.st_hits[o] = cnts[sel[cidx]];
+                    a.st_approx[o] = (u16)ap;
+                    a.st_accept[o] = ap <= E;
+                }
+            }
+        }
+        wave_sync();
+
+        // 7. read accept flag and taxon counts
+        if (lane == 0) {
+            a.ncand[r] = (u32)nc;
+            int best = 0x7fffffff;
+            for (int c = 0; c < nc; c++)
+                if (apx[c] <= E && apx[c] < best) best = apx[c];
+            if (best == 0x7fffffff) {
+                a.read_accepted[r] = 0;
+                atomicAdd(a.unmapped, 1ull);
+            } else {
+                // distinct taxa of the accepted candidates with the best count
+                a.read_accepted[r] = 1;
+                int nt = 0;
+                u32 first = 0;
+                for (int c = 0; c < nc; c++) {
+                    if (apx[c] != best) continue;
+                    u32 t = a.taxon[key_genome(hh[sel[c]])];
+                    bool seen = false;
+                    for (int b = 0; b < c; b++)
+                        seen |= apx[b] == best && a.taxon[key_genome(hh[sel[b]])] == t;
+                    if (seen) continue;
+                    if (nt == 0) first = t;
+                    nt++;
+                }
+                if (nt == 1) {
+                    atomicAdd(&a.uniq[first], 1ull);
+                } else {
+                    for (int c = 0; c < nc; c++) {
+                        if (apx[c] != best) continue;
+                        u32 t = a.taxon[key_genome(hh[sel[c]])];
+                        bool seen = false;
+                        for (int b = 0; b < c; b++)
+                            seen |= apx[b] == best && a.taxon[key_genome(hh[sel[b]])] == t;
+                        if (!seen) atomicAdd(&a.multi[t], 1ull);
+                    }
+                }
+            }
+        }
+        st_reads += 1;
+        st_bases += (u64)m;
+        st_mins += (u64)nmin;
+        st_cands += (u64)nc;
+        st_wblk += (u64)nc * (u64)((m + 2 * E + 63) / 64);
+        wave_sync();
+    }
+    if (lane == 0) {
+        if (wflags) atomicOr(a.flags, wflags);
+        atomicAdd(&a.stats[ST_READS], st_reads);
+        atomicAdd(&a.stats[ST_BASES], st_bases);
+        atomicAdd(&a.stats[ST_MINS], st_mins);
+        atomicAdd(&a.stats[ST_WBLOCKS], st_wblk);
+        atomicAdd(&a.stats[ST_CANDS], st_cands);
+    }
+}
+
+// Offsets check for the fused path (it reads the ASCII bytes directly).
+__global__ void k_check_reads(const u64 *__restrict__ off, u64 n, u64 total, u32 *__restrict__ flags) {
+    u64 s = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n) return;
+    u64 a = off[s], b = off[s + 1];
+    u32 f = 0;
+    if (b < a || b > total || (s == 0 && a != 0) || (s == n - 1 && b != total)) f |= ERR_OFFSETS;
+    else if (b - a > 65535) f |= ERR_READ_TOO_LONG;
+    if (f) atomicOr(flags, f);
+}
+
+// Subset of reads (the fallback list) gathered into a contiguous batch.
+__global__ void k_subset_lengths(const u64 *__restrict__ off, const u32 *__restrict__ list, u64 n,
+                                 u64 *__restrict__ len) {
+    u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) len[i] = off[list[i] + 1] - off[list[i]];
+}
+
+__global__ void k_subset_copy(const u8 *__restrict__ seq, const u64 *__restrict__ off, const u32 *__restrict__ list,
+                              u64 n, const u64 *__restrict__ sub_off, u8 *__restrict__ sub_seq) {
+    u64 i = blockIdx.x;
+    if (i >= n) return;
+    u64 src = off[list[i]], dst = sub_off[i], len = sub_off[i + 1] - dst;
+    for (u64 t = threadIdx.x; t < len; t += blockDim.x) sub_seq[dst + t] = seq[src + t];
+}
+
+__global__ void k_subset_scatter(const u32 *__restrict__ list, u64 n, u32 top_n, const u64 *__restrict__ sub_off,
+                                 const u8 *__restrict__ sub_acc, const u32 *__restrict__ sg,
+                                 const i64 *__restrict__ sd, const u32 *__restrict__ sh,
+                                 const u16 *__restrict__ sa, const u8 *__restrict__ sc, u32 *__restrict__ ncand,
+                                 u8 *__restrict__ read_accepted, u32 *__restrict__ st_genome,
+                                 i64 *__restrict__ st_diag, u32 *__restrict__ st_hits, u16 *__restrict__ st_approx,
+                                 u8 *__restrict__ st_accept) {
+    u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    u64 r = list[i];
+    u64 b = sub_off[i], e = sub_off[i + 1];
+    ncand[r] = (u32)(e - b);
+    read_accepted[r] = sub_acc[i];
+    for (u64 c = b; c < e; c++) {
+        u64 o = r * top_n + (c - b);
+        st_genome[o] = sg[c];
+        st_diag[o] = sd[c];
+        st_hits[o] = sh[c];
+        st_approx[o] = sa[c];
+        st_accept[o] = sc[c];
+    }
+}
+
+__global__ void k_add_u64(unsigned long long *__restrict__ dst, const u64 *__restrict__ src, u64 n) {
+    u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] += src[i];
+}
+
+__global__ void k_compact_staged(const u64 *__restrict__ cand_off, u64 n, u32 top_n,
+                                 const u32 *__restrict__ st_genome, const i64 *__restrict__ st_diag,
+                                 const u32 *__restrict__ st_hits, const u16 *__restrict__ st_approx,
+                                 const u8 *__restrict__ st_accept, u32 *__restrict__ genome, i64 *__restrict__ diag,
+                                 u32 *__restrict__ hits, u16 *__restrict__ approx, u8 *__restrict__ accept) {
+    u64 r = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    u64 o = cand_off[r], c = cand_off[r + 1] - o;
+    for (u64 i = 0; i < c; i++) {
+        u64 s = r * top_n + i;
+        genome[o + i] = st_genome[s];
+        diag[o + i] = st_diag[s];
+        hits[o + i] = st_hits[s];
+        approx[o + i] = st_approx[s];
+        accept[o + i] = st_accept[s];
+    }
+}
+
+void classify_fused(const mt_index &ix, const mt_query_params &q, const mt_seqs &reads, ReadBatch &rb,
+                    mt_result &res, Timer &tm, hipStream_t s) {
+    const u64 n = reads.n;
+    const u32 N = q.top_n;
+    if (N == 0 || N > (u32)F_MAX_TOPN) {
+        // Unbounded or long candidate lists: the per-stage kernels handle them.
+        rb.prepare(reads, q.e_mode, q.e_value, s);
+        MT_HIP(hipMemcpyAsync(res.read_E.p, rb.read_E.p, (n ? n : 1) * sizeof(u16), hipMemcpyDeviceToDevice, s));
+        tm.mark("pack");
+        classify_per_stage(ix, q, reads, rb, res, tm, s);
+        return;
+    }
+    rb.n = n;
+    rb.flags.alloc(1);
+    MT_HIP(hipMemsetAsync(rb.flags.p, 0, sizeof(u32), s));
+    if (n == 0) return;
+    k_check_reads<<<grid_for(n, 256), 256, 0, s>>>(reads.offsets, n, reads.total, rb.flags.p);
+    MT_HIP(hipGetLastError());
+    u32 f0 = 0;
+    read_back(s, rb.flags.p, &f0, sizeof f0);
+    check_flags(f0);
+    tm.mark("check");
+
+    DBuf<u32> st_genome(n * N), st_hits(n * N), ncand(n), fb_list(n), fb_count(1);
+    DBuf<i64> st_diag(n * N);
+    DBuf<u16> st_approx(n * N);
+    DBuf<u8> st_accept(n * N);
+    DBuf<unsigned long long> stats(ST_COUNT);
+    MT_HIP(hipMemsetAsync(fb_count.p, 0, sizeof(u32), s));
+    MT_HIP(hipMemsetAsync(stats.p, 0, ST_COUNT * sizeof(u64), s));
+
+    FusedArgs a{};
+    a.seq = (const u8 *)reads.seq;
+    a.off = reads.offsets;
+    a.n = n;
+    a.k = ix.k;
+    a.w = ix.w;
+    a.min_hits = q.min_hits;
+    a.top_n = N;
+    a.e_mode = q.e_mode;
+    a.e_value = q.e_value;
+    a.table = ix.table.p;
+    a.nbuckets = ix.nbuckets;
+    a.occ = ix.occ.p;
+    a.ref_blk = ix.ref.blk_off.p;
+    a.ref_lohi = ix.ref.lohi.p;
+    a.ref_nb = ix.ref.nb.p;
+    a.glen = ix.glen.p;
+    a.has_n = ix.has_n.p;
+    a.taxon = ix.taxon.p;
+    a.st_genome = st_genome.p;
+    a.st_diag = st_diag.p;
+    a.st_hits = st_hits.p;
+    a.st_approx = st_approx.p;
+    a.st_accept = st_accept.p;
+    a.ncand = ncand.p;
+    a.read_accepted = res.read_accepted.p;
+    a.read_E = res.read_E.p;
+    a.uniq = (unsigned long long *)res.uniq.p;
+    a.multi = (unsigned long long *)res.multi.p;
+    a.unmapped = (unsigned long long *)res.unmapped.p;
+    a.fb_list = fb_list.p;
+    a.fb_count = fb_count.p;
+    a.flags = rb.flags.p;
+    a.stats = stats.p;
+    int dev = 0, cus = 0;
+    MT_HIP(hipGetDevice(&dev));
+    MT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    u64 blocks = (n + F_WPB - 1) / F_WPB;
+    u64 cap = (u64)cus * 16;
+    if (blocks > cap) blocks = cap;
+    k_fused<<<(unsigned)blocks, 64 * F_WPB, 0, s>>>(a);
+    MT_HIP(hipGetLastError());
+    tm.mark("fused");
+
+    u32 nfb = 0;
+    u64 st[ST_COUNT];
+    MT_HIP(hipMemcpyAsync(st, stats.p, sizeof st, hipMemcpyDeviceToHost, s));
+    read_back(s, fb_count.p, &nfb, sizeof nfb);
+    u32 f1 = 0;
+    read_back(s, rb.flags.p, &f1, sizeof f1);
+    check_flags(f1);
+    mt_stats &ls = last_stats();
+    ls.fused_reads += st[ST_READS];
+    ls.fused_bases += st[ST_BASES];
+    ls.fused_minimizers += st[ST_MINS];
+    ls.fused_window_blocks += st[ST_WBLOCKS];
+    ls.fused_cands += st[ST_CANDS];
+    ls.n_minimizers += st[ST_MINS];
+
+    if (nfb) {
+        // Reads past the fused kernel's limits: finish them per stage.
+        DBuf<u64> sub_len(nfb), sub_off(nfb + 1);
+        k_subset_lengths<<<grid_for(nfb, 256), 256, 0, s>>>(reads.offsets, fb_list.p, nfb, sub_len.p);
+        MT_HIP(hipGetLastError());
+        scan_u64(sub_len.p, sub_off.p, nfb, s);
+        u64 sub_total = 0;
+        read_back(s, sub_off.p + nfb, &sub_total, sizeof sub_total);
+        DBuf<u8> sub_seq(sub_total);
+        k_subset_copy<<<nfb, 256, 0, s>>>((const u8 *)reads.seq, reads.offsets, fb_list.p, nfb, sub_off.p,
+                                          sub_seq.p);
+        MT_HIP(hipGetLastError());
+        mt_seqs sub{(const char *)sub_seq.p, sub_off.p, nfb, sub_total};
+        mt_result tmp;
+        mt_result_init(tmp, nfb, ix.n_taxa, s);
+        ReadBatch srb;
+        srb.prepare(sub, q.e_mode, q.e_value, s);
+        classify_per_stage(ix, q, sub, srb, tmp, tm, s);
+        u32 f2 = 0;
+        read_back(s, srb.flags.p, &f2, sizeof f2);
+        check_flags(f2);
+        k_subset_scatter<<<grid_for(nfb, 256), 256, 0, s>>>(fb_list.p, nfb, N, tmp.cand_off.p, tmp.read_accepted.p,
+                                                            tmp.genome.p, tmp.diag.p, tmp.hits.p, tmp.approx.p,
+                                                            tmp.accept.p, ncand.p, res.read_accepted.p, st_genome.p,
+                                                            st_diag.p, st_hits.p, st_approx.p, st_accept.p);
+        MT_HIP(hipGetLastError());
+        if (ix.n_taxa) {
+            k_add_u64<<<grid_for(ix.n_taxa, 256), 256, 0, s>>>((unsigned long long *)res.uniq.p, tmp.uniq.p,
+                                                               ix.n_taxa);
+            k_add_u64<<<grid_for(ix.n_taxa, 256), 256, 0, s>>>((unsigned long long *)res.multi.p, tmp.multi.p,
+                                                               ix.n_taxa);
+        }
+        k_add_u64<<<1, 64, 0, s>>>((unsigned long long *)res.unmapped.p, tmp.unmapped.p, 1);
+        MT_HIP(hipGetLastError());
+        tm.mark("fallback");
+    }
+
+    res.alloc_cands(n * N);
+    scan_u32(ncand.p, res.cand_off.p, n, s);
+    k_compact_staged<<<grid_for(n, 256), 256, 0, s>>>(res.cand_off.p, n, N, st_genome.p, st_diag.p, st_hits.p,
+                                                      st_approx.p, st_accept.p, res.genome.p, res.diag.p,
+                                                      res.hits.p, res.approx.p, res.accept.p);
+    MT_HIP(hipGetLastError());
+    tm.mark("compact");
 }
 
 }  // namespace mt

@@ -48,12 +48,16 @@ def run_both(mt, genomes, reads, k, w, max_occ=0, taxon=None, n_taxa=None, mode=
     return got, ref
 
 
-@pytest.mark.parametrize("top_n", [3, 0])
-@pytest.mark.parametrize("E", [0, 3, 7, 15])
-def test_small_workload_bit_exact(mt, top_n, E):
+MODES = [0, 1]  # per-stage, fused
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("top_n", [3, 0, 1])
+@pytest.mark.parametrize("E", [0, 3, 7, 15, 31])
+def test_small_workload_bit_exact(mt, top_n, E, mode):
     gen, reads, p = synth.workload_small()
-    got, ref = run_both(mt, gen.ascii(), reads, p["k"], p["w"], min_hits=3, top_n=top_n, e_value=E)
-    assert_same(got, ref, f"small top_n={top_n} E={E}")
+    got, ref = run_both(mt, gen.ascii(), reads, p["k"], p["w"], min_hits=3, top_n=top_n, e_value=E, mode=mode)
+    assert_same(got, ref, f"small top_n={top_n} E={E} mode={mode}")
     assert len(ref["genome"]) > 9000
 
 
@@ -87,8 +91,9 @@ def _random_case(rnd):
     return genomes, reads
 
 
+@pytest.mark.parametrize("mode", MODES)
 @pytest.mark.parametrize("seed", range(12))
-def test_random_small_cases_bit_exact(mt, seed):
+def test_random_small_cases_bit_exact(mt, seed, mode):
     rnd = random.Random(seed)
     genomes, reads = _random_case(rnd)
     k, w = rnd.randint(3, 16), rnd.randint(1, 12)
@@ -98,45 +103,67 @@ def test_random_small_cases_bit_exact(mt, seed):
              e_value=rnd.choice([0, 2, 50, 120]) if True else 0)
     if q["e_mode"] == 0:
         q["e_value"] = rnd.randint(0, 9)
+    if mode == 1 and rnd.random() < 0.7:
+        q["top_n"] = rnd.randint(1, 4)
     got, ref = run_both(mt, synth.SeqSet.from_list(genomes), synth.SeqSet.from_list(reads), k, w,
-                        max_occ=rnd.choice([0, 0, 4]), taxon=taxon, n_taxa=n_tax, **q)
-    assert_same(got, ref, f"seed {seed}")
+                        max_occ=rnd.choice([0, 0, 4]), taxon=taxon, n_taxa=n_tax, mode=mode, **q)
+    assert_same(got, ref, f"seed {seed} mode {mode}")
 
 
-def test_many_hits_per_read_uses_large_path(mt):
+@pytest.mark.parametrize("mode", MODES)
+def test_many_hits_per_read_uses_large_path(mt, mode):
     """Reads with more seed hits than one block holds in LDS (repetitive reference)."""
     rnd = random.Random(77)
     unit = "".join(rnd.choice("ACGT") for _ in range(40))
     genome = "".join(unit if rnd.random() < 0.9 else rnd.choice("ACGT") * 40 for _ in range(300))
     reads = [genome[i:i + 400] for i in range(0, 4000, 397)]
     got, ref = run_both(mt, synth.SeqSet.from_list([genome, genome[::-1]]), synth.SeqSet.from_list(reads), 8, 3,
-                        min_hits=2, top_n=0, e_value=10)
+                        min_hits=2, top_n=0, e_value=10, mode=mode)
     assert_same(got, ref, "large")
     co = ref["cand_offsets"].astype(np.int64)
     assert np.diff(co).max() > 100
 
 
-def test_long_reads_large_E_bit_exact(mt):
+def test_fused_fallback_for_hit_overflow(mt):
+    """Short reads with more seed hits than the fused kernel holds go to the
+    per-stage kernels and still match the oracle."""
+    rnd = random.Random(78)
+    unit = "".join(rnd.choice("ACGT") for _ in range(30))
+    genome = "".join(unit if rnd.random() < 0.95 else rnd.choice("ACGT") * 30 for _ in range(400))
+    others = ["".join(rnd.choice("ACGT") for _ in range(5000)) for _ in range(3)]
+    reads = [genome[i:i + 150] for i in range(0, 6000, 149)] + [o[i:i + 150] for o in others for i in (0, 999)]
+    got, ref = run_both(mt, synth.SeqSet.from_list([genome] + others), synth.SeqSet.from_list(reads), 9, 3,
+                        min_hits=2, top_n=4, e_value=7, mode=1)
+    assert_same(got, ref, "fused overflow")
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_long_reads_large_E_bit_exact(mt, mode):
     rnd = np.random.default_rng(5)
     gen = synth.make_genomes(rnd, 3, 60_000, 0.5)
-    lens = rnd.integers(1000, 6000, 40)
+    lens = np.concatenate([rnd.integers(1000, 6000, 40), rnd.integers(75, 300, 200)])
     reads, _ = synth.make_reads(rnd, gen, lens, 0.02, 0.03)
-    got, ref = run_both(mt, gen.ascii(), reads, 15, 10, min_hits=3, top_n=3, e_mode=1, e_value=50)
+    got, ref = run_both(mt, gen.ascii(), reads, 15, 10, min_hits=3, top_n=3, e_mode=1, e_value=50, mode=mode)
     assert_same(got, ref, "long")
     assert ref["read_E"].max() >= 100
 
 
-def test_empty_read_set(mt):
+@pytest.mark.parametrize("mode", MODES)
+def test_empty_read_set(mt, mode):
     gen, _, p = synth.workload_small(10)
-    got, ref = run_both(mt, gen.ascii(), synth.SeqSet.from_list([]), p["k"], p["w"])
+    got, ref = run_both(mt, gen.ascii(), synth.SeqSet.from_list([]), p["k"], p["w"], mode=mode)
     assert_same(got, ref, "empty")
 
 
-def test_invalid_byte_rejected(mt):
+@pytest.mark.parametrize("mode", MODES)
+def test_invalid_byte_rejected(mt, mode):
     gen, _, p = synth.workload_small(10)
     ix = mt.Index(gen.ascii(), p["k"], p["w"])
     with pytest.raises(mt.MTError) as e:
-        ix.classify(mt.to_device(synth.SeqSet.from_list(["ACGTACGTAC", "ACGT*ACG"])))
+        ix.classify(mt.to_device(synth.SeqSet.from_list(["ACGTACGTAC", "ACGT*ACG"])), mode=mode)
+    assert e.value.status == -1
+    with pytest.raises(mt.MTError) as e:
+        ix.classify(mt.to_device(synth.SeqSet.from_list(["ACGT" * 20000])), mode=mode)
     assert e.value.status == -1
     with pytest.raises(mt.MTError):
         mt.Index(synth.SeqSet.from_list(["ACGTXACGT"]), 4, 2)
@@ -170,10 +197,14 @@ def test_filter_pairs_against_oracle(mt):
     assert (oap <= pe).mean() > 0.3 and (oap > pe).mean() > 0.05
 
 
-def test_repeat_calls_identical(mt):
+def test_repeat_calls_and_modes_identical(mt):
     gen, reads, p = synth.workload_small(3000)
     ix = mt.Index(gen.ascii(), p["k"], p["w"])
     dr = mt.to_device(reads)
     a = ix.classify(dr).to_host()
     b = ix.classify(dr).to_host()
+    c = ix.classify(dr, mode=1).to_host()
+    d = ix.classify(dr, mode=1).to_host()
     assert_same(a, b, "repeat")
+    assert_same(a, c, "per-stage vs fused")
+    assert_same(c, d, "fused repeat")
