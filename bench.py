@@ -45,11 +45,23 @@ def main() -> int:
     ap.add_argument("--mode", default="fused", choices=["fused", "per_stage"])
     ap.add_argument("--E", type=int, default=7)
     ap.add_argument("--reads", type=int, default=1_000_000)
-    ap.add_argument("--cpu-reads", type=int, default=200_000,
+    ap.add_argument("--cpu-reads", type=int, default=1_000_000,
                     help="reads in the oracle's timed sample (0 skips the CPU baseline)")
     ap.add_argument("--no-timing", action="store_true", help="do not record per-stage HIP events")
     ap.add_argument("--genomes", type=int, default=200, help="genomes of 2.5 Mbp in the database")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (3 times), to scale HBM byte counters")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        import torch
+        nbytes = args.calibrate_copy << 20
+        src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": nbytes, "copies": 3}), flush=True)
+        return 0
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

@@ -272,11 +272,9 @@ struct FilterArgs {
     const u64x2 *read_lohi;
     const u64 *read_nb;
     u64 n_genomes;
-    const u64 *ref_blk;
+    const GenomeMeta *meta;
     const u64x2 *ref_lohi;
     const u64 *ref_nb;
-    const u64 *glen;
-    const u32 *has_n;
     u16 *approx;
     u8 *accept;
     u32 *flags;
@@ -312,10 +310,11 @@ __global__ __launch_bounds__(256) void k_filter(FilterArgs a) {
     v.qlohi = a.read_lohi + a.read_blk[r];
     v.qnb = a.read_nb + a.read_blk[r];
     v.m = (int)(a.read_off[r + 1] - a.read_off[r]);
-    v.rlohi = a.ref_lohi + a.ref_blk[g];
-    v.rnb = a.ref_nb + a.ref_blk[g];
-    v.L = (i64)a.glen[g];
-    v.has_n = a.has_n[g] != 0;
+    GenomeMeta gm = a.meta[g];
+    v.rlohi = a.ref_lohi + gm.blk;
+    v.rnb = a.ref_nb + gm.blk;
+    v.L = (i64)gm.len;
+    v.has_n = meta_has_n(gm);
     v.diag = a.pair_diag[p];
     int approx = obstacle_walk<G>(v, E, lane);
     if (lane == 0) {
@@ -485,11 +484,9 @@ void classify_per_stage(const mt_index &ix, const mt_query_params &q, const mt_s
     fa.read_lohi = rb.planes.lohi.p;
     fa.read_nb = rb.planes.nb.p;
     fa.n_genomes = ix.n_genomes;
-    fa.ref_blk = ix.ref.blk_off.p;
+    fa.meta = ix.meta.p;
     fa.ref_lohi = ix.ref.lohi.p;
     fa.ref_nb = ix.ref.nb.p;
-    fa.glen = ix.glen.p;
-    fa.has_n = ix.has_n.p;
     fa.approx = res.approx.p;
     fa.accept = res.accept.p;
     fa.flags = rb.flags.p;
@@ -687,11 +684,9 @@ extern "C" int mt_filter_pairs(const mt_index *index, const mt_seqs *reads, cons
         fa.read_lohi = rb.planes.lohi.p;
         fa.read_nb = rb.planes.nb.p;
         fa.n_genomes = index->n_genomes;
-        fa.ref_blk = index->ref.blk_off.p;
+        fa.meta = index->meta.p;
         fa.ref_lohi = index->ref.lohi.p;
         fa.ref_nb = index->ref.nb.p;
-        fa.glen = index->glen.p;
-        fa.has_n = index->has_n.p;
         fa.approx = approx_out;
         fa.accept = accept_out;
         fa.flags = rb.flags.p;

@@ -142,13 +142,37 @@ __device__ inline u64 mismatch(const Bits64 &q, const Bits64 &w) {
     return (q.lo ^ w.lo) | (q.hi ^ w.hi) | q.nb | w.nb;
 }
 
-// Max over the G lanes of a group (G a power of two <= 64).
+// Max over the G lanes of an aligned group (G = 16, 32 or 64).  Within a
+// 16-lane DPP row the max is spread by rotating the row by 1, 2, 4 and 8
+// lanes (every lane ends up with the row max); wider groups then combine the
+// row maxima read from lanes 0, 16, 32 and 48.  Every lane of the group must
+// be active (the rows of inactive groups are read but never used).
 template <int G>
 __device__ inline int group_max(int v) {
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, G));
+    static_assert(G == 16 || G == 32 || G == 64, "group of 16, 32 or 64 lanes");
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x121, 0xF, 0xF, false));  // row_ror:1
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x122, 0xF, 0xF, false));  // row_ror:2
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x124, 0xF, 0xF, false));  // row_ror:4
+    v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x128, 0xF, 0xF, false));  // row_ror:8
+    if (G > 16) {
+        // row maxima sit in lanes 0, 16, 32 and 48; combine them per group
+        int r0 = __builtin_amdgcn_readlane(v, 0), r1 = __builtin_amdgcn_readlane(v, 16);
+        int r2 = __builtin_amdgcn_readlane(v, 32), r3 = __builtin_amdgcn_readlane(v, 48);
+        if (G == 64) return max(max(r0, r1), max(r2, r3));
+        return (threadIdx.x & 32) ? max(r2, r3) : max(r0, r1);
+    }
     return v;
 }
+
+// Per-genome record, one 16-byte load: first plane block, length, taxon and
+// whether the genome holds an N (top bit).
+struct alignas(16) GenomeMeta {
+    u64 blk;
+    u32 len;
+    u32 taxon_n;
+};
+__host__ __device__ inline u32 meta_taxon(const GenomeMeta &m) { return m.taxon_n & 0x7fffffffu; }
+__host__ __device__ inline bool meta_has_n(const GenomeMeta &m) { return (m.taxon_n >> 31) != 0; }
 
 // Read planes + reference planes of one (read, location) pair.
 struct PairView {

@@ -39,6 +39,9 @@ constexpr int F_MAX_M = 256;     // longest read the fused kernel takes
 constexpr int F_HIT_CAP = 256;   // seed hits per read held in LDS
 constexpr int F_MAX_E = 31;      // 2E + 1 rows fit one wavefront
 constexpr int F_MAX_TOPN = 4;
+constexpr int F_QCAP = 4;        // queued (read, candidate) pairs per wave: one per 16-lane group
+constexpr int F_PCAP = 8;        // reads per wave waiting for their filter results
+constexpr int F_WORDS = F_MAX_M / 16 + 2;  // 2-bit stream words (16 bases per word) + padding
 
 enum : u32 { ST_READS, ST_BASES, ST_MINS, ST_WBLOCKS, ST_CANDS, ST_COUNT };
 
@@ -50,12 +53,9 @@ struct FusedArgs {
     const u64x2 *table;
     u64 nbuckets;
     const u64 *occ;
-    const u64 *ref_blk;
+    const GenomeMeta *meta;
     const u64x2 *ref_lohi;
     const u64 *ref_nb;
-    const u64 *glen;
-    const u32 *has_n;
-    const u32 *taxon;
     // staging: top_n slots per read
     u32 *st_genome;
     i64 *st_diag;
@@ -72,6 +72,25 @@ struct FusedArgs {
     unsigned long long *stats;
 };
 
+// A read whose candidates wait in the filter queue (per-wave LDS).
+struct PendRead {
+    u64 plane[12];   // lo[0..3], hi[0..3], nb[0..3] of the read
+    u64 r;
+    u32 nc, left;    // candidates, candidates not yet filtered
+    u16 E, m;
+    u16 apx[F_MAX_TOPN];
+    u32 tax[F_MAX_TOPN];
+};
+
+// One queued (read, candidate) pair.
+struct QEntry {
+    u64 key;   // (genome, diagonal)
+    u32 out;   // staging slot: read * top_n + candidate index
+    u32 hits;
+    u8 pend;   // PendRead slot
+    u8 cidx;   // candidate index within the read
+};
+
 __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
@@ -85,24 +104,30 @@ __device__ inline u32 lanes_below(u64 m, int lane) {
     return (u32)__popcll(lane ? m & ((~0ull) >> (64 - lane)) : 0ull);
 }
 
-// mm[w] for a wave-uniform or per-lane word index w in 0..4 (mm[4] is all ones).
-__device__ inline u64 pick5(const u64 (&mm)[5], int w) {
-    u64 v = mm[4];
-    v = w == 3 ? mm[3] : v;
-    v = w == 2 ? mm[2] : v;
-    v = w == 1 ? mm[1] : v;
-    v = w == 0 ? mm[0] : v;
+// The mismatch words of one band row over the whole read (bases 0..255).
+// Kept as four scalars, never as an array: a dynamically indexed array would
+// be placed in scratch memory.  Word 4 and beyond read as all ones.
+struct RowBits {
+    u64 w0, w1, w2, w3;
+};
+
+__device__ inline u64 row_word(RowBits r, int w) {
+    u64 v = ~0ull;
+    v = w == 3 ? r.w3 : v;
+    v = w == 2 ? r.w2 : v;
+    v = w == 1 ? r.w1 : v;
+    v = w == 0 ? r.w0 : v;
     return v;
 }
 
-// Obstacle-free run of a row from column j, from the row's mismatch words
-// (bits past the read's end are set, so the run stops by the end).
-__device__ inline int reg_run(const u64 (&mm)[5], int j) {
+// Obstacle-free run of a row from column j (bits past the read's end are
+// set, so the run stops by the end).
+__device__ inline int reg_run(RowBits r, int j) {
     int w = j >> 6;
     u32 s = (u32)j & 63u;
     int run = 0;
     for (;;) {
-        u64 v = funnel(pick5(mm, w), pick5(mm, w + 1), s);
+        u64 v = funnel(row_word(r, w), row_word(r, w + 1), s);
         if (v) return run + (int)__builtin_ctzll(v);
         run += 64;
         w += 1;
@@ -127,140 +152,311 @@ __device__ inline u64 bucket_lookup(const u64x2 *__restrict__ table, u64 nbucket
     }
 }
 
-template <int G>
-__device__ inline int filter_group(const FusedArgs &a, const u64 (&Qlo)[5], const u64 (&Qhi)[5],
-                                   const u64 (&Qn)[5], int m, int E, u32 g, i64 diag, int lane_g) {
-    u64 mm[5];
-    mm[4] = ~0ull;
-    int rows = 2 * E + 1;
-    if (lane_g < rows) {
-        int d = lane_g - E;
-        const u64x2 *rl = a.ref_lohi + a.ref_blk[g];
-        const u64 *rn = a.ref_nb + a.ref_blk[g];
-        i64 L = (i64)a.glen[g];
-        bool hn = a.has_n[g] != 0;
+// k-mer value at position i from the big-endian 2-bit stream (base j at bits
+// 30 - 2(j mod 16) of word j / 16): bits [2i, 2i + 2k) of the stream.
+__device__ inline u64 stream_kmer(const u32 *st, int i, u32 k) {
+    int w = i >> 4;
+    u32 s = 2u * (u32)(i & 15);
+    u64 hi = ((u64)st[w] << 32) | st[w + 1];
+    u64 y = (hi << s) | (((u64)st[w + 2] << s) >> 32);
+    return y >> (64 - 2 * k);
+}
+
+// Smallest hash of window [ws, ws + W) (leftmost on ties), all W hashes read
+// before the compare chain; -1 when every hash reads ~0.  Unrolled for
+// W <= 12 (the usual minimizer windows); wider windows take a loop.
+template <int W>
+__device__ inline int window_argmin(const u64 *hh, int ws) {
+    u64 v[W];
 #pragma unroll
-        for (int q = 0; q < 4; q++) {
-            Bits64 wv = fetch_ref(rl, rn, L, hn, diag + d + 64 * q);
-            mm[q] = (Qlo[q] ^ wv.lo) | (Qhi[q] ^ wv.hi) | Qn[q] | wv.nb;
+    for (int t = 0; t < W; t++) v[t] = hh[ws + t];
+    u64 bh = ~0ull;
+    int bt = -1;  // offset of the best so far (a constant per step)
+#pragma unroll
+    for (int t = 0; t < W; t++)
+        if (v[t] < bh) {
+            bh = v[t];
+            bt = t;
         }
-    } else {
-#pragma unroll
-        for (int q = 0; q < 4; q++) mm[q] = ~0ull;
+    return bt < 0 ? -1 : ws + bt;
+}
+
+__device__ inline int window_argmin_any(const u64 *hh, int ws, int win) {
+    switch (win) {
+#define MT_WIN(W) \
+    case W:       \
+        return window_argmin<W>(hh, ws);
+        MT_WIN(1) MT_WIN(2) MT_WIN(3) MT_WIN(4) MT_WIN(5) MT_WIN(6) MT_WIN(7) MT_WIN(8)
+        MT_WIN(9) MT_WIN(10) MT_WIN(11) MT_WIN(12)
+#undef MT_WIN
+    default: {
+        u64 bh = ~0ull;
+        int best = -1;
+        for (int t = 0; t < win; t++) {
+            u64 hv = hh[ws + t];
+            if (hv < bh) {
+                bh = hv;
+                best = ws + t;
+            }
+        }
+        return best;
+    }
+    }
+}
+
+// Filters the first qn queued pairs, one pair per group of G lanes (lane_g <
+// 2E+1 owns band row d = lane_g - E): the row's mismatch words over the read
+// come from the read planes (LDS) and 64-base reference fetches, then the
+// obstacle walk runs on registers.  Results go to the staging slot and to the
+// pair's pending read.
+template <int G>
+__device__ inline void filter_batch(const FusedArgs &a, const QEntry *q, int qn, PendRead *pend, int lane) {
+    const int gi = lane / G, lane_g = lane % G;
+    if (gi >= qn) return;
+    const QEntry e = q[gi];
+    PendRead &pr = pend[e.pend];
+    const int E = pr.E, m = pr.m;
+    const u32 g = key_genome(e.key);
+    const i64 diag = key_diag(e.key);
+    const GenomeMeta gm = a.meta[g];
+    RowBits row{~0ull, ~0ull, ~0ull, ~0ull};
+    if (lane_g < 2 * E + 1) {
+        const i64 base = diag + (lane_g - E);
+        const u64x2 *rl = a.ref_lohi + gm.blk;
+        const u64 *rn = a.ref_nb + gm.blk;
+        const i64 L = (i64)gm.len;
+        const bool hn = meta_has_n(gm);
+        Bits64 w0 = fetch_ref(rl, rn, L, hn, base);
+        Bits64 w1 = fetch_ref(rl, rn, L, hn, base + 64);
+        Bits64 w2 = fetch_ref(rl, rn, L, hn, base + 128);
+        Bits64 w3 = fetch_ref(rl, rn, L, hn, base + 192);
+        row.w0 = (pr.plane[0] ^ w0.lo) | (pr.plane[4] ^ w0.hi) | pr.plane[8] | w0.nb;
+        row.w1 = (pr.plane[1] ^ w1.lo) | (pr.plane[5] ^ w1.hi) | pr.plane[9] | w1.nb;
+        row.w2 = (pr.plane[2] ^ w2.lo) | (pr.plane[6] ^ w2.hi) | pr.plane[10] | w2.nb;
+        row.w3 = (pr.plane[3] ^ w3.lo) | (pr.plane[7] ^ w3.hi) | pr.plane[11] | w3.nb;
     }
     int j = 0, c = 0;
     for (;;) {
-        int run = reg_run(mm, j);
-        run = group_max<G>(run);
+        int run = group_max<G>(reg_run(row, j));
         j += run;
         if (j >= m) break;
         c += 1;
         if (c > E) break;
         j += 1;
     }
-    return c < E + 1 ? c : E + 1;
+    const int ap = c < E + 1 ? c : E + 1;
+    if (lane_g == 0) {
+        a.st_genome[e.out] = g;
+        a.st_diag[e.out] = diag;
+        a.st_hits[e.out] = e.hits;
+        a.st_approx[e.out] = (u16)ap;
+        a.st_accept[e.out] = ap <= E;
+        pr.apx[e.cidx] = (u16)ap;
+        pr.tax[e.cidx] = meta_taxon(gm);
+    }
 }
 
-__global__ __launch_bounds__(64 * F_WPB) void k_fused(FusedArgs a) {
-    __shared__ u64 sh_h[F_WPB][F_MAX_M];     // k-mer hashes; later candidate keys
-    __shared__ u64 sh_x[F_WPB][F_MAX_M];     // k-mer values
+// Read accept flag and per-taxon counts of a read whose candidates are all
+// filtered: the distinct taxa of its accepted candidates with the smallest
+// count; one taxon is unique, several are multi-mapped.
+__device__ inline void finalize_read(const FusedArgs &a, const PendRead &pr) {
+    const int nc = (int)pr.nc, E = pr.E;
+    int best = 0x7fffffff;
+    for (int c = 0; c < nc; c++)
+        if (pr.apx[c] <= E && pr.apx[c] < best) best = pr.apx[c];
+    if (best == 0x7fffffff) {
+        a.read_accepted[pr.r] = 0;
+        atomicAdd(a.unmapped, 1ull);
+        return;
+    }
+    a.read_accepted[pr.r] = 1;
+    int nt = 0;
+    u32 first = 0;
+    for (int c = 0; c < nc; c++) {
+        if (pr.apx[c] != best) continue;
+        bool seen = false;
+        for (int b = 0; b < c; b++) seen |= pr.apx[b] == best && pr.tax[b] == pr.tax[c];
+        if (seen) continue;
+        if (nt == 0) first = pr.tax[c];
+        nt++;
+    }
+    if (nt == 1) {
+        atomicAdd(&a.uniq[first], 1ull);
+        return;
+    }
+    for (int c = 0; c < nc; c++) {
+        if (pr.apx[c] != best) continue;
+        bool seen = false;
+        for (int b = 0; b < c; b++) seen |= pr.apx[b] == best && pr.tax[b] == pr.tax[c];
+        if (!seen) atomicAdd(&a.multi[pr.tax[c]], 1ull);
+    }
+}
+
+// Runs the queued filter batch (group size by the queue's class), then
+// finalizes every pending read whose last candidate it filtered.  Returns the
+// new set of used pending slots.
+__device__ inline u32 flush_queue(const FusedArgs &a, QEntry *q, int &qn, int qG, PendRead *pend, u32 used,
+                                  int lane) {
+    if (qn > 0) {
+        if (qG == 16)
+            filter_batch<16>(a, q, qn, pend, lane);
+        else if (qG == 32)
+            filter_batch<32>(a, q, qn, pend, lane);
+        else
+            filter_batch<64>(a, q, qn, pend, lane);
+        wave_sync();
+        if (lane == 0)
+            for (int i = 0; i < qn; i++) pend[q[i].pend].left -= 1;
+        wave_sync();
+        qn = 0;
+    }
+    bool done = lane < F_PCAP && ((used >> lane) & 1u) && pend[lane].left == 0;
+    if (done) finalize_read(a, pend[lane]);
+    u32 fin = (u32)ballot64(done);
+    wave_sync();
+    return used & ~fin;
+}
+
+// The bytes of one read, one per lane for each 64-base round (reads longer
+// than the kernel takes are not loaded).
+struct ReadBytes {
+    u64 beg;
+    int m;
+    u32 b[4];
+};
+
+__device__ inline void issue_read_bytes(const FusedArgs &a, u64 r, int lane, ReadBytes &rb) {
+    rb.beg = a.off[r];
+    rb.m = (int)(a.off[r + 1] - rb.beg);
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        int i = 64 * q + lane;
+        rb.b[q] = (rb.m <= F_MAX_M && i < rb.m) ? (u32)a.seq[rb.beg + i] : (u32)'N';
+    }
+}
+
+// Four wavefronts per SIMD: the kernel is bound by memory latency as much as
+// by VALU issue, and the register budget of 128 is met with one spilled value.
+__global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_fused(FusedArgs a) {
+    __shared__ u64 sh_h[F_WPB][F_MAX_M];     // k-mer hashes (~0 when invalid); later candidate keys
     __shared__ u64 sh_hit[F_WPB][F_HIT_CAP]; // (genome, diagonal) keys of the seed hits
     __shared__ u32 sh_cnt[F_WPB][F_HIT_CAP]; // candidate hit counts
     __shared__ u16 sh_pos[F_WPB][F_MAX_M];   // minimizer positions
     __shared__ u8 sh_pick[F_WPB][F_MAX_M];   // window picks
     __shared__ u8 sh_ok[F_WPB][F_MAX_M];     // k-mer has no N
+    __shared__ u32 sh_st[F_WPB][F_WORDS];    // big-endian 2-bit stream of the read
     __shared__ u32 sh_sel[F_WPB][F_MAX_TOPN];
-    __shared__ u16 sh_apx[F_WPB][F_MAX_TOPN];
+    __shared__ QEntry sh_q[F_WPB][F_QCAP];
+    __shared__ PendRead sh_pend[F_WPB][F_PCAP];
+    __shared__ u64 sh_stats[F_WPB][ST_COUNT];
 
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     u64 *hh = sh_h[wid];
-    u64 *xx = sh_x[wid];
     u64 *hits = sh_hit[wid];
     u32 *cnts = sh_cnt[wid];
     u16 *mpos = sh_pos[wid];
     u8 *pick = sh_pick[wid];
     u8 *okk = sh_ok[wid];
+    u32 *stream = sh_st[wid];
     u32 *sel = sh_sel[wid];
-    u16 *apx = sh_apx[wid];
+    QEntry *queue = sh_q[wid];
+    PendRead *pend = sh_pend[wid];
+    u64 *wst = sh_stats[wid];
+    if (lane < ST_COUNT) wst[lane] = 0;
 
     const u32 k = a.k, T = a.min_hits ? a.min_hits : 1u, N = a.top_n;
     const u64 kmask = (1ull << k) - 1;
-    u64 st_reads = 0, st_bases = 0, st_mins = 0, st_wblk = 0, st_cands = 0;
+    const u64 stride = (u64)gridDim.x * F_WPB;
     u32 wflags = 0;
+    int qn = 0, qG = 16;  // queued pairs and their group size
+    u32 used = 0;         // pending-read slots in use
 
-    for (u64 r = (u64)blockIdx.x * F_WPB + wid; r < a.n; r += (u64)gridDim.x * F_WPB) {
-        const u64 beg = a.off[r];
-        const int m = (int)(a.off[r + 1] - beg);
-        const u64 mm_ = (u64)m;
+    u64 r = (u64)blockIdx.x * F_WPB + wid;
+    ReadBytes cur;
+    if (r < a.n) issue_read_bytes(a, r, lane, cur);
+    for (; r < a.n; r += stride) {
+        const u64 rn = r + stride;
+        const int m = cur.m;
         u64 Ewide = a.e_mode == MT_E_FIXED ? a.e_value
-                    : a.e_mode == MT_E_CEIL_PERMILLE ? (mm_ * a.e_value + 999) / 1000
-                                                     : (mm_ * a.e_value) / 1000;
+                    : a.e_mode == MT_E_CEIL_PERMILLE ? ((u64)m * a.e_value + 999) / 1000
+                                                     : ((u64)m * a.e_value) / 1000;
         if (Ewide > 65534) wflags |= ERR_E_TOO_LARGE;
         const int E = Ewide > 65535 ? 65535 : (int)Ewide;
         if (lane == 0) a.read_E[r] = (u16)E;
         if (m > F_MAX_M || E > F_MAX_E) {
             if (lane == 0) a.fb_list[atomicAdd(a.fb_count, 1u)] = (u32)r;
+            if (rn < a.n) issue_read_bytes(a, rn, lane, cur);
             continue;
         }
 
-        // 1. bit planes of the read (bases past m are N)
-        u64 Qlo[5], Qhi[5], Qn[5];
+        // 1. bit planes of the read (bases past m are N), written straight into
+        // a free pending-read slot, and the read's big-endian 2-bit stream
+        const int slot = __builtin_ctz(~used);
+        PendRead &pr = pend[slot];
+        if (lane < F_WORDS) stream[lane] = 0;
         bool bad = false;
+        wave_sync();
 #pragma unroll
         for (int q = 0; q < 4; q++) {
             int i = 64 * q + lane;
-            u32 c = i < m ? base_code(a.seq[beg + i]) : 4u;
+            u32 c = i < m ? base_code(cur.b[q]) : 4u;
             bad |= c == 5;
-            Qlo[q] = ballot64(c < 4 && (c & 1u));
-            Qhi[q] = ballot64(c < 4 && (c & 2u));
-            Qn[q] = ballot64(c >= 4);
+            u64 lo = ballot64(c < 4 && (c & 1u));
+            u64 hi = ballot64(c < 4 && (c & 2u));
+            u64 nb = ballot64(c >= 4);
+            if (lane == 0) {
+                pr.plane[q] = lo;
+                pr.plane[4 + q] = hi;
+                pr.plane[8 + q] = nb;
+            }
+            if (c < 4 && c > 0) atomicOr(&stream[i >> 4], c << (30 - 2 * (i & 15)));
         }
-        Qlo[4] = Qhi[4] = 0;
-        Qn[4] = ~0ull;
+        // the next read's offsets (their bytes are requested after the probes)
+        u64 nbeg = 0, nend = 0;
+        if (rn < a.n) {
+            nbeg = a.off[rn];
+            nend = a.off[rn + 1];
+        }
         if (ballot64(bad)) {
             wflags |= ERR_BAD_BYTE;
+            if (rn < a.n) issue_read_bytes(a, rn, lane, cur);
             continue;
         }
+        wave_sync();
 
-        // 2. k-mer values and hashes
+        // 2. k-mer hashes (~0 for k-mers with an N)
         const int nk = m - (int)k + 1;
 #pragma unroll
         for (int q = 0; q < 4; q++) {
             int i = 64 * q + lane;
             bool ok = false;
             if (i < nk) {
-                u64 lo = funnel(Qlo[q], Qlo[q + 1], (u32)lane);
-                u64 hi = funnel(Qhi[q], Qhi[q + 1], (u32)lane);
-                u64 nb = funnel(Qn[q], Qn[q + 1], (u32)lane);
-                u64 x = kmer_value(lo, hi, k);
-                xx[i] = x;
-                hh[i] = mix64(x);
+                u64 nb = funnel(pr.plane[8 + q], q < 3 ? pr.plane[9 + q] : ~0ull, (u32)lane);
                 ok = (nb & kmask) == 0;
+                hh[i] = ok ? mix64(stream_kmer(stream, i, k)) : ~0ull;
             }
             okk[i] = ok;
             pick[i] = 0;
         }
         wave_sync();
 
-        // 3. window minima
+        // 3. window minima: an invalid k-mer reads as ~0 and never wins unless
+        // the whole window is ~0, which the slow path resolves exactly.
         int nmin = 0;
         if (nk > 0) {
             const int win = nk < (int)a.w ? nk : (int)a.w;
             const int nws = nk - win + 1;
-#pragma unroll
+#pragma unroll 1
             for (int q = 0; q < 4; q++) {
                 int ws = 64 * q + lane;
                 if (ws < nws) {
-                    int best = -1;
-                    u64 bh = 0;
-                    for (int i = ws; i < ws + win; i++) {
-                        if (!okk[i]) continue;
-                        u64 hv = hh[i];
-                        if (best < 0 || hv < bh) {
-                            best = i;
-                            bh = hv;
-                        }
-                    }
+                    int best = window_argmin_any(hh, ws, win);
+                    if (best < 0)  // every hash read ~0: leftmost valid k-mer, if any
+                        for (int t = 0; t < win; t++)
+                            if (okk[ws + t]) {
+                                best = ws + t;
+                                break;
+                            }
                     if (best >= 0) pick[best] = 1;
                 }
             }
@@ -286,10 +482,9 @@ __global__ __launch_bounds__(64 * F_WPB) void k_fused(FusedArgs a) {
             u32 cnt = 0;
             if (j < nmin) {
                 p = mpos[j];
-                v = bucket_lookup(a.table, a.nbuckets, xx[p]);
+                v = bucket_lookup(a.table, a.nbuckets, stream_kmer(stream, p, k));
                 cnt = v == SLOT_NONE ? 0u : slot_count(v);
             }
-            // exclusive prefix of cnt over the wave
             u32 pre = cnt;
 #pragma unroll
             for (int o = 1; o < 64; o <<= 1) {
@@ -316,13 +511,26 @@ __global__ __launch_bounds__(64 * F_WPB) void k_fused(FusedArgs a) {
             }
             H += (int)tot;
         }
+        // the next read's bytes arrive while this one is counted and filtered
+        ReadBytes nxt;
+        if (rn < a.n) {
+            nxt.beg = nbeg;
+            nxt.m = (int)(nend - nbeg);
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                int i = 64 * q + lane;
+                nxt.b[q] = (nxt.m <= F_MAX_M && i < nxt.m) ? (u32)a.seq[nbeg + i] : (u32)'N';
+            }
+        }
         if (overflow) {
             if (lane == 0) a.fb_list[atomicAdd(a.fb_count, 1u)] = (u32)r;
+            cur = nxt;
+            wave_sync();
             continue;
         }
         wave_sync();
 
-        // 5. hits per location, candidates, top_n by rank
+        // 5. hits per location (8 keys read per batch), candidates, top_n by rank
         int C = 0;
         for (int t0 = 0; t0 < H; t0 += 64) {
             int j = t0 + lane;
@@ -332,19 +540,24 @@ __global__ __launch_bounds__(64 * F_WPB) void k_fused(FusedArgs a) {
             if (j < H) {
                 key = hits[j];
                 bool first = true;
-                for (int u = 0; u < H; u++) {
-                    u64 ku = hits[u];
-                    bool eq = ku == key;
-                    c += eq;
-                    first &= !(eq && u < j);
+                for (int u0 = 0; u0 < H; u0 += 8) {
+                    u64 kb[8];
+#pragma unroll
+                    for (int t = 0; t < 8; t++) kb[t] = u0 + t < H ? hits[u0 + t] : ~0ull;
+#pragma unroll
+                    for (int t = 0; t < 8; t++) {
+                        bool eq = kb[t] == key;
+                        c += eq;
+                        first &= !(eq && u0 + t < j);
+                    }
                 }
                 is_c = first && c >= T;
             }
             u64 cm = ballot64(is_c);
             if (is_c) {
-                int s = C + (int)lanes_below(cm, lane);
-                hh[s] = key;
-                cnts[s] = c;
+                int s2 = C + (int)lanes_below(cm, lane);
+                hh[s2] = key;
+                cnts[s2] = c;
             }
             C += __popcll(cm);
         }
@@ -365,89 +578,53 @@ __global__ __launch_bounds__(64 * F_WPB) void k_fused(FusedArgs a) {
         }
         wave_sync();
 
-        // 6. filter the kept candidates
-        const int rows = 2 * E + 1;
-        const int G = rows <= 16 ? 16 : rows <= 32 ? 32 : 64;
-        const int per = 64 / G;
-        for (int c0 = 0; c0 < nc; c0 += per) {
-            int cidx = c0 + lane / G;
-            int lane_g = lane % G;
-            if (cidx < nc) {
-                u64 key = hh[sel[cidx]];
-                u32 g = key_genome(key);
-                i64 diag = key_diag(key);
-                int ap;
-                if (G == 16)
-                    ap = filter_group<16>(a, Qlo, Qhi, Qn, m, E, g, diag, lane_g);
-                else if (G == 32)
-                    ap = filter_group<32>(a, Qlo, Qhi, Qn, m, E, g, diag, lane_g);
-                else
-                    ap = filter_group<64>(a, Qlo, Qhi, Qn, m, E, g, diag, lane_g);
-                if (lane_g == 0) {
-                    apx[cidx] = (u16)ap;
-                    u64 o = r * N + (u64)cidx;
-                    a.st_genome[o] = g;
-                    a.st_diag[o] = diag;
-                    a.st_hits[o] = cnts[sel[cidx]];
-                    a.st_approx[o] = (u16)ap;
-                    a.st_accept[o] = ap <= E;
-                }
-            }
-        }
-        wave_sync();
-
-        // 7. read accept flag and taxon counts
-        if (lane == 0) {
-            a.ncand[r] = (u32)nc;
-            int best = 0x7fffffff;
-            for (int c = 0; c < nc; c++)
-                if (apx[c] <= E && apx[c] < best) best = apx[c];
-            if (best == 0x7fffffff) {
+        // 6. queue the kept candidates for batched filtering
+        if (lane == 0) a.ncand[r] = (u32)nc;
+        if (nc == 0) {
+            if (lane == 0) {
                 a.read_accepted[r] = 0;
                 atomicAdd(a.unmapped, 1ull);
-            } else {
-                // distinct taxa of the accepted candidates with the best count
-                a.read_accepted[r] = 1;
-                int nt = 0;
-                u32 first = 0;
-                for (int c = 0; c < nc; c++) {
-                    if (apx[c] != best) continue;
-                    u32 t = a.taxon[key_genome(hh[sel[c]])];
-                    bool seen = false;
-                    for (int b = 0; b < c; b++)
-                        seen |= apx[b] == best && a.taxon[key_genome(hh[sel[b]])] == t;
-                    if (seen) continue;
-                    if (nt == 0) first = t;
-                    nt++;
+            }
+        } else {
+            const int rows = 2 * E + 1;
+            const int G = rows <= 16 ? 16 : rows <= 32 ? 32 : 64;
+            used |= 1u << slot;
+            if (lane == 0) {
+                pr.r = r;
+                pr.nc = (u32)nc;
+                pr.left = (u32)nc;
+                pr.E = (u16)E;
+                pr.m = (u16)m;
+            }
+            wave_sync();
+            // one flush site: the queue is flushed when it is full or holds
+            // pairs of another group size
+            for (int c = 0; c < nc; c++) {
+                if (qn > 0 && (qn == 64 / qG || qG != G)) used = flush_queue(a, queue, qn, qG, pend, used, lane);
+                qG = G;
+                if (lane == 0) {
+                    u32 si = sel[c];
+                    queue[qn] = QEntry{hh[si], (u32)(r * N + (u64)c), cnts[si], (u8)slot, (u8)c};
                 }
-                if (nt == 1) {
-                    atomicAdd(&a.uniq[first], 1ull);
-                } else {
-                    for (int c = 0; c < nc; c++) {
-                        if (apx[c] != best) continue;
-                        u32 t = a.taxon[key_genome(hh[sel[c]])];
-                        bool seen = false;
-                        for (int b = 0; b < c; b++)
-                            seen |= apx[b] == best && a.taxon[key_genome(hh[sel[b]])] == t;
-                        if (!seen) atomicAdd(&a.multi[t], 1ull);
-                    }
-                }
+                qn += 1;
+                wave_sync();
             }
         }
-        st_reads += 1;
-        st_bases += (u64)m;
-        st_mins += (u64)nmin;
-        st_cands += (u64)nc;
-        st_wblk += (u64)nc * (u64)((m + 2 * E + 63) / 64);
+        if (lane == 0) {  // work counts, kept in LDS to spare registers
+            wst[ST_READS] += 1;
+            wst[ST_BASES] += (u64)m;
+            wst[ST_MINS] += (u64)nmin;
+            wst[ST_CANDS] += (u64)nc;
+            wst[ST_WBLOCKS] += (u64)nc * (u64)((m + 2 * E + 63) / 64);
+        }
+        cur = nxt;
         wave_sync();
     }
+    used = flush_queue(a, queue, qn, qG, pend, used, lane);
     if (lane == 0) {
+        if (used) wflags |= ERR_INTERNAL;  // every queued read is finalized by now
         if (wflags) atomicOr(a.flags, wflags);
-        atomicAdd(&a.stats[ST_READS], st_reads);
-        atomicAdd(&a.stats[ST_BASES], st_bases);
-        atomicAdd(&a.stats[ST_MINS], st_mins);
-        atomicAdd(&a.stats[ST_WBLOCKS], st_wblk);
-        atomicAdd(&a.stats[ST_CANDS], st_cands);
+        for (int i = 0; i < ST_COUNT; i++) atomicAdd(&a.stats[i], wst[i]);
     }
 }
 
@@ -567,12 +744,9 @@ void classify_fused(const mt_index &ix, const mt_query_params &q, const mt_seqs 
     a.table = ix.table.p;
     a.nbuckets = ix.nbuckets;
     a.occ = ix.occ.p;
-    a.ref_blk = ix.ref.blk_off.p;
+    a.meta = ix.meta.p;
     a.ref_lohi = ix.ref.lohi.p;
     a.ref_nb = ix.ref.nb.p;
-    a.glen = ix.glen.p;
-    a.has_n = ix.has_n.p;
-    a.taxon = ix.taxon.p;
     a.st_genome = st_genome.p;
     a.st_diag = st_diag.p;
     a.st_hits = st_hits.p;

@@ -24,9 +24,14 @@
 
 namespace mt {
 
-__global__ void k_genome_meta(const u64 *__restrict__ off, u64 n, u64 *__restrict__ glen) {
+__global__ void k_genome_meta(const u64 *__restrict__ off, u64 n, const u64 *__restrict__ blk_off,
+                              const u32 *__restrict__ has_n, const u32 *__restrict__ taxon, u64 *__restrict__ glen,
+                              GenomeMeta *__restrict__ meta) {
     u64 g = (u64)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g < n) glen[g] = off[g + 1] - off[g];
+    if (g >= n) return;
+    u64 len = off[g + 1] - off[g];
+    glen[g] = len;
+    meta[g] = GenomeMeta{blk_off[g], (u32)len, taxon[g] | (has_n[g] ? 0x80000000u : 0u)};
 }
 
 __global__ void k_insert(const u64 *__restrict__ xs, u64 n, u64x2 *__restrict__ table, u64 nbuckets,
@@ -116,6 +121,7 @@ void build_index(mt_index &ix, const mt_index_params &p, const mt_seqs &g, const
     MT_REQUIRE(p.w >= 1 && p.w <= 255, "w must be in 1..255");
     MT_REQUIRE(p.reserved == 0, "reserved field must be 0");
     MT_REQUIRE(g.n < (1ull << 31), "at most 2^31 - 1 genomes");
+    MT_REQUIRE(n_taxa < (1u << 31), "at most 2^31 - 1 taxa");
     MT_REQUIRE(g.n == 0 || (g.seq && g.offsets), "null genome arrays");
     std::vector<u32> tax(g.n);
     for (u64 i = 0; i < g.n; i++) {
@@ -135,13 +141,15 @@ void build_index(mt_index &ix, const mt_index_params &p, const mt_seqs &g, const
     MT_HIP(hipMemsetAsync(ix.has_n.p, 0, (g.n ? g.n : 1) * sizeof(u32), s));
     pack_sequences(g, 4294901759ull, ERR_READ_TOO_LONG, "genome length must be below 2^32 - 2^16", ix.ref,
                    flags.p, ix.has_n.p, s);
-    ix.glen.alloc(g.n);
-    if (g.n) {
-        k_genome_meta<<<grid_for(g.n, 256), 256, 0, s>>>(g.offsets, g.n, ix.glen.p);
-        MT_HIP(hipGetLastError());
-    }
     ix.taxon.alloc(g.n);
     if (g.n) MT_HIP(hipMemcpyAsync(ix.taxon.p, tax.data(), g.n * sizeof(u32), hipMemcpyHostToDevice, s));
+    ix.glen.alloc(g.n);
+    ix.meta.alloc(g.n);
+    if (g.n) {
+        k_genome_meta<<<grid_for(g.n, 256), 256, 0, s>>>(g.offsets, g.n, ix.ref.blk_off.p, ix.has_n.p, ix.taxon.p,
+                                                          ix.glen.p, ix.meta.p);
+        MT_HIP(hipGetLastError());
+    }
     tm.mark("index_pack");
 
     MinimizerPlan mp;
@@ -203,6 +211,7 @@ void build_index(mt_index &ix, const mt_index_params &p, const mt_seqs &g, const
 u64 index_device_bytes(const mt_index &ix) {
     return ix.ref.lohi.n * sizeof(u64x2) + ix.ref.nb.n * sizeof(u64) + ix.ref.blk_off.n * sizeof(u64) +
            ix.glen.n * sizeof(u64) + ix.has_n.n * sizeof(u32) + ix.taxon.n * sizeof(u32) +
+           ix.meta.n * sizeof(GenomeMeta) +
            ix.table.n * sizeof(u64x2) + ix.occ.n * sizeof(u64);
 }
 

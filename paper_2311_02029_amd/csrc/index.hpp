@@ -12,6 +12,7 @@ struct mt_index {
     mt::DBuf<mt::u64> glen;      // genome lengths
     mt::DBuf<mt::u32> has_n;     // 1 if the genome contains N
     mt::DBuf<mt::u32> taxon;     // taxon of each genome
+    mt::DBuf<GenomeMeta> meta;   // per-genome record used by the filter
     mt::DBuf<u64x2> table;     // nbuckets * 4 slots {k-mer, value}
     mt::u64 nbuckets = 0;
     mt::DBuf<mt::u64> occ;       // occurrences (genome << 32 | position) of multi-occurrence k-mers

@@ -1,0 +1,101 @@
+"""Parity at the benchmark's full size: 200 genomes / 500 Mbp, 1M reads of
+150 bp, k=21, w=11, >= 3 hits, top 3, E=7, in the launch configuration the
+benchmark times (fused), against
+
+  * the CPU oracle, read by read, on a seeded sample of the batch (the oracle
+    finishes a sample in seconds; its index over 500 Mbp takes ~40 s);
+  * the per-stage GPU form on every read (both GPU forms must agree bit for
+    bit everywhere);
+  * properties that hold at any size: canonical candidate order, >= min_hits,
+    accept == (approx <= E), approx <= E + 1, per-taxon conservation.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("cand_offsets", "read_accepted", "read_E", "genome", "diag", "hits", "approx", "accept", "unique",
+          "multi")
+
+
+@pytest.fixture(scope="module")
+def full():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2311_02029_amd as mt
+    db = synth.workload_batched_db()
+    reads = synth.workload_batched_reads(db, 1_000_000)
+    ga = db.ascii()
+    ix = mt.Index(mt.to_device(ga), 21, 11)
+    dr = mt.to_device(reads)
+    res = ix.classify(dr, min_hits=3, top_n=3, e_value=7, mode=mt.MT_MODE_FUSED)
+    fused = res.to_host()
+    res.free()
+    res = ix.classify(dr, min_hits=3, top_n=3, e_value=7, mode=mt.MT_MODE_PER_STAGE)
+    stage = res.to_host()
+    res.free()
+    return dict(ga=ga, reads=reads, fused=fused, stage=stage)
+
+
+def _slice(res, idx):
+    co = res["cand_offsets"].astype(np.int64)
+    out = {f: [] for f in ("genome", "diag", "hits", "approx", "accept")}
+    offs = [0]
+    for r in idx:
+        for f in out:
+            out[f].append(res[f][co[r]:co[r + 1]])
+        offs.append(offs[-1] + co[r + 1] - co[r])
+    out = {f: np.concatenate(v) if v else np.zeros(0) for f, v in out.items()}
+    out["cand_offsets"] = np.array(offs, np.uint64)
+    out["read_accepted"] = res["read_accepted"][idx]
+    out["read_E"] = res["read_E"][idx]
+    return out
+
+
+def test_fused_equals_per_stage_on_every_read(full):
+    for f in FIELDS:
+        assert np.array_equal(full["fused"][f], full["stage"][f]), f
+    assert full["fused"]["unmapped"] == full["stage"]["unmapped"]
+
+
+def test_sampled_reads_match_oracle(full):
+    reads = full["reads"]
+    idx = np.sort(np.random.default_rng(2024).choice(reads.n, 3000, replace=False))
+    oix = oracle.Index(full["ga"], 21, 11)
+    ref = oix.classify(reads.subset(idx), 3, 3, 0, 7)
+    got = _slice(full["fused"], idx)
+    for f in ("cand_offsets", "read_accepted", "read_E", "genome", "diag", "hits", "approx", "accept"):
+        a, b = np.asarray(got[f]), np.asarray(ref[f])
+        assert a.shape == b.shape and np.array_equal(a.astype(b.dtype), b), f
+
+
+def test_properties_at_full_size(full):
+    res = full["fused"]
+    co = res["cand_offsets"].astype(np.int64)
+    n = len(co) - 1
+    nc = np.diff(co)
+    assert nc.max() <= 3
+    assert (res["hits"] >= 3).all()
+    E = np.repeat(res["read_E"], nc)
+    assert np.array_equal(res["accept"], (res["approx"] <= E).astype(np.uint8))
+    assert (res["approx"] <= E + 1).all()
+    # canonical order inside every read: hits desc, genome asc, diag asc
+    same = np.repeat(np.arange(n), nc)
+    nxt = np.flatnonzero(same[1:] == same[:-1])
+    h, g, d = res["hits"].astype(np.int64), res["genome"].astype(np.int64), res["diag"]
+    ok = (h[nxt] > h[nxt + 1]) | ((h[nxt] == h[nxt + 1]) & ((g[nxt] < g[nxt + 1]) |
+                                                            ((g[nxt] == g[nxt + 1]) & (d[nxt] < d[nxt + 1]))))
+    assert ok.all()
+    # read flags and per-taxon conservation
+    acc = np.zeros(n, np.uint8)
+    np.maximum.at(acc, same, res["accept"])
+    assert np.array_equal(res["read_accepted"], acc)
+    n_acc = int(acc.sum())
+    assert n_acc + res["unmapped"] == n
+    n_unique = int(res["unique"].sum())
+    assert n_unique <= n_acc and int(res["multi"].sum()) >= 2 * (n_acc - n_unique)
+    assert n_acc > 0.99 * n
