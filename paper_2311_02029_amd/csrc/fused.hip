@@ -36,7 +36,8 @@ void launch_max_u16(const u16 *v, u64 n, u32 *out, hipStream_t s) {
 
 constexpr int F_WPB = 4;         // wavefronts per block
 constexpr int F_MAX_M = 256;     // longest read the fused kernel takes
-constexpr int F_HIT_CAP = 256;   // seed hits per read held in LDS
+constexpr int F_HIT_CAP = 256;   // seed hits per read (distinct locations fit the table)
+constexpr int F_TSLOTS = 256;    // per-read LDS hash table of locations
 constexpr int F_MAX_E = 31;      // 2E + 1 rows fit one wavefront
 constexpr int F_MAX_TOPN = 4;
 constexpr int F_QCAP = 4;        // queued (read, candidate) pairs per wave: one per 16-lane group
@@ -149,6 +150,29 @@ __device__ inline u64 bucket_lookup(const u64x2 *__restrict__ table, u64 nbucket
         if (e3.lo == x) return e3.hi;
         if (e3.lo == SLOT_EMPTY_KEY) return SLOT_NONE;
         b = (b + 1 == nbuckets) ? 0 : b + 1;
+    }
+}
+
+// Slot of a location key in the per-read LDS table.
+__device__ inline u32 tslot(u64 key) {
+    u32 x = (u32)key ^ (u32)(key >> 29);
+    return (x * 0x9E3779B1u) >> 24;
+}
+
+// Counts one seed hit of `key` in the per-read LDS table (linear probing; the
+// table never holds more than F_HIT_CAP <= F_TSLOTS distinct keys).
+__device__ inline void table_add(u64 *tkey, u32 *tcnt, u64 key) {
+    u32 s = tslot(key);
+    for (int probe = 0; probe < F_TSLOTS; probe++, s = (s + 1) & (F_TSLOTS - 1)) {
+        u64 cur = tkey[s];
+        if (cur == ~0ull) {
+            cur = atomicCAS((unsigned long long *)&tkey[s], ~0ull, (unsigned long long)key);
+            if (cur == ~0ull) cur = key;
+        }
+        if (cur == key) {
+            atomicAdd(&tcnt[s], 1u);
+            return;
+        }
     }
 }
 
@@ -335,13 +359,13 @@ __device__ inline void issue_read_bytes(const FusedArgs &a, u64 r, int lane, Rea
     }
 }
 
-// Four wavefronts per SIMD: the kernel is bound by memory latency as much as
-// by VALU issue, and the register budget of 128 is met with one spilled value.
-__global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_fused(FusedArgs a) {
+// Five wavefronts per SIMD (96 registers, a few spilled; the LDS of 4-wave
+// blocks also allows five): the kernel waits on memory as much as it issues.
+__global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_fused(FusedArgs a) {
     __shared__ u64 sh_h[F_WPB][F_MAX_M];     // k-mer hashes (~0 when invalid); later candidate keys
-    __shared__ u64 sh_hit[F_WPB][F_HIT_CAP]; // (genome, diagonal) keys of the seed hits
-    __shared__ u32 sh_cnt[F_WPB][F_HIT_CAP]; // candidate hit counts
-    __shared__ u16 sh_pos[F_WPB][F_MAX_M];   // minimizer positions
+    __shared__ u64 sh_tkey[F_WPB][F_TSLOTS]; // per-read hash table of (genome, diagonal) keys
+    __shared__ u32 sh_tcnt[F_WPB][F_TSLOTS]; // ... and their seed-hit counts
+    __shared__ u16 sh_pos[F_WPB][F_MAX_M];   // minimizer positions; later candidate hit counts
     __shared__ u8 sh_pick[F_WPB][F_MAX_M];   // window picks
     __shared__ u8 sh_ok[F_WPB][F_MAX_M];     // k-mer has no N
     __shared__ u32 sh_st[F_WPB][F_WORDS];    // big-endian 2-bit stream of the read
@@ -350,10 +374,13 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(4, 8
     __shared__ PendRead sh_pend[F_WPB][F_PCAP];
     __shared__ u64 sh_stats[F_WPB][ST_COUNT];
 
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    // wid is wave-uniform; saying so keeps every per-read value (read index,
+    // length, E, loop bounds) in scalar registers.
+    const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     u64 *hh = sh_h[wid];
-    u64 *hits = sh_hit[wid];
-    u32 *cnts = sh_cnt[wid];
+    u64 *tkey = sh_tkey[wid];
+    u32 *tcnt = sh_tcnt[wid];
+    u16 *ccnt = sh_pos[wid];  // candidate hit counts reuse the minimizer positions (dead after the probes)
     u16 *mpos = sh_pos[wid];
     u8 *pick = sh_pick[wid];
     u8 *okk = sh_ok[wid];
@@ -363,6 +390,11 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(4, 8
     PendRead *pend = sh_pend[wid];
     u64 *wst = sh_stats[wid];
     if (lane < ST_COUNT) wst[lane] = 0;
+    // the table starts empty and every read leaves it empty
+    for (int t = lane; t < F_TSLOTS; t += 64) {
+        tkey[t] = ~0ull;
+        tcnt[t] = 0;
+    }
 
     const u32 k = a.k, T = a.min_hits ? a.min_hits : 1u, N = a.top_n;
     const u64 kmask = (1ull << k) - 1;
@@ -491,21 +523,20 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(4, 8
                 u32 y = __shfl_up(pre, o, 64);
                 if (lane >= o) pre += y;
             }
-            u32 tot = __shfl(pre, 63, 64);
+            const u32 tot = __builtin_amdgcn_readfirstlane(__shfl(pre, 63, 64));
             pre -= cnt;
             if (H + (int)tot > F_HIT_CAP) {
                 overflow = true;
                 break;
             }
             if (cnt) {
-                int base = H + (int)pre;
                 if (!(v & SLOT_MULTI)) {
-                    hits[base] = cand_key((u32)(v >> 32), (i64)(u32)v - p);
+                    table_add(tkey, tcnt, cand_key((u32)(v >> 32), (i64)(u32)v - p));
                 } else {
                     u64 st = slot_start(v);
                     for (u32 u = 0; u < cnt; u++) {
                         u64 gp = a.occ[st + u];
-                        hits[base + u] = cand_key((u32)(gp >> 32), (i64)(u32)gp - p);
+                        table_add(tkey, tcnt, cand_key((u32)(gp >> 32), (i64)(u32)gp - p));
                     }
                 }
             }
@@ -522,44 +553,40 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(4, 8
                 nxt.b[q] = (nxt.m <= F_MAX_M && i < nxt.m) ? (u32)a.seq[nbeg + i] : (u32)'N';
             }
         }
+        wave_sync();
         if (overflow) {
+            for (int t = lane; t < F_TSLOTS; t += 64) {
+                tkey[t] = ~0ull;
+                tcnt[t] = 0;
+            }
             if (lane == 0) a.fb_list[atomicAdd(a.fb_count, 1u)] = (u32)r;
             cur = nxt;
             wave_sync();
             continue;
         }
-        wave_sync();
 
-        // 5. hits per location (8 keys read per batch), candidates, top_n by rank
+        // 5. locations with >= min_hits hits become candidates (the table is
+        // emptied as it is read), then top_n by rank
         int C = 0;
-        for (int t0 = 0; t0 < H; t0 += 64) {
-            int j = t0 + lane;
-            bool is_c = false;
-            u64 key = 0;
-            u32 c = 0;
-            if (j < H) {
-                key = hits[j];
-                bool first = true;
-                for (int u0 = 0; u0 < H; u0 += 8) {
-                    u64 kb[8];
+        if (H > 0) {
 #pragma unroll
-                    for (int t = 0; t < 8; t++) kb[t] = u0 + t < H ? hits[u0 + t] : ~0ull;
-#pragma unroll
-                    for (int t = 0; t < 8; t++) {
-                        bool eq = kb[t] == key;
-                        c += eq;
-                        first &= !(eq && u0 + t < j);
-                    }
+            for (int q = 0; q < F_TSLOTS / 64; q++) {
+                const int t = 64 * q + lane;
+                const u64 key = tkey[t];
+                const u32 c = tcnt[t];
+                const bool is_c = key != ~0ull && c >= T;
+                if (key != ~0ull) {
+                    tkey[t] = ~0ull;
+                    tcnt[t] = 0;
                 }
-                is_c = first && c >= T;
+                const u64 cm = ballot64(is_c);
+                if (is_c) {
+                    const int s2 = C + (int)lanes_below(cm, lane);
+                    hh[s2] = key;
+                    ccnt[s2] = (u16)c;
+                }
+                C += __popcll(cm);
             }
-            u64 cm = ballot64(is_c);
-            if (is_c) {
-                int s2 = C + (int)lanes_below(cm, lane);
-                hh[s2] = key;
-                cnts[s2] = c;
-            }
-            C += __popcll(cm);
         }
         wave_sync();
         const int nc = C < (int)N ? C : (int)N;
@@ -567,10 +594,10 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(4, 8
             int cidx = t0 + lane;
             if (cidx < C) {
                 u64 kc = hh[cidx];
-                u32 hc = cnts[cidx];
+                u32 hc = ccnt[cidx];
                 int rank = 0;
                 for (int b = 0; b < C; b++) {
-                    u32 hb = cnts[b];
+                    u32 hb = ccnt[b];
                     rank += hb > hc || (hb == hc && hh[b] < kc);
                 }
                 if (rank < nc) sel[rank] = (u32)cidx;
@@ -604,7 +631,7 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(4, 8
                 qG = G;
                 if (lane == 0) {
                     u32 si = sel[c];
-                    queue[qn] = QEntry{hh[si], (u32)(r * N + (u64)c), cnts[si], (u8)slot, (u8)c};
+                    queue[qn] = QEntry{hh[si], (u32)(r * N + (u64)c), ccnt[si], (u8)slot, (u8)c};
                 }
                 qn += 1;
                 wave_sync();
