@@ -37,6 +37,23 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per dispatch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    record of this kernel (scaled by the plain-copy calibration), or None when
+    the record is missing or was taken on a different kernel source."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_fused_hbm_counters_500mbp_1m.json")
+    if kernel != "fused" or not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for src in rec["kernel_sources"]:
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    if h.hexdigest() != rec["source_sha256"]:
+        return None
+    return int(rec["traffic_bytes_per_dispatch"])
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -144,7 +161,7 @@ def main() -> int:
         if alg is not None and dur_s > 0:
             ach = alg / dur_s / 1e9
             roofline = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                        "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom),
                         "avg_ms": round(stages[dom], 4), "algorithmic_bytes": int(alg)}
         else:
             roofline = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
