@@ -256,85 +256,6 @@ __global__ void k_compact(const u64 *__restrict__ read_hs, const u32 *__restrict
     }
 }
 
-// ----------------------------------------------------------------- filter --
-
-struct FilterArgs {
-    const u32 *pair_read;
-    const u32 *pair_genome;
-    const i64 *pair_diag;
-    const u16 *pair_E;   // per-pair E, or null to use read_E
-    const u16 *read_E;
-    const u64 *n_dev;    // pair count on the device, or null to use n_host
-    u64 n_host;
-    u64 n_reads;
-    const u64 *read_off;  // ASCII offsets (lengths)
-    const u64 *read_blk;
-    const u64x2 *read_lohi;
-    const u64 *read_nb;
-    u64 n_genomes;
-    const GenomeMeta *meta;
-    const u64x2 *ref_lohi;
-    const u64 *ref_nb;
-    u16 *approx;
-    u8 *accept;
-    u32 *flags;
-};
-
-// G lanes per pair, 256 / G pairs per block of 256 threads.
-template <int G>
-__global__ __launch_bounds__(256) void k_filter(FilterArgs a) {
-    u64 tid = (u64)blockIdx.x * blockDim.x + threadIdx.x;
-    u64 p = tid / G;
-    int lane = (int)(tid % G);
-    u64 np = a.n_dev ? *a.n_dev : a.n_host;
-    if (p >= np) return;
-    u32 r = a.pair_read[p], g = a.pair_genome[p];
-    if (r >= a.n_reads || g >= a.n_genomes) {
-        if (lane == 0) {
-            atomicOr(a.flags, ERR_PAIR_RANGE);
-            a.approx[p] = 0xFFFF;
-            a.accept[p] = 0;
-        }
-        return;
-    }
-    int E = a.pair_E ? a.pair_E[p] : a.read_E[r];
-    if (E > 65534) {
-        if (lane == 0) {
-            atomicOr(a.flags, ERR_E_TOO_LARGE);
-            a.approx[p] = 0xFFFF;
-            a.accept[p] = 0;
-        }
-        return;
-    }
-    PairView v;
-    v.qlohi = a.read_lohi + a.read_blk[r];
-    v.qnb = a.read_nb + a.read_blk[r];
-    v.m = (int)(a.read_off[r + 1] - a.read_off[r]);
-    GenomeMeta gm = a.meta[g];
-    v.rlohi = a.ref_lohi + gm.blk;
-    v.rnb = a.ref_nb + gm.blk;
-    v.L = (i64)gm.len;
-    v.has_n = meta_has_n(gm);
-    v.diag = a.pair_diag[p];
-    int approx = obstacle_walk<G>(v, E, lane);
-    if (lane == 0) {
-        a.approx[p] = (u16)approx;
-        a.accept[p] = approx <= E;
-    }
-}
-
-static void launch_filter(const FilterArgs &a, u64 n_cap, u32 max_E, hipStream_t s) {
-    if (n_cap == 0) return;
-    u32 rows = 2 * max_E + 1;
-    if (rows <= 16)
-        k_filter<16><<<grid_for(n_cap * 16, 256), 256, 0, s>>>(a);
-    else if (rows <= 32)
-        k_filter<32><<<grid_for(n_cap * 32, 256), 256, 0, s>>>(a);
-    else
-        k_filter<64><<<grid_for(n_cap * 64, 256), 256, 0, s>>>(a);
-    MT_HIP(hipGetLastError());
-}
-
 // ----------------------------------------------------------------- reduce --
 
 __global__ void k_reduce(const u64 *__restrict__ cand_off, u64 n, const u32 *__restrict__ genome,
@@ -662,14 +583,6 @@ extern "C" int mt_filter_pairs(const mt_index *index, const mt_seqs *reads, cons
         mt::CallScope scope(s);
         mt::ReadBatch rb;
         rb.prepare(*reads, MT_E_FIXED, 0, s);
-        mt::DBuf<mt::u32> maxE(1);
-        MT_HIP(hipMemsetAsync(maxE.p, 0, sizeof(mt::u32), s));
-        if (n_pairs) {
-            mt::launch_max_u16(pair_E, n_pairs, maxE.p, s);
-        }
-        mt::u32 max_E = 0;
-        mt::read_back(s, maxE.p, &max_E, sizeof max_E);
-        if (max_E > 65534) max_E = 65534;
         mt::FilterArgs fa{};
         fa.pair_read = pair_read;
         fa.pair_genome = pair_genome;
@@ -690,7 +603,7 @@ extern "C" int mt_filter_pairs(const mt_index *index, const mt_seqs *reads, cons
         fa.approx = approx_out;
         fa.accept = accept_out;
         fa.flags = rb.flags.p;
-        mt::launch_filter(fa, n_pairs, max_E, s);
+        mt::launch_filter(fa, n_pairs, 0, s);
         mt::u32 f = 0;
         mt::read_back(s, rb.flags.p, &f, sizeof f);
         mt::check_flags(f);

@@ -31,6 +31,34 @@ struct ReadBatch {
     void prepare(const mt_seqs &reads, u32 e_mode, u32 e_value, hipStream_t s);
 };
 
+// Pair lists handed to the filter kernels.
+struct FilterArgs {
+    const u32 *pair_read;
+    const u32 *pair_genome;
+    const i64 *pair_diag;
+    const u16 *pair_E;   // per-pair E, or null to use read_E
+    const u16 *read_E;
+    const u64 *n_dev;    // pair count on the device, or null to use n_host
+    u64 n_host;
+    u64 n_reads;
+    const u64 *read_off;  // ASCII offsets (lengths)
+    const u64 *read_blk;
+    const u64x2 *read_lohi;
+    const u64 *read_nb;
+    u64 n_genomes;
+    const GenomeMeta *meta;
+    const u64x2 *ref_lohi;
+    const u64 *ref_nb;
+    u16 *approx;
+    u8 *accept;
+    u32 *flags;
+};
+
+// Filters pairs [0, n) (n = *n_dev if set, else n_host; n_cap bounds it):
+// pairs are bucketed by their E (one synchronization to size the buckets),
+// then each bucket runs the kernel shaped for it.
+void launch_filter(const FilterArgs &a, u64 n_cap, u32 max_E, hipStream_t s);
+
 void validate_query(const mt_query_params &q);
 void mt_result_init(mt_result &res, u64 n, u32 n_taxa, hipStream_t s);
 void classify_per_stage(const mt_index &ix, const mt_query_params &q, const mt_seqs &reads, ReadBatch &rb,

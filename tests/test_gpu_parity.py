@@ -208,3 +208,35 @@ def test_repeat_calls_and_modes_identical(mt):
     assert_same(a, b, "repeat")
     assert_same(a, c, "per-stage vs fused")
     assert_same(c, d, "fused repeat")
+
+
+def test_filter_buckets_long_reads_against_oracle(mt):
+    """Pairs in every filter bucket: E <= 7, <= 15, <= 31, the LDS long-read
+    kernel (E > 31) and pairs too large for its LDS budget (30 kbp, E = 1500)."""
+    import torch
+    rnd = np.random.default_rng(21)
+    gen = synth.make_genomes(rnd, 2, 120_000, 0.5)
+    lens = np.array([150, 150, 280, 900, 2500, 6000, 10_000, 30_000, 30_000, 75])
+    reads, origin = synth.make_reads(rnd, gen, lens, 0.02, 0.02)
+    pr, pg, pd, pe = [], [], [], []
+    for i in range(reads.n):
+        for E in (0, 5, 12, 25, 40, 130, 500, 1500):
+            for shift in (0, -3, 17):
+                pr.append(i)
+                pg.append(origin[i, 0])
+                pd.append(origin[i, 1] + shift)
+                pe.append(E)
+    pr = np.array(pr, np.uint32)
+    pg = np.array(pg, np.uint32)
+    pd = np.array(pd, np.int64)
+    pe = np.array(pe, np.uint16)
+    ga = gen.ascii()
+    ix = mt.Index(ga, 15, 10)
+    ap, ac = ix.filter_pairs(mt.to_device(reads), torch.from_numpy(pr.view(np.int32)).cuda(),
+                             torch.from_numpy(pg.view(np.int32)).cuda(), torch.from_numpy(pd).cuda(),
+                             torch.from_numpy(pe.view(np.int16)).cuda())
+    ap = ap.cpu().numpy().view(np.uint16)
+    oap, oac = oracle.Index(ga, 15, 10).filter_pairs(reads, pr, pg, pd, pe)
+    assert np.array_equal(ap, oap), np.flatnonzero(ap != oap)[:10]
+    assert np.array_equal(ac.cpu().numpy(), oac)
+    assert ((oap <= pe) & (pe >= 130)).any() and (oap == pe + 1).any()
