@@ -62,8 +62,13 @@ def main() -> int:
     ap.add_argument("--mode", default="fused", choices=["fused", "per_stage"])
     ap.add_argument("--E", type=int, default=7)
     ap.add_argument("--reads", type=int, default=1_000_000)
-    ap.add_argument("--cpu-reads", type=int, default=1_000_000,
-                    help="reads in the oracle's timed sample (0 skips the CPU baseline)")
+    ap.add_argument("--workload", default="batched", choices=["batched", "uneven", "strains"],
+                    help="batched: 500 Mbp, 1M x 150 bp, E=7 (the metric's workload); uneven: same database, "
+                         "2M reads of 75-300 bp plus 5%% of 1-10 kbp, E=ceil(5%% of length); strains: 2,000 "
+                         "near-duplicate strain genomes (4 Gbp), 10M x 150 bp at 1%% error, E=7")
+    ap.add_argument("--cpu-reads", type=int, default=-1,
+                    help="reads in the oracle's timed sample (0 skips the CPU baseline; default: 1M for batched, "
+                         "2000 for uneven, 0 for strains)")
     ap.add_argument("--no-timing", action="store_true", help="do not record per-stage HIP events")
     ap.add_argument("--genomes", type=int, default=200, help="genomes of 2.5 Mbp in the database")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -92,9 +97,29 @@ def main() -> int:
 
     torch.cuda.set_device(0)
     t = time.time()
-    db = synth.workload_batched_db(n_genomes=args.genomes)
-    reads = synth.workload_batched_reads(db, args.reads)
-    log(f"[bench] data generated in {time.time() - t:.1f}s: {db.n} genomes, {reads.n} reads")
+    if args.cpu_reads < 0:
+        args.cpu_reads = {"batched": 1_000_000, "uneven": 2000, "strains": 0}[args.workload]
+    e_mode, e_value = mt.MT_E_FIXED, args.E
+    if args.workload == "strains":
+        log("[bench] generating 400 roots x 5 strains x 2 Mbp and the reads ...")
+        db = synth.workload_strains_db()
+        reads = synth.workload_strain_reads(db, args.reads if args.reads != 1_000_000 else 10_000_000)
+        workload = (f"strains: 2,000 genomes (400 roots x 5 strains, 1-5% divergence) = 4 Gbp, {reads.n} x 150 bp "
+                    f"at 1% error, k=21 w=11, min_hits=3, top_n=3, E={args.E}")
+    elif args.workload == "uneven":
+        log("[bench] generating the database and the uneven reads ...")
+        db = synth.workload_batched_db(n_genomes=args.genomes)
+        reads = synth.workload_uneven_reads(db, args.reads if args.reads != 1_000_000 else 2_000_000)
+        e_mode, e_value = mt.MT_E_CEIL_PERMILLE, 50
+        workload = (f"uneven: 500 Mbp / 200 genomes, {reads.n} reads (95% of 75-300 bp, 5% of 1-10 kbp), k=21 w=11, "
+                    "min_hits=3, top_n=3, E=ceil(5% of length)")
+    else:
+        db = synth.workload_batched_db(n_genomes=args.genomes)
+        reads = synth.workload_batched_reads(db, args.reads)
+        workload = (f"500 Mbp / 200 genomes, {reads.n // 1000}k x 150 bp reads, k=21 w=11, min_hits=3, top_n=3, "
+                    f"E={args.E}")
+    log(f"[bench] data generated in {time.time() - t:.1f}s: {db.n} genomes, {reads.n} reads, "
+        f"{int(reads.offsets[-1])} bases")
     ga = db.ascii()
     dgen = mt.to_device(ga)
     dreads = mt.to_device(reads)
@@ -114,7 +139,7 @@ def main() -> int:
     del dgen
 
     mode = mt.MT_MODE_FUSED if args.mode == "fused" else mt.MT_MODE_PER_STAGE
-    q = dict(min_hits=3, top_n=3, e_mode=mt.MT_E_FIXED, e_value=args.E, mode=mode)
+    q = dict(min_hits=3, top_n=3, e_mode=e_mode, e_value=e_value, mode=mode)
 
     for i in range(args.warmup):
         t = time.time()
@@ -161,7 +186,8 @@ def main() -> int:
         if alg is not None and dur_s > 0:
             ach = alg / dur_s / 1e9
             roofline = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom),
+                        "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                        "traffic": measured_traffic(dom) if args.workload == "batched" else None,
                         "avg_ms": round(stages[dom], 4), "algorithmic_bytes": int(alg)}
         else:
             roofline = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -175,7 +201,7 @@ def main() -> int:
         log(f"[bench] oracle index built in {time.time() - t:.1f}s (not timed)")
         sample = reads.subset(np.arange(min(args.cpu_reads, reads.n)))
         t = time.perf_counter()
-        out = oix.classify(sample, 3, 3, 0, args.E)
+        out = oix.classify(sample, 3, 3, e_mode, e_value)
         dt = time.perf_counter() - t
         cpu = {"value": round(len(out["genome"]) / dt, 1), "unit": "pairs/s", "cores": 1, "kind": "oracle",
                "reads_per_s": round(sample.n / dt, 1),
@@ -186,9 +212,8 @@ def main() -> int:
         "metric": METRIC, "value": round(pairs_s, 1), "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u64", "data": "synthetic",
-        "config": {"workload": "500 Mbp / 200 genomes, 1M x 150 bp reads, k=21 w=11, min_hits=3, top_n=3, "
-                               f"E={args.E}", "reads": reads.n, "pairs_per_step": int(n_cands),
-                   "mode": args.mode, "parallelism": "single GPU"},
+        "config": {"workload": workload, "reads": reads.n, "bases": int(reads.offsets[-1]),
+                   "pairs_per_step": int(n_cands), "mode": args.mode, "parallelism": "single GPU"},
         "reads_per_s": round(reads_s, 1),
         "index_build_s": round(index_s, 3),
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},

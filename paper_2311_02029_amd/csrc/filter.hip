@@ -7,9 +7,10 @@
 //   E <= 15  groups of 32 lanes, 2 pairs per wavefront
 //   E <= 31  one pair per wavefront
 //   E > 31   long reads: one pair per wavefront with the read and its
-//            reference window staged in LDS and the 2E+1 rows dealt to the
-//            lanes round-robin (k_filter_long); pairs too large for its LDS
-//            budget use the 64-lane kernel that fetches from global memory.
+//            reference window staged in LDS; each lane owns a contiguous
+//            strip of the 2E+1 rows, so one 128-base reference fetch per step
+//            serves its whole strip (k_filter_long); pairs too large for its
+//            LDS budget use the 64-lane kernel that fetches from global memory.
 #include "classify.hpp"
 
 namespace mt {
@@ -39,10 +40,11 @@ __device__ inline void pair_fields(const FilterArgs &a, u64 p, u32 &r, u32 &g, i
 __device__ inline int read_len(const FilterArgs &a, u32 r) { return (int)(a.read_off[r + 1] - a.read_off[r]); }
 
 // Blocks the long kernel stages for a pair: the read's (with its padding
-// block) and the reference window [diag - E, diag + m + E + 64).
+// block) and the reference window from diag - E, long enough for a 128-base
+// fetch at any column < m of any row.
 __device__ inline void long_blocks(int m, int E, int &nrb, int &nwb) {
     nrb = (m + 63) / 64 + 1;
-    nwb = ((m + 2 * E + 126) >> 6) + 2;
+    nwb = ((m + 2 * E + 190) >> 6) + 2;
 }
 
 __global__ void k_pair_class(FilterArgs a, u64 n_cap, u32 *__restrict__ count, u8 *__restrict__ cls) {
@@ -175,26 +177,41 @@ __global__ __launch_bounds__(64 * LONG_WPB) void k_filter_long(FilterArgs a, con
         const u64x2 *WL = L + nrb;
         const u64 *WN = NB + nrb;
         const i64 wbase = diag - 64 * b0;  // window offset of (row 0, column 0)
+        // lane owns the contiguous rows [r0, r1): one 128-base reference fetch
+        // per step serves all of them through funnel shifts
         const int rows = 2 * E + 1;
+        const int S = (rows + 63) / 64;
+        const int r0 = min(lane * S, rows), r1 = min(r0 + S, rows);
         int j = 0, c = 0;
         for (;;) {
             const Bits64 q0 = lds_bits(L, NB, j);
             int best = 0;
-            for (int row = lane; row < rows; row += 64) {
-                const i64 w0 = wbase + (row - E) + j;
-                Bits64 q = q0;
-                int run = 0;
-                for (;;) {
-                    const u64 mm = mismatch(q, lds_bits(WL, WN, w0 + run));
+            for (int s0 = r0; s0 < r1; s0 += 64) {  // chunks of <= 64 rows (funnel shifts < 64)
+                const i64 pos = wbase + (s0 - E) + j;  // window offset of (row s0, column j)
+                const Bits64 wa = lds_bits(WL, WN, pos), wb = lds_bits(WL, WN, pos + 64);
+                const int cnt = min(64, r1 - s0);
+                for (int i = 0; i < cnt; i++) {
+                    Bits64 w;
+                    w.lo = funnel(wa.lo, wb.lo, (u32)i);
+                    w.hi = funnel(wa.hi, wb.hi, (u32)i);
+                    w.nb = funnel(wa.nb, wb.nb, (u32)i);
+                    u64 mm = mismatch(q0, w);
+                    int run;
                     if (mm) {
-                        run += (int)__builtin_ctzll(mm);
-                        break;
+                        run = (int)__builtin_ctzll(mm);
+                    } else {  // 64 matching columns: continue word by word
+                        run = 64;
+                        while (j + run < m) {
+                            mm = mismatch(lds_bits(L, NB, j + run), lds_bits(WL, WN, pos + i + run));
+                            if (mm) {
+                                run += (int)__builtin_ctzll(mm);
+                                break;
+                            }
+                            run += 64;
+                        }
                     }
-                    run += 64;
-                    if (j + run >= m) break;
-                    q = lds_bits(L, NB, j + run);
+                    best = max(best, min(run, m - j));
                 }
-                best = max(best, min(run, m - j));
             }
             best = group_max<64>(best);
             j += best;

@@ -236,6 +236,7 @@ extern "C" int mt_index_build(const mt_index_params *params, const mt_seqs *geno
             mt::CallScope scope((hipStream_t)stream);
             mt::build_index(*ix, *params, *genomes, taxon_of_genome, n_taxa, (hipStream_t)stream);
         }
+        mt::pool_trim();  // the build's scratch (several times the index) is not needed again
         *out = ix;
         mt::set_last_error("");
         return MT_OK;

@@ -220,9 +220,9 @@ void minimizer_plan(const mt_seqs &in, const PackedSeqs &ps, u32 k, u32 w, int t
     mp.tile_map.alloc(mp.tiles_cap);
     mp.tile_count.alloc(mp.tiles_cap);
     mp.min_off.alloc(mp.tiles_cap + 1);
-    if (in.n == 0) {
+    if (in.n == 0) {  // no tiles: every offset is 0 (callers read min_off[tiles_cap])
         MT_HIP(hipMemsetAsync(mp.tile_off.p, 0, sizeof(u64), s));
-        MT_HIP(hipMemsetAsync(mp.min_off.p, 0, sizeof(u64), s));
+        MT_HIP(hipMemsetAsync(mp.min_off.p, 0, (mp.tiles_cap + 1) * sizeof(u64), s));
         return;
     }
     DBuf<u64> ntile(in.n);

@@ -262,6 +262,13 @@ def workload_strains_db(seed: int = 4, n_roots: int = 400, root_len: int = 2_000
     return make_strain_genomes(rng, n_roots, root_len, strains)
 
 
+def workload_strain_reads(gen: Genomes, n_reads: int = 10_000_000, seed: int = 104):
+    """150 bp reads at 1% error (0.9% substitutions, 0.1% indels) from the strain database."""
+    rng = np.random.default_rng(seed)
+    reads, _ = make_reads(rng, gen, np.full(n_reads, 150), 0.009, 0.001)
+    return reads
+
+
 def request_trace(seed: int, n_requests: int, qps: float, max_reads: int = 50_000,
                   len_range=(100, 250)):
     """Poisson arrivals at `qps`; each request has U{1..max_reads} reads of one
