@@ -54,6 +54,160 @@ def measured_traffic(kernel: str):
     return int(rec["traffic_bytes_per_dispatch"])
 
 
+def _pct(v, q):
+    return float(np.percentile(np.asarray(v, dtype=np.float64), q)) if len(v) else None
+
+
+def serving_bench(mt, ix, pool, seconds: float = 2.0, loads=(0.5, 0.8, 0.95), threads: int = 8,
+                  baseline_s: float = 4.0) -> dict:
+    """The served workload: requests of U{1..50,000} reads of one length in
+    100-250 bp at 0.5% error, E = ceil(5% of length), against the resident
+    index.  Measures
+      * the server's saturated reads/s (closed loop: `threads` clients submit
+        back to back for `seconds`);
+      * p50 / p99 request latency (completion minus scheduled arrival) on
+        Poisson traces offering each fraction in `loads` of that rate;
+      * the same trace served by sequential per-request solves (upload,
+        mt_classify, download, one request at a time), plain per-stage form
+        and fused form, for at most `baseline_s` seconds each.
+    """
+    import threading
+    import synth
+    from collections import deque
+
+    q = dict(min_hits=3, top_n=3, e_mode=mt.MT_E_CEIL_PERMILLE, e_value=50)
+    mean_reads = 25_000.5
+
+    def trace(seed, n, qps):
+        return synth.request_trace(seed, n, qps, lengths=synth.SERVED_LENGTHS)
+
+    def run_served(tr, paced: bool, stop_after: float | None = None):
+        """Submits tr (paced by arrival, or back to back); returns per-request
+        (arrival_ns, submit_ns, done_ns, reads) and the wall interval."""
+        recs = [None] * len(tr)
+        ids = [None] * len(tr)
+        errs = []
+        with mt.Server(ix, pinned_arena_bytes=4 << 30, max_queued_requests=8192) as sv:
+            t0 = time.monotonic_ns()
+            stop_at = None if stop_after is None else t0 + int(stop_after * 1e9)
+            avail = [threading.Semaphore(0) for _ in range(threads)]
+            done_n = [0] * threads
+
+            def client(k):
+                try:
+                    for i in range(k, len(tr), threads):
+                        arr_ns = t0 + int(tr[i][0] * 1e9) if paced else time.monotonic_ns()
+                        if stop_at is not None and time.monotonic_ns() >= stop_at:
+                            break
+                        if paced:
+                            while True:
+                                d = (arr_ns - time.monotonic_ns()) / 1e9
+                                if d <= 0:
+                                    break
+                                time.sleep(min(d, 0.002))
+                        reads = synth.request_reads(pool, tr[i][1], tr[i][2])
+                        while True:
+                            try:
+                                rid = sv.submit(reads, **q)
+                                break
+                            except mt.MTError as e:
+                                if e.status != mt._abi.MT_EAGAIN:
+                                    raise
+                                time.sleep(0.0002)
+                        ids[i] = (rid, arr_ns)
+                        avail[k].release()
+                        done_n[k] += 1
+                    avail[k].release()  # end marker
+                except Exception as e:  # noqa: BLE001
+                    errs.append(e)
+                    avail[k].release()
+
+            def waiter(k):
+                try:
+                    i = k
+                    while True:
+                        avail[k].acquire()
+                        if i >= len(tr) or ids[i] is None:
+                            return
+                        rid, arr_ns = ids[i]
+                        res = sv.wait(rid)
+                        s_ns, d_ns = res.times_ns()
+                        res.free()
+                        recs[i] = (arr_ns, s_ns, d_ns, tr[i][1])
+                        i += threads
+                except Exception as e:  # noqa: BLE001
+                    errs.append(e)
+
+            ts = [threading.Thread(target=client, args=(k,)) for k in range(threads)]
+            ws = [threading.Thread(target=waiter, args=(k,)) for k in range(threads)]
+            for x in ts + ws:
+                x.start()
+            for x in ts + ws:
+                x.join()
+        if errs:
+            raise errs[0]
+        recs = [r for r in recs if r is not None]
+        return recs, t0
+
+    def summarize(recs, t0):
+        if not recs:
+            return None
+        lat = [(d - a) / 1e6 for a, _, d, _ in recs]
+        reads = sum(r[3] for r in recs)
+        first = min(r[0] for r in recs)
+        last = max(r[2] for r in recs)
+        span = (last - first) / 1e9
+        return {"requests": len(recs), "reads": int(reads), "reads_per_s": round(reads / span, 1),
+                "p50_ms": round(_pct(lat, 50), 3), "p99_ms": round(_pct(lat, 99), 3),
+                "mean_ms": round(float(np.mean(lat)), 3)}
+
+    out = {"workload": "requests of U{1..50,000} reads x one length in {100..250} bp (16 lengths), 0.5% error, "
+                       "E=ceil(5% of length), min_hits=3, top_n=3, 500 Mbp index resident; Poisson arrivals",
+           "threads": threads}
+    # warm up the server path (allocator, pinned buffers)
+    recs, t0 = run_served(trace(99, 64, 1.0), paced=False)
+    # saturation: back to back for `seconds`
+    recs, t0 = run_served(trace(3, 100_000, 1.0), paced=False, stop_after=seconds)
+    sat = summarize(recs, t0)
+    out["saturated"] = sat
+    log(f"[serve] saturated: {sat}")
+    sat_rps = sat["reads_per_s"]
+    out["traces"] = []
+    for i, load in enumerate(loads):
+        qps = load * sat_rps / mean_reads
+        n = max(20, int(qps * seconds))
+        recs, t0 = run_served(trace(3 + i, n, qps), paced=True)
+        sm = summarize(recs, t0)
+        sm.update({"offered_load": load, "qps": round(qps, 1)})
+        out["traces"].append(sm)
+        log(f"[serve] load {load}: {sm}")
+
+    # sequential per-request solves on the 80% trace
+    qps = 0.8 * sat_rps / mean_reads
+    tr = trace(4, max(20, int(qps * seconds)), qps)
+    for name, mode in (("sequential_per_stage", mt.MT_MODE_PER_STAGE), ("sequential_fused", mt.MT_MODE_FUSED)):
+        recs = []
+        t0 = time.monotonic_ns()
+        stop_at = t0 + int(baseline_s * 1e9)
+        for arr_s, n, m in tr:
+            arr_ns = t0 + int(arr_s * 1e9)
+            now = time.monotonic_ns()
+            if now >= stop_at:
+                break
+            if arr_ns > now:
+                time.sleep((arr_ns - now) / 1e9)
+            reads = synth.request_reads(pool, n, m)
+            res = ix.classify(mt.to_device(reads), mode=mode, **q)
+            res.to_host()
+            res.free()
+            recs.append((arr_ns, arr_ns, time.monotonic_ns(), n))
+        sm = summarize(recs, t0)
+        sm.update({"offered_load": 0.8, "qps": round(qps, 1), "of_trace_requests": len(tr)})
+        out[name] = sm
+        log(f"[serve] {name}: {sm}")
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +225,9 @@ def main() -> int:
                          "2000 for uneven, 0 for strains)")
     ap.add_argument("--no-timing", action="store_true", help="do not record per-stage HIP events")
     ap.add_argument("--genomes", type=int, default=200, help="genomes of 2.5 Mbp in the database")
+    ap.add_argument("--serving", type=int, default=1,
+                    help="1: also measure the served workload (batched workload only); 0: skip it")
+    ap.add_argument("--serve-seconds", type=float, default=2.0, help="length of each served trace")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times), to scale HBM byte counters")
     args = ap.parse_args()
@@ -120,6 +277,11 @@ def main() -> int:
                     f"E={args.E}")
     log(f"[bench] data generated in {time.time() - t:.1f}s: {db.n} genomes, {reads.n} reads, "
         f"{int(reads.offsets[-1])} bases")
+    pool = None
+    if args.serving and args.workload == "batched":
+        t = time.time()
+        pool = synth.served_read_pool(db)
+        log(f"[bench] served read pool generated in {time.time() - t:.1f}s")
     ga = db.ascii()
     dgen = mt.to_device(ga)
     dreads = mt.to_device(reads)
@@ -193,6 +355,10 @@ def main() -> int:
             roofline = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": None, "traffic": None, "avg_ms": round(stages[dom], 4)}
 
+    serving = None
+    if pool is not None:
+        serving = serving_bench(mt, ix, pool, seconds=args.serve_seconds)
+
     cpu = None
     if args.cpu_reads > 0:
         import oracle
@@ -219,6 +385,7 @@ def main() -> int:
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
     return 0

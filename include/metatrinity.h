@@ -206,6 +206,66 @@ int mt_filter_pairs(const mt_index *index, const mt_seqs *reads, const uint32_t 
                     const uint32_t *pair_genome, const int64_t *pair_diag, const uint16_t *pair_E,
                     uint64_t n_pairs, uint16_t *approx_out, uint8_t *accept_out, void *stream);
 
+/*
+ * Serving loop: continuous batching of classification requests on one GPU
+ * with the index resident in HBM.  Requests that arrive while others run are
+ * admitted as batch slots and device memory free up; reads of several
+ * requests with the same query parameters share a device batch, and a large
+ * request is split across batches.  n_streams worker threads each own a HIP
+ * stream, so the upload of one batch overlaps the classification of another.
+ * Each request gets exactly what mt_classify gives for its reads alone
+ * (Fig. 1 steps 2b-2d, and the taxon counts of step 3a over its own reads).
+ */
+typedef struct mt_server mt_server;
+
+typedef struct mt_server_params {
+    uint64_t mem_budget_bytes;      /* device bytes admitted at once; 0 = 4 GiB */
+    uint64_t max_batch_reads;       /* reads per device batch; 0 = 1,048,576 */
+    uint32_t n_streams;             /* batches in flight (worker threads); 0 = 2 */
+    uint32_t max_queued_requests;   /* submitted and not yet waited for; 0 = 4096 */
+    uint64_t pinned_arena_bytes;    /* pinned host memory for queued reads; 0 = 1 GiB */
+    uint32_t reserved[4];           /* must be 0 */
+} mt_server_params;
+
+/* Creates the server (threads start at once).  The index must outlive it. */
+int mt_server_create(const mt_index *index, const mt_server_params *params, mt_server **out);
+
+/*
+ * Queues one request.  seq / offsets are HOST memory (offsets: n + 1
+ * non-decreasing entries, offsets[0] = 0), validated and copied into the
+ * server's pinned arena before the call returns.  params->mode is ignored (the
+ * fused form runs, with the same per-stage handling of reads past its limits
+ * as mt_classify).  *request_id receives the id to wait for.
+ * Errors: MT_EINVAL (bad parameter, offset or byte, read > 65535 bases,
+ * E > 65534, request larger than the arena), MT_EAGAIN (max_queued_requests
+ * not yet waited for, or the arena is full: retry after a wait), MT_ECANCELED
+ * (server shutting down), MT_ENOMEM, MT_EDEVICE.
+ */
+int mt_server_submit(mt_server *server, const mt_query_params *params, const char *seq, const uint64_t *offsets,
+                     uint64_t n, uint64_t *request_id);
+
+/*
+ * Waits up to timeout_us (< 0: forever) for a request and hands over its
+ * result: a handle like mt_classify's, but its arrays are HOST memory
+ * (mt_result_on_host) and its taxon counts cover this request only.
+ * A finished request is handed over once; *out is NULL on error.
+ * Errors: MT_ETIMEDOUT (not finished yet; wait again), MT_EINVAL (unknown id,
+ * already handed over, or waited for by another thread), and the error of a
+ * device batch that held the request (MT_EDEVICE, MT_ENOMEM).
+ */
+int mt_server_wait(mt_server *server, uint64_t request_id, int64_t timeout_us, mt_result **out);
+
+/* Stops accepting requests, finishes the queued ones, joins the threads.
+ * Results not yet waited for are released. */
+int mt_server_destroy(mt_server *server);
+
+/* 1 if the result's arrays live in host memory (served results), 0 if on
+ * the device (mt_classify). */
+int mt_result_on_host(const mt_result *res);
+
+/* Submit and completion times of a served request (steady clock, ns). */
+int mt_result_times(const mt_result *res, uint64_t *submit_ns, uint64_t *done_ns);
+
 /* Releases device memory cached by the library's allocator (not held by any handle). */
 int mt_trim(void);
 /* Description of the last error on the calling thread ("" if none). */

@@ -16,7 +16,7 @@ from . import _abi
 from ._abi import (MT_E_CEIL_PERMILLE, MT_E_FIXED, MT_E_FLOOR_PERMILLE, MT_MODE_FUSED,  # noqa: F401
                    MT_MODE_PER_STAGE, MT_OK)
 
-__all__ = ["MTError", "DeviceSeqs", "Index", "Result", "to_device", "mt_set_timing", "last_timings"]
+__all__ = ["MTError", "DeviceSeqs", "Index", "Result", "Server", "to_device", "mt_set_timing", "last_timings"]
 
 
 class MTError(RuntimeError):
@@ -61,6 +61,14 @@ def to_device(seqset, device="cuda") -> DeviceSeqs:
     ts = torch.from_numpy(seq if len(seq) else np.zeros(1, np.uint8)).to(device)
     to = torch.from_numpy(offs).to(device)
     return DeviceSeqs(ts, to, int(len(offs) - 1), int(offs[-1]) if len(offs) else 0)
+
+
+def _host_array(ptr: int, n: int, dtype) -> np.ndarray:
+    """Copy of n elements at a host pointer owned by the library."""
+    out = np.empty(n, dtype=dtype)
+    if n:
+        C.memmove(out.ctypes.data, ptr, out.nbytes)
+    return out
 
 
 def _copy_to_host(ptr: int, n: int, dtype) -> np.ndarray:
@@ -141,17 +149,26 @@ class Result:
     def n_cands(self) -> int:
         return self._cands()[0]
 
+    @property
+    def on_host(self) -> bool:
+        return bool(self.lib.mt_result_on_host(self.h))
+
+    def times_ns(self) -> tuple[int, int]:
+        """(submit, done) steady-clock times of a served request."""
+        a, b = C.c_uint64(), C.c_uint64()
+        _check(self.lib.mt_result_times(self.h, C.byref(a), C.byref(b)), self.lib)
+        return a.value, b.value
+
     def to_host(self) -> dict:
         nr, co, ra, re = self._reads()
         nc, (g, d, h, a, ac) = self._cands()
         nt, (u, mu, un) = self._taxa()
+        cp = _host_array if self.on_host else _copy_to_host
         return dict(
-            cand_offsets=_copy_to_host(co, nr + 1, np.uint64), read_accepted=_copy_to_host(ra, nr, np.uint8),
-            read_E=_copy_to_host(re, nr, np.uint16), genome=_copy_to_host(g, nc, np.uint32),
-            diag=_copy_to_host(d, nc, np.int64), hits=_copy_to_host(h, nc, np.uint32),
-            approx=_copy_to_host(a, nc, np.uint16), accept=_copy_to_host(ac, nc, np.uint8),
-            unique=_copy_to_host(u, nt, np.uint64), multi=_copy_to_host(mu, nt, np.uint64),
-            unmapped=int(_copy_to_host(un, 1, np.uint64)[0]))
+            cand_offsets=cp(co, nr + 1, np.uint64), read_accepted=cp(ra, nr, np.uint8),
+            read_E=cp(re, nr, np.uint16), genome=cp(g, nc, np.uint32), diag=cp(d, nc, np.int64),
+            hits=cp(h, nc, np.uint32), approx=cp(a, nc, np.uint16), accept=cp(ac, nc, np.uint8),
+            unique=cp(u, nt, np.uint64), multi=cp(mu, nt, np.uint64), unmapped=int(cp(un, 1, np.uint64)[0]))
 
     def free(self) -> None:
         if self.h:
@@ -218,5 +235,61 @@ class Index:
     def __del__(self):
         try:
             self.free()
+        except Exception:
+            pass
+
+
+class Server:
+    """Continuous-batching request server over an Index (mt_server_*).
+
+    submit() takes HOST reads (a sequence set with .seq / .offsets) and
+    returns a request id; wait() returns that request's Result (host arrays),
+    or None if it is not finished within the timeout.  Both release the GIL
+    inside the library, so several Python threads can submit and wait.
+    """
+
+    def __init__(self, index: Index, mem_budget_bytes=0, max_batch_reads=0, n_streams=0, max_queued_requests=0,
+                 pinned_arena_bytes=0):
+        self.lib = index.lib
+        self.index = index  # the index must outlive the server
+        p = _abi.mt_server_params(mem_budget_bytes, max_batch_reads, n_streams, max_queued_requests,
+                                  pinned_arena_bytes)
+        h = C.c_void_p()
+        _check(self.lib.mt_server_create(index.h, C.byref(p), C.byref(h)), self.lib)
+        self.h = h.value
+
+    def submit(self, seqset, min_hits=3, top_n=3, e_mode=MT_E_FIXED, e_value=7) -> int:
+        seq = np.ascontiguousarray(seqset.seq, dtype=np.uint8)
+        offs = np.ascontiguousarray(seqset.offsets, dtype=np.uint64)
+        q = _abi.mt_query_params(min_hits, top_n, e_mode, e_value, MT_MODE_FUSED)
+        rid = C.c_uint64()
+        rc = self.lib.mt_server_submit(self.h, C.byref(q), seq.ctypes.data if len(seq) else None,
+                                       offs.ctypes.data, len(offs) - 1, C.byref(rid))
+        _check(rc, self.lib)
+        return rid.value
+
+    def wait(self, request_id: int, timeout_s: float | None = None):
+        t = -1 if timeout_s is None else int(timeout_s * 1e6)
+        h = C.c_void_p()
+        rc = self.lib.mt_server_wait(self.h, request_id, t, C.byref(h))
+        if rc == _abi.MT_ETIMEDOUT:
+            return None
+        _check(rc, self.lib)
+        return Result(h.value, self.lib)
+
+    def close(self) -> None:
+        if getattr(self, "h", None):
+            self.lib.mt_server_destroy(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
         except Exception:
             pass

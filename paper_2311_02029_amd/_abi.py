@@ -18,7 +18,8 @@ MT_MODE_PER_STAGE, MT_MODE_FUSED = 0, 1
 ABI_FUNCTIONS = (
     "mt_index_build", "mt_index_free", "mt_index_get_info", "mt_classify", "mt_result_reads",
     "mt_result_cands", "mt_result_taxa", "mt_result_free", "mt_last_timings", "mt_set_timing",
-    "mt_filter_pairs", "mt_trim", "mt_last_error", "mt_abi_version", "mt_last_stats",
+    "mt_filter_pairs", "mt_trim", "mt_last_error", "mt_abi_version", "mt_last_stats", "mt_server_create",
+    "mt_server_submit", "mt_server_wait", "mt_server_destroy", "mt_result_on_host", "mt_result_times",
 )
 
 
@@ -45,6 +46,12 @@ class mt_index_info(C.Structure):
 class mt_stats(C.Structure):
     _fields_ = [(f, C.c_uint64) for f in ("n_reads", "n_minimizers", "n_hits", "n_cands", "fused_reads",
                                           "fused_bases", "fused_minimizers", "fused_window_blocks", "fused_cands")]
+
+
+class mt_server_params(C.Structure):
+    _fields_ = [("mem_budget_bytes", C.c_uint64), ("max_batch_reads", C.c_uint64), ("n_streams", C.c_uint32),
+                ("max_queued_requests", C.c_uint32), ("pinned_arena_bytes", C.c_uint64),
+                ("reserved", C.c_uint32 * 4)]
 
 
 _lib = None
@@ -77,6 +84,12 @@ def load(path: str = LIB_PATH):
         "mt_last_error": (C.c_char_p, []),
         "mt_abi_version": (i32, []),
         "mt_last_stats": (i32, [C.POINTER(mt_stats)]),
+        "mt_server_create": (i32, [vp, C.POINTER(mt_server_params), pp]),
+        "mt_server_submit": (i32, [vp, C.POINTER(mt_query_params), vp, vp, u64, C.POINTER(u64)]),
+        "mt_server_wait": (i32, [vp, u64, C.c_int64, pp]),
+        "mt_server_destroy": (i32, [vp]),
+        "mt_result_on_host": (i32, [vp]),
+        "mt_result_times": (i32, [vp, C.POINTER(u64), C.POINTER(u64)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

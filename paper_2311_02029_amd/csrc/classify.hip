@@ -258,24 +258,21 @@ __global__ void k_compact(const u64 *__restrict__ read_hs, const u32 *__restrict
 
 // ----------------------------------------------------------------- reduce --
 
-__global__ void k_reduce(const u64 *__restrict__ cand_off, u64 n, const u32 *__restrict__ genome,
-                         const u16 *__restrict__ approx, const u16 *__restrict__ read_E,
-                         const u32 *__restrict__ taxon, u8 *__restrict__ read_accepted,
-                         unsigned long long *__restrict__ uniq, unsigned long long *__restrict__ multi,
-                         unsigned long long *__restrict__ unmapped) {
-    u64 r = (u64)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    u64 cs = cand_off[r], ce = cand_off[r + 1];
-    u32 E = read_E[r];
+// One read of the taxon step (Fig. 1 step 3a): its mapped taxa are the taxa of
+// its accepted candidates at the smallest count; one taxon counts as unique,
+// several as multi-mapped for each, none as unmapped.  Returns whether the
+// read has an accepted candidate.
+__device__ inline bool reduce_read(u64 cs, u64 ce, u32 E, const u32 *__restrict__ genome,
+                                   const u16 *__restrict__ approx, const u32 *__restrict__ taxon,
+                                   unsigned long long *uniq, unsigned long long *multi,
+                                   unsigned long long *unmapped) {
     u32 best = 0xFFFFFFFFu;
     for (u64 c = cs; c < ce; c++)
         if (approx[c] <= E && approx[c] < best) best = approx[c];
     if (best == 0xFFFFFFFFu) {
-        read_accepted[r] = 0;
         atomicAdd(unmapped, 1ull);
-        return;
+        return false;
     }
-    read_accepted[r] = 1;
     // Distinct taxa of the accepted candidates at the best count.
     u32 ntax = 0, first = 0;
     for (u64 c = cs; c < ce; c++) {
@@ -290,7 +287,7 @@ __global__ void k_reduce(const u64 *__restrict__ cand_off, u64 n, const u32 *__r
     }
     if (ntax == 1) {
         atomicAdd(&uniq[first], 1ull);
-        return;
+        return true;
     }
     for (u64 c = cs; c < ce; c++) {
         if (approx[c] != best) continue;
@@ -300,6 +297,45 @@ __global__ void k_reduce(const u64 *__restrict__ cand_off, u64 n, const u32 *__r
             if (approx[d] == best && taxon[genome[d]] == t) seen = true;
         if (!seen) atomicAdd(&multi[t], 1ull);
     }
+    return true;
+}
+
+__global__ void k_reduce(const u64 *__restrict__ cand_off, u64 n, const u32 *__restrict__ genome,
+                         const u16 *__restrict__ approx, const u16 *__restrict__ read_E,
+                         const u32 *__restrict__ taxon, u8 *__restrict__ read_accepted,
+                         unsigned long long *__restrict__ uniq, unsigned long long *__restrict__ multi,
+                         unsigned long long *__restrict__ unmapped) {
+    u64 r = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    read_accepted[r] = reduce_read(cand_off[r], cand_off[r + 1], read_E[r], genome, approx, taxon, uniq, multi,
+                                   unmapped);
+}
+
+// The taxon step per request slot of a served batch: reads [slot_off[s],
+// slot_off[s + 1]) count into counts[s] = {unique[n_taxa], multi[n_taxa],
+// unmapped}.
+__global__ void k_reduce_slots(const u64 *__restrict__ cand_off, u64 n, const u32 *__restrict__ genome,
+                               const u16 *__restrict__ approx, const u16 *__restrict__ read_E,
+                               const u32 *__restrict__ taxon, const u64 *__restrict__ slot_off, u32 n_slots,
+                               unsigned long long *const *__restrict__ counts, u32 n_taxa) {
+    u64 r = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    u32 lo = 0, hi = n_slots;  // last slot with slot_off[s] <= r
+    while (hi - lo > 1) {
+        u32 mid = (lo + hi) >> 1;
+        if (slot_off[mid] <= r) lo = mid; else hi = mid;
+    }
+    unsigned long long *c = counts[lo];
+    reduce_read(cand_off[r], cand_off[r + 1], read_E[r], genome, approx, taxon, c, c + n_taxa, c + 2 * (u64)n_taxa);
+}
+
+void launch_reduce_slots(const mt_result &res, const mt_index &ix, const u64 *slot_off, u32 n_slots,
+                         unsigned long long *const *counts, hipStream_t s) {
+    if (res.n_reads == 0 || n_slots == 0) return;
+    k_reduce_slots<<<grid_for(res.n_reads, 256), 256, 0, s>>>(res.cand_off.p, res.n_reads, res.genome.p,
+                                                              res.approx.p, res.read_E.p, ix.taxon.p, slot_off,
+                                                              n_slots, counts, ix.n_taxa);
+    MT_HIP(hipGetLastError());
 }
 
 // ----------------------------------------------------------------- driver --
@@ -455,23 +491,7 @@ void mt_result::alloc_cands(mt::u64 c) {
 
 using mt::Error;
 
-template <class F>
-static int guarded(const char *what, F &&f) {
-    try {
-        f();
-        mt::set_last_error("");
-        return MT_OK;
-    } catch (const Error &e) {
-        mt::set_last_error(std::string(what) + ": " + e.what());
-        return e.status;
-    } catch (const std::bad_alloc &) {
-        mt::set_last_error(std::string(what) + ": host allocation failed");
-        return MT_ENOMEM;
-    } catch (const std::exception &e) {
-        mt::set_last_error(std::string(what) + ": " + e.what());
-        return MT_EINTERNAL;
-    }
-}
+using mt::guarded;
 
 extern "C" int mt_classify(const mt_index *index, const mt_query_params *params, const mt_seqs *reads,
                            void *stream, mt_result **out) {
@@ -526,9 +546,9 @@ extern "C" int mt_result_reads(const mt_result *res, uint64_t *n_reads, const ui
         return MT_EINVAL;
     }
     if (n_reads) *n_reads = res->n_reads;
-    if (cand_offsets) *cand_offsets = res->cand_off.p;
-    if (read_accepted) *read_accepted = res->read_accepted.p;
-    if (read_E) *read_E = res->read_E.p;
+    if (cand_offsets) *cand_offsets = res->on_host ? res->h.cand_off.data() : res->cand_off.p;
+    if (read_accepted) *read_accepted = res->on_host ? res->h.read_accepted.data() : res->read_accepted.p;
+    if (read_E) *read_E = res->on_host ? res->h.read_E.data() : res->read_E.p;
     return MT_OK;
 }
 
@@ -540,11 +560,12 @@ extern "C" int mt_result_cands(const mt_result *res, uint64_t *n_cands, const ui
         return MT_EINVAL;
     }
     if (n_cands) *n_cands = res->n_cands;
-    if (genome) *genome = res->genome.p;
-    if (diag) *diag = res->diag.p;
-    if (hits) *hits = res->hits.p;
-    if (approx) *approx = res->approx.p;
-    if (accept) *accept = res->accept.p;
+    const bool h = res->on_host;
+    if (genome) *genome = h ? res->h.genome.data() : res->genome.p;
+    if (diag) *diag = h ? res->h.diag.data() : res->diag.p;
+    if (hits) *hits = h ? res->h.hits.data() : res->hits.p;
+    if (approx) *approx = h ? res->h.approx.data() : res->approx.p;
+    if (accept) *accept = h ? res->h.accept.data() : res->accept.p;
     return MT_OK;
 }
 
@@ -555,9 +576,28 @@ extern "C" int mt_result_taxa(const mt_result *res, uint32_t *n_taxa, const uint
         return MT_EINVAL;
     }
     if (n_taxa) *n_taxa = res->n_taxa;
+    if (res->on_host) {
+        const mt::u64 *c = res->h.counts.data();
+        if (unique_reads) *unique_reads = c;
+        if (multi_reads) *multi_reads = c + res->n_taxa;
+        if (unmapped) *unmapped = c + 2 * (mt::u64)res->n_taxa;
+        return MT_OK;
+    }
     if (unique_reads) *unique_reads = res->uniq.p;
     if (multi_reads) *multi_reads = res->multi.p;
     if (unmapped) *unmapped = res->unmapped.p;
+    return MT_OK;
+}
+
+extern "C" int mt_result_on_host(const mt_result *res) { return res && res->on_host ? 1 : 0; }
+
+extern "C" int mt_result_times(const mt_result *res, uint64_t *submit_ns, uint64_t *done_ns) {
+    if (!res) {
+        mt::set_last_error("mt_result_times: null result");
+        return MT_EINVAL;
+    }
+    if (submit_ns) *submit_ns = res->submit_ns;
+    if (done_ns) *done_ns = res->done_ns;
     return MT_OK;
 }
 

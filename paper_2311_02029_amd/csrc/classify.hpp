@@ -17,6 +17,20 @@ struct mt_result {
     mt::DBuf<mt::u64> uniq, multi;    // n_taxa
     mt::DBuf<mt::u64> unmapped;       // 1
     void alloc_cands(mt::u64 c);
+    // Served results live in host memory (the DBufs above stay empty).
+    bool on_host = false;
+    struct Host {
+        std::vector<mt::u64> cand_off;
+        std::vector<mt::u8> read_accepted;
+        std::vector<mt::u16> read_E;
+        std::vector<mt::u32> genome;
+        std::vector<mt::i64> diag;
+        std::vector<mt::u32> hits;
+        std::vector<mt::u16> approx;
+        std::vector<mt::u8> accept;
+        std::vector<mt::u64> counts;  // unique[n_taxa], multi[n_taxa], unmapped
+    } h;
+    mt::u64 submit_ns = 0, done_ns = 0;
 };
 
 namespace mt {
@@ -66,5 +80,10 @@ void classify_per_stage(const mt_index &ix, const mt_query_params &q, const mt_s
 void classify_fused(const mt_index &ix, const mt_query_params &q, const mt_seqs &reads, ReadBatch &rb,
                     mt_result &res, Timer &tm, hipStream_t s);
 void launch_max_u16(const u16 *v, u64 n, u32 *out, hipStream_t s);
+// The taxon step of a batch that holds several requests: reads
+// [slot_off[s], slot_off[s+1]) add into counts[s] = {unique[n_taxa],
+// multi[n_taxa], unmapped} (device arrays; slot_off and counts on the device).
+void launch_reduce_slots(const mt_result &res, const mt_index &ix, const u64 *slot_off, u32 n_slots,
+                         unsigned long long *const *counts, hipStream_t s);
 
 }  // namespace mt

@@ -134,4 +134,24 @@ mt_stats &last_stats();
 // Validation flags the kernels raise, decoded into an error.
 void check_flags(u32 flags);
 
+// Runs f as the body of an ABI call: maps exceptions to an mt_status and
+// records the message for mt_last_error.
+template <class F>
+int guarded(const char *what, F &&f) {
+    try {
+        f();
+        set_last_error("");
+        return MT_OK;
+    } catch (const Error &e) {
+        set_last_error(std::string(what) + ": " + e.what());
+        return e.status;
+    } catch (const std::bad_alloc &) {
+        set_last_error(std::string(what) + ": host allocation failed");
+        return MT_ENOMEM;
+    } catch (const std::exception &e) {
+        set_last_error(std::string(what) + ": " + e.what());
+        return MT_EINTERNAL;
+    }
+}
+
 }  // namespace mt

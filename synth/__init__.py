@@ -270,12 +270,34 @@ def workload_strain_reads(gen: Genomes, n_reads: int = 10_000_000, seed: int = 1
 
 
 def request_trace(seed: int, n_requests: int, qps: float, max_reads: int = 50_000,
-                  len_range=(100, 250)):
+                  len_range=(100, 250), lengths=None):
     """Poisson arrivals at `qps`; each request has U{1..max_reads} reads of one
-    length drawn from U{len_range}.  Returns a list of (arrival_s, n_reads, length)."""
+    length drawn from U{len_range} (or uniformly from `lengths` when given).
+    Returns a list of (arrival_s, n_reads, length)."""
     rng = np.random.default_rng(seed)
     gaps = rng.exponential(1.0 / qps, n_requests)
     t = np.cumsum(gaps)
     nr = rng.integers(1, max_reads + 1, n_requests)
-    ln = rng.integers(len_range[0], len_range[1] + 1, n_requests)
+    if lengths is None:
+        ln = rng.integers(len_range[0], len_range[1] + 1, n_requests)
+    else:
+        ln = rng.choice(np.asarray(lengths, dtype=np.int64), n_requests)
     return [(float(a), int(b), int(c)) for a, b, c in zip(t, nr, ln)]
+
+
+SERVED_LENGTHS = tuple(int(v) for v in np.linspace(100, 250, 16).round())
+
+
+def served_read_pool(gen: Genomes, n_per_length: int = 50_000, lengths=SERVED_LENGTHS, seed: int = 3,
+                     p_sub: float = 0.0045, p_indel: float = 0.0005) -> dict:
+    """Per read length, n_per_length reads at 0.5% error (0.45% substitutions,
+    0.05% indels).  A served request of n reads of length m takes the first n
+    reads of pool[m] (request_reads), so a long trace needs no more generation."""
+    rng = np.random.default_rng(seed)
+    return {m: make_reads(rng, gen, np.full(n_per_length, m), p_sub, p_indel)[0] for m in lengths}
+
+
+def request_reads(pool: dict, n: int, m: int) -> SeqSet:
+    """The first n reads of pool[m] (views, no copy)."""
+    s = pool[m]
+    return SeqSet(seq=s.seq[:n * m], offsets=s.offsets[:n + 1])

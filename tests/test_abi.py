@@ -39,15 +39,19 @@ def test_struct_layouts_match_header(tmp_path):
 #include <stddef.h>
 #include "metatrinity.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(mt_seqs), sizeof(mt_index_params), sizeof(mt_query_params),
-         sizeof(mt_index_info), offsetof(mt_query_params, mode), offsetof(mt_index_info, k));
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(mt_seqs), sizeof(mt_index_params),
+         sizeof(mt_query_params), sizeof(mt_index_info), offsetof(mt_query_params, mode),
+         offsetof(mt_index_info, k), sizeof(mt_server_params), offsetof(mt_server_params, pinned_arena_bytes),
+         sizeof(mt_stats));
   return 0;
 }''')
     exe = tmp_path / "sizes"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)])
     got = [int(v) for v in subprocess.check_output([str(exe)]).split()]
     want = [C.sizeof(_abi.mt_seqs), C.sizeof(_abi.mt_index_params), C.sizeof(_abi.mt_query_params),
-            C.sizeof(_abi.mt_index_info), _abi.mt_query_params.mode.offset, _abi.mt_index_info.k.offset]
+            C.sizeof(_abi.mt_index_info), _abi.mt_query_params.mode.offset, _abi.mt_index_info.k.offset,
+            C.sizeof(_abi.mt_server_params), _abi.mt_server_params.pinned_arena_bytes.offset,
+            C.sizeof(_abi.mt_stats)]
     assert got == want
 
 
@@ -58,3 +62,10 @@ def test_null_arguments_are_errors_not_crashes():
     assert b"null" in lib.mt_last_error()
     assert lib.mt_classify(None, None, None, None, C.byref(h)) == _abi.MT_EINVAL
     assert lib.mt_result_reads(None, None, None, None, None) == _abi.MT_EINVAL
+    assert lib.mt_server_create(None, None, C.byref(h)) == _abi.MT_EINVAL
+    rid = C.c_uint64()
+    assert lib.mt_server_submit(None, None, None, None, 0, C.byref(rid)) == _abi.MT_EINVAL
+    assert lib.mt_server_wait(None, 1, 0, C.byref(h)) == _abi.MT_EINVAL
+    assert lib.mt_server_destroy(None) == _abi.MT_OK
+    assert lib.mt_result_on_host(None) == 0
+    assert lib.mt_result_times(None, None, None) == _abi.MT_EINVAL
