@@ -208,12 +208,36 @@ def serving_bench(mt, ix, pool, seconds: float = 2.0, loads=(0.5, 0.8, 0.95), th
     return out
 
 
+def measured_valu(kernel: str):
+    """VALU wave-instructions per dispatch from the committed rocprofv3 SQ_INSTS_VALU
+    record of this kernel, or None when it is missing or was taken on a different
+    kernel source."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_fused_valu_counters_500mbp_1m.json")
+    if kernel != "fused" or not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    h = hashlib.sha256()
+    for src in rec["kernel_sources"]:
+        h.update(open(os.path.join(ROOT, src), "rb").read())
+    if h.hexdigest() != rec["source_sha256"]:
+        return None
+    return float(rec["per_dispatch"]["SQ_INSTS_VALU"])
+
+
+# Integer VALU peak of the MI355X: 256 CUs x 4 SIMD16 units x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s,
+# i.e. one wave64 VALU instruction per CU per cycle.
+VALU_WAVE_INSTR_PEAK = 256 * 2.4e9
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--mode", default="fused", choices=["fused", "per_stage"])
+    ap.add_argument("--mode", default="fused", choices=["fused", "graph", "per_stage"],
+                    help="fused: the fused kernel (launched eagerly); graph: the same launches replayed as one "
+                         "HIP graph; per_stage: one launch per step")
     ap.add_argument("--E", type=int, default=7)
     ap.add_argument("--reads", type=int, default=1_000_000)
     ap.add_argument("--workload", default="batched", choices=["batched", "uneven", "strains"],
@@ -300,7 +324,7 @@ def main() -> int:
         f"{info['device_bytes'] / 2**30:.2f} GiB")
     del dgen
 
-    mode = mt.MT_MODE_FUSED if args.mode == "fused" else mt.MT_MODE_PER_STAGE
+    mode = {"fused": mt.MT_MODE_FUSED, "graph": mt.MT_MODE_FUSED_GRAPH, "per_stage": mt.MT_MODE_PER_STAGE}[args.mode]
     q = dict(min_hits=3, top_n=3, e_mode=e_mode, e_value=e_value, mode=mode)
 
     for i in range(args.warmup):
@@ -351,6 +375,11 @@ def main() -> int:
                         "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                         "traffic": measured_traffic(dom) if args.workload == "batched" else None,
                         "avg_ms": round(stages[dom], 4), "algorithmic_bytes": int(alg)}
+            vi = measured_valu(dom) if args.workload == "batched" and args.E == 7 else None
+            if vi is not None:
+                # counter-measured VALU issue against the integer VALU peak (same live duration)
+                roofline["valu"] = {"wave_instructions": int(vi), "peak_lane_ops_per_s": VALU_WAVE_INSTR_PEAK * 64,
+                                    "issue_frac": round(vi / (dur_s * VALU_WAVE_INSTR_PEAK), 4)}
         else:
             roofline = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": None, "traffic": None, "avg_ms": round(stages[dom], 4)}

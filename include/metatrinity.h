@@ -90,8 +90,10 @@ enum {
 /* Execution form; every form gives bit-identical results. */
 enum {
     MT_MODE_PER_STAGE = 0,   /* one kernel launch per step of the path */
-    MT_MODE_FUSED = 1        /* one fused seed-count + filter kernel for short reads,
+    MT_MODE_FUSED = 1,       /* one fused seed-count + filter kernel for short reads,
                                 per-stage kernels for the rest */
+    MT_MODE_FUSED_GRAPH = 2  /* MT_MODE_FUSED with its launches captured and replayed as
+                                one HIP graph (needs a stream other than NULL) */
 };
 
 typedef struct mt_query_params {

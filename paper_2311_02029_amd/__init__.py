@@ -14,7 +14,7 @@ import numpy as np
 
 from . import _abi
 from ._abi import (MT_E_CEIL_PERMILLE, MT_E_FIXED, MT_E_FLOOR_PERMILLE, MT_MODE_FUSED,  # noqa: F401
-                   MT_MODE_PER_STAGE, MT_OK)
+                   MT_MODE_FUSED_GRAPH, MT_MODE_PER_STAGE, MT_OK)
 
 __all__ = ["MTError", "DeviceSeqs", "Index", "Result", "Server", "to_device", "mt_set_timing", "last_timings"]
 
@@ -69,6 +69,18 @@ def _host_array(ptr: int, n: int, dtype) -> np.ndarray:
     if n:
         C.memmove(out.ctypes.data, ptr, out.nbytes)
     return out
+
+
+_graph_streams = {}
+
+
+def _graph_stream():
+    """A torch stream per device for the graph form when the caller is on the null stream."""
+    torch = _torch()
+    dev = torch.cuda.current_device()
+    if dev not in _graph_streams:
+        _graph_streams[dev] = torch.cuda.Stream(device=dev)
+    return _graph_streams[dev]
 
 
 def _copy_to_host(ptr: int, n: int, dtype) -> np.ndarray:
@@ -210,7 +222,17 @@ class Index:
                  mode=MT_MODE_PER_STAGE, stream=None) -> Result:
         q = _abi.mt_query_params(min_hits, top_n, e_mode, e_value, mode)
         h = C.c_void_p()
-        rc = self.lib.mt_classify(self.h, C.byref(q), C.byref(reads.abi()), _stream_ptr(stream), C.byref(h))
+        sp = _stream_ptr(stream)
+        if mode == MT_MODE_FUSED_GRAPH and sp == 0:
+            # a graph is captured on a stream of its own, ordered after and before the null stream's work
+            torch = _torch()
+            cur = torch.cuda.current_stream()
+            own = _graph_stream()
+            own.wait_stream(cur)
+            rc = self.lib.mt_classify(self.h, C.byref(q), C.byref(reads.abi()), int(own.cuda_stream), C.byref(h))
+            cur.wait_stream(own)
+        else:
+            rc = self.lib.mt_classify(self.h, C.byref(q), C.byref(reads.abi()), sp, C.byref(h))
         _check(rc, self.lib)
         return Result(h.value, self.lib)
 

@@ -358,7 +358,7 @@ void ReadBatch::prepare(const mt_seqs &reads, u32 e_mode, u32 e_value, hipStream
 void validate_query(const mt_query_params &q) {
     MT_REQUIRE(q.e_mode <= MT_E_FLOOR_PERMILLE, "unknown e_mode");
     MT_REQUIRE(q.e_mode != MT_E_FIXED || q.e_value <= 65534, "E must be at most 65534");
-    MT_REQUIRE(q.mode <= MT_MODE_FUSED, "unknown mode");
+    MT_REQUIRE(q.mode <= MT_MODE_FUSED_GRAPH, "unknown mode");
     MT_REQUIRE(q.reserved[0] == 0 && q.reserved[1] == 0 && q.reserved[2] == 0, "reserved fields must be 0");
 }
 
@@ -514,19 +514,19 @@ extern "C" int mt_classify(const mt_index *index, const mt_query_params *params,
             tm.begin(s);
             mt::mt_result_init(*res, reads->n, index->n_taxa, s);
             mt::ReadBatch rb;
-            if (params->mode == MT_MODE_FUSED) {
-                mt::classify_fused(*index, *params, *reads, rb, *res, tm, s);
+            if (params->mode != MT_MODE_PER_STAGE) {
+                mt::classify_fused(*index, *params, *reads, rb, *res, tm, s, params->mode == MT_MODE_FUSED_GRAPH);
             } else {
                 rb.prepare(*reads, params->e_mode, params->e_value, s);
                 MT_HIP(hipMemcpyAsync(res->read_E.p, rb.read_E.p, (reads->n ? reads->n : 1) * sizeof(mt::u16),
                                       hipMemcpyDeviceToDevice, s));
                 tm.mark("pack");
                 mt::classify_per_stage(*index, *params, *reads, rb, *res, tm, s);
+                mt::u32 f = 0;
+                mt::read_back(s, rb.flags.p, &f, sizeof f);
+                mt::check_flags(f);
+                mt::read_back(s, res->cand_off.p + reads->n, &res->n_cands, sizeof(mt::u64));
             }
-            mt::u32 f = 0;
-            mt::read_back(s, rb.flags.p, &f, sizeof f);
-            mt::check_flags(f);
-            mt::read_back(s, res->cand_off.p + reads->n, &res->n_cands, sizeof(mt::u64));
             mt::last_stats().n_cands = res->n_cands;
         }
         tm.finish();

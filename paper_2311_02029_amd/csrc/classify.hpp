@@ -77,8 +77,10 @@ void validate_query(const mt_query_params &q);
 void mt_result_init(mt_result &res, u64 n, u32 n_taxa, hipStream_t s);
 void classify_per_stage(const mt_index &ix, const mt_query_params &q, const mt_seqs &reads, ReadBatch &rb,
                         mt_result &res, Timer &tm, hipStream_t s);
+// Fused form.  Checks the call's flags and sets res.n_cands before it
+// returns; graph = launch the sequence as one captured HIP graph.
 void classify_fused(const mt_index &ix, const mt_query_params &q, const mt_seqs &reads, ReadBatch &rb,
-                    mt_result &res, Timer &tm, hipStream_t s);
+                    mt_result &res, Timer &tm, hipStream_t s, bool graph);
 void launch_max_u16(const u16 *v, u64 n, u32 *out, hipStream_t s);
 // The taxon step of a batch that holds several requests: reads
 // [slot_off[s], slot_off[s+1]) add into counts[s] = {unique[n_taxa],

@@ -47,39 +47,55 @@ __device__ inline void long_blocks(int m, int E, int &nrb, int &nwb) {
     nwb = ((m + 2 * E + 190) >> 6) + 2;
 }
 
-__global__ void k_pair_class(FilterArgs a, u64 n_cap, u32 *__restrict__ count, u8 *__restrict__ cls) {
-    u64 p = (u64)blockIdx.x * blockDim.x + threadIdx.x;
-    u64 np = a.n_dev ? *a.n_dev : a.n_host;
-    if (p >= np || p >= n_cap) return;
+// Class of pair p (0..3: the bucket kernels; 4: the general kernel).
+__device__ inline u8 pair_class(const FilterArgs &a, u64 p) {
     u32 r, g, err;
     int E;
     bool ok;
     pair_fields(a, p, r, g, E, ok, err);
-    u8 c;
-    if (!ok) {
-        c = 4;  // the general kernel reports the error
-    } else if (E <= 7) {
-        c = 0;
-    } else if (E <= 15) {
-        c = 1;
-    } else if (E <= 31) {
-        c = 2;
-    } else {
-        int nrb, nwb;
-        long_blocks(read_len(a, r), E, nrb, nwb);
-        c = nrb + nwb <= LONG_BLOCKS ? 3 : 4;
+    if (!ok) return 4;  // the general kernel reports the error
+    if (E <= 7) return 0;
+    if (E <= 15) return 1;
+    if (E <= 31) return 2;
+    int nrb, nwb;
+    long_blocks(read_len(a, r), E, nrb, nwb);
+    return nrb + nwb <= LONG_BLOCKS ? 3 : 4;
+}
+
+// Counting and placing pairs use one atomic per wavefront and class: the
+// lanes of a class are ranked by ballot, and their lowest lane adds them all.
+__global__ void k_pair_class(FilterArgs a, u64 n_cap, u32 *__restrict__ count, u8 *__restrict__ cls) {
+    const u64 p = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    const u64 np = a.n_dev ? *a.n_dev : a.n_host;
+    const bool active = p < np && p < n_cap;
+    const int lane = threadIdx.x & 63;
+    u8 c = 0xFF;
+    if (active) {
+        c = pair_class(a, p);
+        cls[p] = c;
     }
-    cls[p] = c;
-    atomicAdd(&count[c], 1u);
+    for (int k = 0; k < N_CLASSES; k++) {
+        const u64 m = __ballot(c == k);
+        if (m && lane == __builtin_ctzll(m)) atomicAdd(&count[k], (u32)__builtin_popcountll(m));
+    }
 }
 
 __global__ void k_pair_scatter(FilterArgs a, u64 n_cap, const u8 *__restrict__ cls, const u32 *__restrict__ base,
                                u32 *__restrict__ cursor, u32 *__restrict__ idx) {
-    u64 p = (u64)blockIdx.x * blockDim.x + threadIdx.x;
-    u64 np = a.n_dev ? *a.n_dev : a.n_host;
-    if (p >= np || p >= n_cap) return;
-    u8 c = cls[p];
-    idx[base[c] + atomicAdd(&cursor[c], 1u)] = (u32)p;
+    const u64 p = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    const u64 np = a.n_dev ? *a.n_dev : a.n_host;
+    const bool active = p < np && p < n_cap;
+    const int lane = threadIdx.x & 63;
+    const u8 c = active ? cls[p] : (u8)0xFF;
+    for (int k = 0; k < N_CLASSES; k++) {
+        const u64 m = __ballot(c == k);
+        if (!m) continue;
+        const int leader = __builtin_ctzll(m);
+        u32 first = 0;
+        if (lane == leader) first = atomicAdd(&cursor[k], (u32)__builtin_popcountll(m));
+        first = __shfl(first, leader, 64);
+        if (c == k) idx[base[k] + first + __builtin_popcountll(m & ((1ull << lane) - 1))] = (u32)p;
+    }
 }
 
 // G lanes per pair over the bucket idx[0, n).

@@ -70,7 +70,8 @@ struct FusedArgs {
     u32 *fb_list;
     u32 *fb_count;
     u32 *flags;
-    unsigned long long *stats;
+    const u32 *gate;  // offsets check result: nonzero skips the whole launch
+    u64 *stats_part;  // ST_COUNT work counts per block
 };
 
 // A read whose candidates wait in the filter queue (per-wave LDS).
@@ -376,6 +377,7 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
 
     // wid is wave-uniform; saying so keeps every per-read value (read index,
     // length, E, loop bounds) in scalar registers.
+    if (*a.gate) return;  // malformed offsets: nothing may be read through them
     const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     u64 *hh = sh_h[wid];
     u64 *tkey = sh_tkey[wid];
@@ -416,7 +418,10 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
         const int E = Ewide > 65535 ? 65535 : (int)Ewide;
         if (lane == 0) a.read_E[r] = (u16)E;
         if (m > F_MAX_M || E > F_MAX_E) {
-            if (lane == 0) a.fb_list[atomicAdd(a.fb_count, 1u)] = (u32)r;
+            if (lane == 0) {
+                a.fb_list[atomicAdd(a.fb_count, 1u)] = (u32)r;
+                a.ncand[r] = 0;  // until the per-stage kernels fill it in
+            }
             if (rn < a.n) issue_read_bytes(a, rn, lane, cur);
             continue;
         }
@@ -451,6 +456,7 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
         }
         if (ballot64(bad)) {
             wflags |= ERR_BAD_BYTE;
+            if (lane == 0) a.ncand[r] = 0;  // the call fails; its compaction still runs
             if (rn < a.n) issue_read_bytes(a, rn, lane, cur);
             continue;
         }
@@ -559,7 +565,10 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
                 tkey[t] = ~0ull;
                 tcnt[t] = 0;
             }
-            if (lane == 0) a.fb_list[atomicAdd(a.fb_count, 1u)] = (u32)r;
+            if (lane == 0) {
+                a.fb_list[atomicAdd(a.fb_count, 1u)] = (u32)r;
+                a.ncand[r] = 0;
+            }
             cur = nxt;
             wave_sync();
             continue;
@@ -651,7 +660,52 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
     if (lane == 0) {
         if (used) wflags |= ERR_INTERNAL;  // every queued read is finalized by now
         if (wflags) atomicOr(a.flags, wflags);
-        for (int i = 0; i < ST_COUNT; i++) atomicAdd(&a.stats[i], wst[i]);
+    }
+    // work counts: one record per block, summed by k_fused_summary
+    __syncthreads();
+    if (threadIdx.x < ST_COUNT) {
+        u64 t = 0;
+        for (int w = 0; w < F_WPB; w++) t += sh_stats[w][threadIdx.x];
+        a.stats_part[(u64)blockIdx.x * ST_COUNT + threadIdx.x] = t;
+    }
+}
+
+// Control words of one fused call: [0] offsets check, [1] run flags,
+// [2] fallback count.
+constexpr int CTL_GATE = 0, CTL_FLAGS = 1, CTL_FB = 2, CTL_WORDS = 4;
+
+// Host-visible summary of one fused call, read back with a single copy.
+struct FusedSummary {
+    u32 gate, flags, nfb, pad;
+    u64 n_cands;
+    u64 stats[ST_COUNT];
+};
+
+__global__ void k_fused_init(u32 *__restrict__ ctl) {
+    if (threadIdx.x < CTL_WORDS) ctl[threadIdx.x] = 0;
+}
+
+__global__ void k_fused_summary(const u32 *__restrict__ ctl, const u64 *__restrict__ cand_end,
+                                const u64 *__restrict__ stats_part, u32 blocks, FusedSummary *__restrict__ out) {
+    __shared__ u64 part[ST_COUNT][64];
+    const int t = threadIdx.x;  // 64 * ST_COUNT threads
+    const int st = t / 64, l = t % 64;
+    u64 acc = 0;
+    if (!ctl[CTL_GATE])
+        for (u32 b = l; b < blocks; b += 64) acc += stats_part[(u64)b * ST_COUNT + st];
+    part[st][l] = acc;
+    __syncthreads();
+    if (l == 0) {
+        u64 v = 0;
+        for (int i = 0; i < 64; i++) v += part[st][i];
+        out->stats[st] = v;
+    }
+    if (t == 0) {
+        out->gate = ctl[CTL_GATE];
+        out->flags = ctl[CTL_FLAGS];
+        out->nfb = ctl[CTL_FB];
+        out->pad = 0;
+        out->n_cands = ctl[CTL_GATE] ? 0 : *cand_end;
     }
 }
 
@@ -709,14 +763,16 @@ __global__ void k_add_u64(unsigned long long *__restrict__ dst, const u64 *__res
     if (i < n) dst[i] += src[i];
 }
 
-__global__ void k_compact_staged(const u64 *__restrict__ cand_off, u64 n, u32 top_n,
+__global__ void k_compact_staged(const u32 *__restrict__ gate, const u64 *__restrict__ cand_off, u64 n, u32 top_n,
                                  const u32 *__restrict__ st_genome, const i64 *__restrict__ st_diag,
                                  const u32 *__restrict__ st_hits, const u16 *__restrict__ st_approx,
                                  const u8 *__restrict__ st_accept, u32 *__restrict__ genome, i64 *__restrict__ diag,
                                  u32 *__restrict__ hits, u16 *__restrict__ approx, u8 *__restrict__ accept) {
     u64 r = (u64)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;
+    if (r >= n || *gate) return;
     u64 o = cand_off[r], c = cand_off[r + 1] - o;
+    if (c > top_n) c = top_n;
+    if (o > n * top_n - c) return;  // never past the candidate capacity
     for (u64 i = 0; i < c; i++) {
         u64 s = r * top_n + i;
         genome[o + i] = st_genome[s];
@@ -727,8 +783,80 @@ __global__ void k_compact_staged(const u64 *__restrict__ cand_off, u64 n, u32 to
     }
 }
 
+// The launches of one fused call once its buffers exist: no host
+// synchronization and no memset, so the sequence can also be captured and
+// replayed as one HIP graph.
+struct FusedLaunch {
+    FusedArgs a;
+    u32 *ctl;
+    u64 n;
+    u32 N;
+    unsigned blocks;
+    u64 total;
+    mt_result *res;
+    FusedSummary *sum;
+};
+
+static void enqueue_fused(const FusedLaunch &L, Timer *tm, hipStream_t s) {
+    const FusedArgs &a = L.a;
+    k_fused_init<<<1, 64, 0, s>>>(L.ctl);
+    k_check_reads<<<grid_for(L.n, 256), 256, 0, s>>>(a.off, L.n, L.total, L.ctl + CTL_GATE);
+    if (tm) tm->mark("check");
+    k_fused<<<L.blocks, 64 * F_WPB, 0, s>>>(a);
+    if (tm) tm->mark("fused");
+    scan_u32(a.ncand, L.res->cand_off.p, L.n, s);
+    k_compact_staged<<<grid_for(L.n, 256), 256, 0, s>>>(L.ctl + CTL_GATE, L.res->cand_off.p, L.n, L.N, a.st_genome,
+                                                        a.st_diag, a.st_hits, a.st_approx, a.st_accept,
+                                                        L.res->genome.p, L.res->diag.p, L.res->hits.p,
+                                                        L.res->approx.p, L.res->accept.p);
+    k_fused_summary<<<1, 64 * ST_COUNT, 0, s>>>(L.ctl, L.res->cand_off.p + L.n, a.stats_part, L.blocks, L.sum);
+    MT_HIP(hipGetLastError());
+    if (tm) tm->mark("compact");
+}
+
+// One executable graph per host thread, updated in place when a new capture
+// has the same shape (only kernel arguments differ) and rebuilt otherwise.
+struct GraphCache {
+    hipGraphExec_t exec = nullptr;
+    ~GraphCache() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+    }
+};
+static thread_local GraphCache g_graph;
+
+static void launch_fused_graph(const FusedLaunch &L, hipStream_t s) {
+    if (s == nullptr) throw Error(MT_EINVAL, "the graph form needs a stream other than the null stream");
+    hipGraph_t graph = nullptr;
+    MT_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+    try {
+        enqueue_fused(L, nullptr, s);
+    } catch (...) {
+        (void)hipStreamEndCapture(s, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        throw;
+    }
+    MT_HIP(hipStreamEndCapture(s, &graph));
+    bool updated = false;
+    if (g_graph.exec) {
+        hipGraphNode_t err_node = nullptr;
+        hipGraphExecUpdateResult ur;
+        updated = hipGraphExecUpdate(g_graph.exec, graph, &err_node, &ur) == hipSuccess &&
+                  ur == hipGraphExecUpdateSuccess;
+        if (!updated) {
+            (void)hipGetLastError();
+            (void)hipGraphExecDestroy(g_graph.exec);
+            g_graph.exec = nullptr;
+        }
+    }
+    hipError_t e = hipSuccess;
+    if (!updated) e = hipGraphInstantiate(&g_graph.exec, graph, nullptr, nullptr, 0);
+    if (e == hipSuccess) e = hipGraphLaunch(g_graph.exec, s);
+    (void)hipGraphDestroy(graph);
+    MT_HIP(e);
+}
+
 void classify_fused(const mt_index &ix, const mt_query_params &q, const mt_seqs &reads, ReadBatch &rb,
-                    mt_result &res, Timer &tm, hipStream_t s) {
+                    mt_result &res, Timer &tm, hipStream_t s, bool graph) {
     const u64 n = reads.n;
     const u32 N = q.top_n;
     if (N == 0 || N > (u32)F_MAX_TOPN) {
@@ -737,28 +865,35 @@ void classify_fused(const mt_index &ix, const mt_query_params &q, const mt_seqs 
         MT_HIP(hipMemcpyAsync(res.read_E.p, rb.read_E.p, (n ? n : 1) * sizeof(u16), hipMemcpyDeviceToDevice, s));
         tm.mark("pack");
         classify_per_stage(ix, q, reads, rb, res, tm, s);
+        u32 f = 0;
+        read_back(s, rb.flags.p, &f, sizeof f);
+        check_flags(f);
+        read_back(s, res.cand_off.p + n, &res.n_cands, sizeof(u64));
         return;
     }
     rb.n = n;
-    rb.flags.alloc(1);
-    MT_HIP(hipMemsetAsync(rb.flags.p, 0, sizeof(u32), s));
-    if (n == 0) return;
-    k_check_reads<<<grid_for(n, 256), 256, 0, s>>>(reads.offsets, n, reads.total, rb.flags.p);
-    MT_HIP(hipGetLastError());
-    u32 f0 = 0;
-    read_back(s, rb.flags.p, &f0, sizeof f0);
-    check_flags(f0);
-    tm.mark("check");
+    if (n == 0) {
+        res.n_cands = 0;
+        return;
+    }
 
-    DBuf<u32> st_genome(n * N), st_hits(n * N), ncand(n), fb_list(n), fb_count(1);
+    int dev = 0, cus = 0;
+    MT_HIP(hipGetDevice(&dev));
+    MT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    u64 blocks = (n + F_WPB - 1) / F_WPB;
+    const u64 cap = (u64)cus * 16;
+    if (blocks > cap) blocks = cap;
+
+    DBuf<u32> st_genome(n * N), st_hits(n * N), ncand(n), fb_list(n), ctl(CTL_WORDS);
     DBuf<i64> st_diag(n * N);
     DBuf<u16> st_approx(n * N);
     DBuf<u8> st_accept(n * N);
-    DBuf<unsigned long long> stats(ST_COUNT);
-    MT_HIP(hipMemsetAsync(fb_count.p, 0, sizeof(u32), s));
-    MT_HIP(hipMemsetAsync(stats.p, 0, ST_COUNT * sizeof(u64), s));
+    DBuf<u64> stats_part(blocks * ST_COUNT);
+    DBuf<FusedSummary> sum(1);
+    res.alloc_cands(n * N);
 
-    FusedArgs a{};
+    FusedLaunch L{};
+    FusedArgs &a = L.a;
     a.seq = (const u8 *)reads.seq;
     a.off = reads.offsets;
     a.n = n;
@@ -786,78 +921,77 @@ void classify_fused(const mt_index &ix, const mt_query_params &q, const mt_seqs 
     a.multi = (unsigned long long *)res.multi.p;
     a.unmapped = (unsigned long long *)res.unmapped.p;
     a.fb_list = fb_list.p;
-    a.fb_count = fb_count.p;
-    a.flags = rb.flags.p;
-    a.stats = stats.p;
-    int dev = 0, cus = 0;
-    MT_HIP(hipGetDevice(&dev));
-    MT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    u64 blocks = (n + F_WPB - 1) / F_WPB;
-    u64 cap = (u64)cus * 16;
-    if (blocks > cap) blocks = cap;
-    k_fused<<<(unsigned)blocks, 64 * F_WPB, 0, s>>>(a);
-    MT_HIP(hipGetLastError());
-    tm.mark("fused");
+    a.fb_count = ctl.p + CTL_FB;
+    a.flags = ctl.p + CTL_FLAGS;
+    a.gate = ctl.p + CTL_GATE;
+    a.stats_part = stats_part.p;
+    L.ctl = ctl.p;
+    L.n = n;
+    L.N = N;
+    L.blocks = (unsigned)blocks;
+    L.total = reads.total;
+    L.res = &res;
+    L.sum = sum.p;
 
-    u32 nfb = 0;
-    u64 st[ST_COUNT];
-    MT_HIP(hipMemcpyAsync(st, stats.p, sizeof st, hipMemcpyDeviceToHost, s));
-    read_back(s, fb_count.p, &nfb, sizeof nfb);
-    u32 f1 = 0;
-    read_back(s, rb.flags.p, &f1, sizeof f1);
-    check_flags(f1);
-    mt_stats &ls = last_stats();
-    ls.fused_reads += st[ST_READS];
-    ls.fused_bases += st[ST_BASES];
-    ls.fused_minimizers += st[ST_MINS];
-    ls.fused_window_blocks += st[ST_WBLOCKS];
-    ls.fused_cands += st[ST_CANDS];
-    ls.n_minimizers += st[ST_MINS];
-
-    if (nfb) {
-        // Reads past the fused kernel's limits: finish them per stage.
-        DBuf<u64> sub_len(nfb), sub_off(nfb + 1);
-        k_subset_lengths<<<grid_for(nfb, 256), 256, 0, s>>>(reads.offsets, fb_list.p, nfb, sub_len.p);
-        MT_HIP(hipGetLastError());
-        scan_u64(sub_len.p, sub_off.p, nfb, s);
-        u64 sub_total = 0;
-        read_back(s, sub_off.p + nfb, &sub_total, sizeof sub_total);
-        DBuf<u8> sub_seq(sub_total);
-        k_subset_copy<<<nfb, 256, 0, s>>>((const u8 *)reads.seq, reads.offsets, fb_list.p, nfb, sub_off.p,
-                                          sub_seq.p);
-        MT_HIP(hipGetLastError());
-        mt_seqs sub{(const char *)sub_seq.p, sub_off.p, nfb, sub_total};
-        mt_result tmp;
-        mt_result_init(tmp, nfb, ix.n_taxa, s);
-        ReadBatch srb;
-        srb.prepare(sub, q.e_mode, q.e_value, s);
-        classify_per_stage(ix, q, sub, srb, tmp, tm, s);
-        u32 f2 = 0;
-        read_back(s, srb.flags.p, &f2, sizeof f2);
-        check_flags(f2);
-        k_subset_scatter<<<grid_for(nfb, 256), 256, 0, s>>>(fb_list.p, nfb, N, tmp.cand_off.p, tmp.read_accepted.p,
-                                                            tmp.genome.p, tmp.diag.p, tmp.hits.p, tmp.approx.p,
-                                                            tmp.accept.p, ncand.p, res.read_accepted.p, st_genome.p,
-                                                            st_diag.p, st_hits.p, st_approx.p, st_accept.p);
-        MT_HIP(hipGetLastError());
-        if (ix.n_taxa) {
-            k_add_u64<<<grid_for(ix.n_taxa, 256), 256, 0, s>>>((unsigned long long *)res.uniq.p, tmp.uniq.p,
-                                                               ix.n_taxa);
-            k_add_u64<<<grid_for(ix.n_taxa, 256), 256, 0, s>>>((unsigned long long *)res.multi.p, tmp.multi.p,
-                                                               ix.n_taxa);
-        }
-        k_add_u64<<<1, 64, 0, s>>>((unsigned long long *)res.unmapped.p, tmp.unmapped.p, 1);
-        MT_HIP(hipGetLastError());
-        tm.mark("fallback");
+    if (graph) {
+        launch_fused_graph(L, s);
+        tm.mark("graph");
+    } else {
+        enqueue_fused(L, &tm, s);
     }
+    FusedSummary h{};
+    read_back(s, sum.p, &h, sizeof h);
+    check_flags(h.gate | h.flags);
+    mt_stats &ls = last_stats();
+    ls.fused_reads += h.stats[ST_READS];
+    ls.fused_bases += h.stats[ST_BASES];
+    ls.fused_minimizers += h.stats[ST_MINS];
+    ls.fused_window_blocks += h.stats[ST_WBLOCKS];
+    ls.fused_cands += h.stats[ST_CANDS];
+    ls.n_minimizers += h.stats[ST_MINS];
+    res.n_cands = h.n_cands;
+    const u32 nfb = h.nfb;
+    if (nfb == 0) return;
 
-    res.alloc_cands(n * N);
-    scan_u32(ncand.p, res.cand_off.p, n, s);
-    k_compact_staged<<<grid_for(n, 256), 256, 0, s>>>(res.cand_off.p, n, N, st_genome.p, st_diag.p, st_hits.p,
-                                                      st_approx.p, st_accept.p, res.genome.p, res.diag.p,
-                                                      res.hits.p, res.approx.p, res.accept.p);
+    // Reads past the fused kernel's limits: finish them per stage on a
+    // gathered subset, scatter the results into the staging slots, and
+    // compact again.
+    DBuf<u64> sub_len(nfb), sub_off(nfb + 1);
+    k_subset_lengths<<<grid_for(nfb, 256), 256, 0, s>>>(reads.offsets, fb_list.p, nfb, sub_len.p);
     MT_HIP(hipGetLastError());
-    tm.mark("compact");
+    scan_u64(sub_len.p, sub_off.p, nfb, s);
+    u64 sub_total = 0;
+    read_back(s, sub_off.p + nfb, &sub_total, sizeof sub_total);
+    DBuf<u8> sub_seq(sub_total);
+    k_subset_copy<<<nfb, 256, 0, s>>>((const u8 *)reads.seq, reads.offsets, fb_list.p, nfb, sub_off.p, sub_seq.p);
+    MT_HIP(hipGetLastError());
+    mt_seqs sub{(const char *)sub_seq.p, sub_off.p, nfb, sub_total};
+    mt_result tmp;
+    mt_result_init(tmp, nfb, ix.n_taxa, s);
+    ReadBatch srb;
+    srb.prepare(sub, q.e_mode, q.e_value, s);
+    classify_per_stage(ix, q, sub, srb, tmp, tm, s);
+    u32 f2 = 0;
+    read_back(s, srb.flags.p, &f2, sizeof f2);
+    check_flags(f2);
+    k_subset_scatter<<<grid_for(nfb, 256), 256, 0, s>>>(fb_list.p, nfb, N, tmp.cand_off.p, tmp.read_accepted.p,
+                                                        tmp.genome.p, tmp.diag.p, tmp.hits.p, tmp.approx.p,
+                                                        tmp.accept.p, ncand.p, res.read_accepted.p, st_genome.p,
+                                                        st_diag.p, st_hits.p, st_approx.p, st_accept.p);
+    MT_HIP(hipGetLastError());
+    if (ix.n_taxa) {
+        k_add_u64<<<grid_for(ix.n_taxa, 256), 256, 0, s>>>((unsigned long long *)res.uniq.p, tmp.uniq.p, ix.n_taxa);
+        k_add_u64<<<grid_for(ix.n_taxa, 256), 256, 0, s>>>((unsigned long long *)res.multi.p, tmp.multi.p,
+                                                           ix.n_taxa);
+    }
+    k_add_u64<<<1, 64, 0, s>>>((unsigned long long *)res.unmapped.p, tmp.unmapped.p, 1);
+    scan_u32(ncand.p, res.cand_off.p, n, s);
+    k_compact_staged<<<grid_for(n, 256), 256, 0, s>>>(ctl.p + CTL_GATE, res.cand_off.p, n, N, st_genome.p,
+                                                      st_diag.p, st_hits.p, st_approx.p, st_accept.p, res.genome.p,
+                                                      res.diag.p, res.hits.p, res.approx.p, res.accept.p);
+    MT_HIP(hipGetLastError());
+    read_back(s, res.cand_off.p + n, &res.n_cands, sizeof(u64));
+    tm.mark("fallback");
 }
 
 }  // namespace mt

@@ -293,11 +293,7 @@ void mt_server::run_batch(Batch &b, hipStream_t s, Pinned &h_in, Pinned &h_out, 
     Timer tm;
     tm.stream = s;
     mt_result_init(res, n, ix->n_taxa, s);
-    classify_fused(*ix, q, seqs, rb, res, tm, s);
-    u32 f = 0;
-    read_back(s, rb.flags.p, &f, sizeof f);
-    check_flags(f);
-    read_back(s, res.cand_off.p + n, &res.n_cands, sizeof(u64));
+    classify_fused(*ix, q, seqs, rb, res, tm, s, false);
     const u64 nc = res.n_cands;
     launch_reduce_slots(res, *ix, d_slot, ns, d_cnt, s);
 

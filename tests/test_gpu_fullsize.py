@@ -38,7 +38,10 @@ def full():
     res = ix.classify(dr, min_hits=3, top_n=3, e_value=7, mode=mt.MT_MODE_PER_STAGE)
     stage = res.to_host()
     res.free()
-    return dict(ga=ga, reads=reads, fused=fused, stage=stage)
+    res = ix.classify(dr, min_hits=3, top_n=3, e_value=7, mode=mt.MT_MODE_FUSED_GRAPH)
+    graph = res.to_host()
+    res.free()
+    return dict(ga=ga, reads=reads, fused=fused, stage=stage, graph=graph)
 
 
 def _slice(res, idx):
@@ -57,9 +60,10 @@ def _slice(res, idx):
 
 
 def test_fused_equals_per_stage_on_every_read(full):
-    for f in FIELDS:
-        assert np.array_equal(full["fused"][f], full["stage"][f]), f
-    assert full["fused"]["unmapped"] == full["stage"]["unmapped"]
+    for other in ("stage", "graph"):
+        for f in FIELDS:
+            assert np.array_equal(full["fused"][f], full[other][f]), (other, f)
+        assert full["fused"]["unmapped"] == full[other]["unmapped"], other
 
 
 def test_sampled_reads_match_oracle(full):

@@ -48,7 +48,7 @@ def run_both(mt, genomes, reads, k, w, max_occ=0, taxon=None, n_taxa=None, mode=
     return got, ref
 
 
-MODES = [0, 1]  # per-stage, fused
+MODES = [0, 1, 2]  # per-stage, fused, fused as one HIP graph
 
 
 @pytest.mark.parametrize("mode", MODES)
@@ -208,6 +208,21 @@ def test_repeat_calls_and_modes_identical(mt):
     assert_same(a, b, "repeat")
     assert_same(a, c, "per-stage vs fused")
     assert_same(c, d, "fused repeat")
+
+
+def test_graph_replays_between_eager_calls(mt):
+    """The graph form, replayed (updated in place) many times with eager calls
+    of other sizes and shapes in between, equals the eager result every time."""
+    gen, reads, p = synth.workload_small(4000)
+    ix = mt.Index(gen.ascii(), p["k"], p["w"])
+    sizes = [4000, 1, 257, 4000, 3999, 64, 4000]
+    sets = {m: mt.to_device(reads.subset(np.arange(m))) for m in set(sizes)}
+    eager = {m: ix.classify(sets[m], mode=1).to_host() for m in sets}
+    for i, m in enumerate(sizes):
+        got = ix.classify(sets[m], mode=2).to_host()
+        assert_same(got, eager[m], f"graph replay {i} ({m} reads)")
+        other = sizes[(i + 3) % len(sizes)]
+        assert_same(ix.classify(sets[other], mode=0).to_host(), eager[other], f"eager between replays {i}")
 
 
 def test_filter_buckets_long_reads_against_oracle(mt):
