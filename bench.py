@@ -249,6 +249,9 @@ def main() -> int:
                          "2000 for uneven, 0 for strains)")
     ap.add_argument("--no-timing", action="store_true", help="do not record per-stage HIP events")
     ap.add_argument("--genomes", type=int, default=200, help="genomes of 2.5 Mbp in the database")
+    ap.add_argument("--autotune", type=int, default=-1,
+                    help="1: time the filter variants on a sample of the batch first and keep the fastest per "
+                         "bucket (default: on for the uneven workload); 0: built-in defaults")
     ap.add_argument("--serving", type=int, default=1,
                     help="1: also measure the served workload (batched workload only); 0: skip it")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="length of each served trace")
@@ -326,6 +329,19 @@ def main() -> int:
 
     mode = {"fused": mt.MT_MODE_FUSED, "graph": mt.MT_MODE_FUSED_GRAPH, "per_stage": mt.MT_MODE_PER_STAGE}[args.mode]
     q = dict(min_hits=3, top_n=3, e_mode=e_mode, e_value=e_value, mode=mode)
+
+    tune = None
+    if args.autotune < 0:
+        args.autotune = 1 if args.workload == "uneven" else 0
+    if args.autotune:
+        t = time.time()
+        sample = mt.to_device(reads.subset(np.arange(min(reads.n, 200_000))))
+        info = ix.autotune(sample, reps=2, **{k: v for k, v in q.items() if k != "mode"})
+        del sample
+        tune = {b["name"]: b["current"] for b in info if b["pairs"]}
+        log(f"[bench] autotuned in {time.time() - t:.1f}s: "
+            + "; ".join(f"{b['name']} ({b['pairs']} pairs): " + ", ".join(f"{k} {v:.3f} ms" for k, v in b["ms"].items())
+                        for b in info if b["pairs"]))
 
     for i in range(args.warmup):
         t = time.time()
@@ -413,6 +429,7 @@ def main() -> int:
         "index_build_s": round(index_s, 3),
         "stages_ms": {k: round(v, 4) for k, v in stages.items()},
         "roofline": roofline,
+        "filter_tuning": tune,
         "cpu_baseline": cpu,
         "serving": serving,
     }

@@ -268,6 +268,51 @@ int mt_result_on_host(const mt_result *res);
 /* Submit and completion times of a served request (steady clock, ns). */
 int mt_result_times(const mt_result *res, uint64_t *submit_ns, uint64_t *done_ns);
 
+/*
+ * Autotuning of the filter step (Fig. 1 step 2d; the E-dependent band of 2E+1
+ * rows of Table 1's pigeonhole filters).  Filter pairs are bucketed by E
+ * (<= 7, <= 15, <= 31) and, for larger E, by the 64-base blocks of read and
+ * reference window they stage in LDS (<= 96, 192, 384, 768); each bucket has
+ * variants: lanes per pair (pairs per wavefront) for small E, the LDS tile
+ * with 1/2/4/8 wavefronts per block or a rows-in-lanes layout reading global
+ * memory for large E.  Every variant gives bit-identical results; the choice
+ * is process-wide and applies to mt_classify (per-stage form and the fused
+ * form's per-stage finish) and mt_filter_pairs.
+ */
+#define MT_TUNE_MAX_VARIANTS 6
+
+typedef struct mt_tune_bucket {
+    const char *name;                                 /* e.g. "E<=7", "long<=384" */
+    uint32_t n_variants;
+    uint32_t current;                                 /* variant in use */
+    const char *variant_names[MT_TUNE_MAX_VARIANTS];  /* NULL past n_variants */
+    float ms[MT_TUNE_MAX_VARIANTS];                   /* last autotune time per variant (0: not timed) */
+    uint64_t pairs;                                   /* pairs the last autotune timed in this bucket */
+} mt_tune_bucket;
+
+/* Number of buckets (*n) and the state of one bucket (host structs; the
+ * strings are static). */
+int mt_tune_buckets(uint32_t *n);
+int mt_tune_info(uint32_t bucket, mt_tune_bucket *out);
+/* Selects a variant for a bucket.  Errors: MT_EINVAL (no such bucket or
+ * variant, or a variant whose LDS does not fit a workgroup). */
+int mt_tune_set(uint32_t bucket, uint32_t variant);
+/* Back to the built-in defaults. */
+int mt_tune_reset(void);
+/*
+ * Classifies `reads` (host struct with device arrays) in the per-stage form to
+ * obtain their filter pairs, then times every variant of every bucket that
+ * holds pairs on those pairs (best of `reps` launches, HIP events on
+ * `stream`) and selects the fastest.  Results: mt_tune_info.
+ */
+int mt_autotune(const mt_index *index, const mt_query_params *params, const mt_seqs *reads, uint32_t reps,
+                void *stream);
+/* Writes / reads the selection as JSON ({"arch": ..., "buckets": {name: variant}}).
+ * mt_tune_load fails with MT_EINVAL for a file made on another GPU
+ * architecture or naming unknown buckets or variants. */
+int mt_tune_save(const char *path);
+int mt_tune_load(const char *path);
+
 /* Releases device memory cached by the library's allocator (not held by any handle). */
 int mt_trim(void);
 /* Description of the last error on the calling thread ("" if none). */

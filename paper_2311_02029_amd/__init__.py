@@ -16,7 +16,8 @@ from . import _abi
 from ._abi import (MT_E_CEIL_PERMILLE, MT_E_FIXED, MT_E_FLOOR_PERMILLE, MT_MODE_FUSED,  # noqa: F401
                    MT_MODE_FUSED_GRAPH, MT_MODE_PER_STAGE, MT_OK)
 
-__all__ = ["MTError", "DeviceSeqs", "Index", "Result", "Server", "to_device", "mt_set_timing", "last_timings"]
+__all__ = ["MTError", "DeviceSeqs", "Index", "Result", "Server", "to_device", "mt_set_timing", "last_timings",
+           "tune_info", "tune_set", "tune_reset", "tune_save", "tune_load"]
 
 
 class MTError(RuntimeError):
@@ -132,6 +133,42 @@ def last_timings() -> list[tuple[str, float]]:
     return [(names[i].decode(), float(ms[i])) for i in range(n.value)]
 
 
+def tune_info() -> list[dict]:
+    """State of every filter bucket: name, variants, the one in use, last autotune times."""
+    lib = _abi.load()
+    n = C.c_uint32()
+    _check(lib.mt_tune_buckets(C.byref(n)), lib)
+    out = []
+    for b in range(n.value):
+        tb = _abi.mt_tune_bucket()
+        _check(lib.mt_tune_info(b, C.byref(tb)), lib)
+        names = [tb.variant_names[v].decode() for v in range(tb.n_variants)]
+        out.append(dict(bucket=b, name=tb.name.decode(), variants=names, current=names[tb.current],
+                        ms={names[v]: float(tb.ms[v]) for v in range(tb.n_variants) if tb.ms[v] > 0},
+                        pairs=int(tb.pairs)))
+    return out
+
+
+def tune_set(bucket: int, variant: int) -> None:
+    lib = _abi.load()
+    _check(lib.mt_tune_set(bucket, variant), lib)
+
+
+def tune_reset() -> None:
+    lib = _abi.load()
+    _check(lib.mt_tune_reset(), lib)
+
+
+def tune_save(path: str) -> None:
+    lib = _abi.load()
+    _check(lib.mt_tune_save(path.encode()), lib)
+
+
+def tune_load(path: str) -> None:
+    lib = _abi.load()
+    _check(lib.mt_tune_load(path.encode()), lib)
+
+
 class Result:
     """Owns an mt_result; arrays are device pointers until to_host()."""
 
@@ -235,6 +272,13 @@ class Index:
             rc = self.lib.mt_classify(self.h, C.byref(q), C.byref(reads.abi()), sp, C.byref(h))
         _check(rc, self.lib)
         return Result(h.value, self.lib)
+
+    def autotune(self, reads: DeviceSeqs, min_hits=3, top_n=3, e_mode=MT_E_FIXED, e_value=7, reps=3,
+                 stream=None) -> list[dict]:
+        """Times the filter variants of every bucket on these reads' pairs and keeps the fastest."""
+        q = _abi.mt_query_params(min_hits, top_n, e_mode, e_value, MT_MODE_PER_STAGE)
+        _check(self.lib.mt_autotune(self.h, C.byref(q), C.byref(reads.abi()), reps, _stream_ptr(stream)), self.lib)
+        return tune_info()
 
     def filter_pairs(self, reads: DeviceSeqs, pair_read, pair_genome, pair_diag, pair_E, stream=None):
         """Device tensors in (uint32/int32 read and genome, int64 diag, int16/uint16 E); returns

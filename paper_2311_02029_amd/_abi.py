@@ -20,6 +20,8 @@ ABI_FUNCTIONS = (
     "mt_result_cands", "mt_result_taxa", "mt_result_free", "mt_last_timings", "mt_set_timing",
     "mt_filter_pairs", "mt_trim", "mt_last_error", "mt_abi_version", "mt_last_stats", "mt_server_create",
     "mt_server_submit", "mt_server_wait", "mt_server_destroy", "mt_result_on_host", "mt_result_times",
+    "mt_tune_buckets", "mt_tune_info", "mt_tune_set", "mt_tune_reset", "mt_autotune", "mt_tune_save",
+    "mt_tune_load",
 )
 
 
@@ -52,6 +54,11 @@ class mt_server_params(C.Structure):
     _fields_ = [("mem_budget_bytes", C.c_uint64), ("max_batch_reads", C.c_uint64), ("n_streams", C.c_uint32),
                 ("max_queued_requests", C.c_uint32), ("pinned_arena_bytes", C.c_uint64),
                 ("reserved", C.c_uint32 * 4)]
+
+
+class mt_tune_bucket(C.Structure):
+    _fields_ = [("name", C.c_char_p), ("n_variants", C.c_uint32), ("current", C.c_uint32),
+                ("variant_names", C.c_char_p * 6), ("ms", C.c_float * 6), ("pairs", C.c_uint64)]
 
 
 _lib = None
@@ -90,6 +97,13 @@ def load(path: str = LIB_PATH):
         "mt_server_destroy": (i32, [vp]),
         "mt_result_on_host": (i32, [vp]),
         "mt_result_times": (i32, [vp, C.POINTER(u64), C.POINTER(u64)]),
+        "mt_tune_buckets": (i32, [C.POINTER(u32)]),
+        "mt_tune_info": (i32, [u32, C.POINTER(mt_tune_bucket)]),
+        "mt_tune_set": (i32, [u32, u32]),
+        "mt_tune_reset": (i32, []),
+        "mt_autotune": (i32, [vp, C.POINTER(mt_query_params), C.POINTER(mt_seqs), u32, vp]),
+        "mt_tune_save": (i32, [C.c_char_p]),
+        "mt_tune_load": (i32, [C.c_char_p]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

@@ -73,6 +73,13 @@ struct FilterArgs {
 // then each bucket runs the kernel shaped for it.
 void launch_filter(const FilterArgs &a, u64 n_cap, u32 max_E, hipStream_t s);
 
+// Filter variants per bucket (see filter.hip) and their autotuner.
+void autotune_filter(const FilterArgs &a, u64 n_pairs, u32 reps, hipStream_t s);
+int tune_buckets();
+void tune_info(int bucket, mt_tune_bucket &out);
+void tune_set(int bucket, int variant);
+void tune_reset();
+
 void validate_query(const mt_query_params &q);
 void mt_result_init(mt_result &res, u64 n, u32 n_taxa, hipStream_t s);
 void classify_per_stage(const mt_index &ix, const mt_query_params &q, const mt_seqs &reads, ReadBatch &rb,

@@ -1,23 +1,32 @@
 // The obstacle-count filter over explicit pair lists (Fig. 1 step 2d), used by
 // the per-stage form, by the fused form's fallback and by mt_filter_pairs.
 //
-// Pairs are bucketed by their threshold E so that each bucket gets the
-// kernel shaped for it (uneven batching):
-//   E <= 7   groups of 16 lanes, 4 pairs per wavefront, one band row per lane
-//   E <= 15  groups of 32 lanes, 2 pairs per wavefront
-//   E <= 31  one pair per wavefront
-//   E > 31   long reads: one pair per wavefront with the read and its
-//            reference window staged in LDS; each lane owns a contiguous
-//            strip of the 2E+1 rows, so one 128-base reference fetch per step
-//            serves its whole strip (k_filter_long); pairs too large for its
-//            LDS budget use the 64-lane kernel that fetches from global memory.
+// Pairs are bucketed by their threshold E, and long pairs by the LDS they
+// need, so that each bucket gets the kernel shaped for it (uneven batching):
+//   E <= 7   groups of G lanes per pair, one band row per lane (G = 16, 32 or 64)
+//   E <= 15  G = 32 or 64
+//   E <= 31  G = 64: one pair per wavefront
+//   E > 31   long reads, four bins by the 64-base blocks of read plus
+//            reference window they stage in LDS (<= 96, 192, 384, 768): one
+//            pair per wavefront, each lane owning a contiguous strip of the
+//            2E+1 rows so that one 128-base window fetch per step serves its
+//            whole strip, with the bin's LDS tile and W wavefronts per block;
+//            or the rows-in-lanes kernel reading the window from global memory
+//   larger   the rows-in-lanes kernel.
+// The variant of each bucket (G, W, layout) is chosen by the autotuner
+// (mt_autotune) or set by mt_tune_set; every variant gives the same result.
+#include <mutex>
+#include <string>
+
 #include "classify.hpp"
 
 namespace mt {
 
-constexpr int N_CLASSES = 5;
-constexpr int LONG_WPB = 4;
-constexpr int LONG_BLOCKS = 640;  // 64-base blocks of read + window staged per wavefront
+constexpr int N_CLASSES = 8;  // E<=7, E<=15, E<=31, four long bins, general
+constexpr int CLS_LONG = 3, LONG_BINS = 4, CLS_GENERAL = 7;
+constexpr int LONG_CAP[LONG_BINS] = {96, 192, 384, 768};  // 64-base blocks staged per wavefront
+constexpr int LDS_BLOCK_BYTES = 24;                        // {lo, hi} + nb of one 64-base block
+constexpr int LONG_LDS_MAX = 64 * 1024;                    // per workgroup
 
 __device__ inline void pair_fields(const FilterArgs &a, u64 p, u32 &r, u32 &g, int &E, bool &ok, u32 &err) {
     r = a.pair_read[p];
@@ -53,13 +62,15 @@ __device__ inline u8 pair_class(const FilterArgs &a, u64 p) {
     int E;
     bool ok;
     pair_fields(a, p, r, g, E, ok, err);
-    if (!ok) return 4;  // the general kernel reports the error
+    if (!ok) return CLS_GENERAL;  // the general kernel reports the error
     if (E <= 7) return 0;
     if (E <= 15) return 1;
     if (E <= 31) return 2;
     int nrb, nwb;
     long_blocks(read_len(a, r), E, nrb, nwb);
-    return nrb + nwb <= LONG_BLOCKS ? 3 : 4;
+    for (int b = 0; b < LONG_BINS; b++)
+        if (nrb + nwb <= LONG_CAP[b]) return (u8)(CLS_LONG + b);
+    return CLS_GENERAL;
 }
 
 // Counting and placing pairs use one atomic per wavefront and class: the
@@ -153,14 +164,15 @@ __device__ inline Bits64 lds_bits(const u64x2 *lohi, const u64 *nb, i64 p) {
     return r;
 }
 
-// Long reads / large E: one wavefront per pair, planes in LDS.
-__global__ __launch_bounds__(64 * LONG_WPB) void k_filter_long(FilterArgs a, const u32 *__restrict__ idx, u64 n) {
-    __shared__ u64x2 s_lohi[LONG_WPB][LONG_BLOCKS];
-    __shared__ u64 s_nb[LONG_WPB][LONG_BLOCKS];
+// Long reads / large E: one wavefront per pair, planes in LDS (`tile` blocks
+// per wavefront, at least the pairs' nrb + nwb; blockDim.x / 64 wavefronts).
+__global__ __launch_bounds__(512) void k_filter_long(FilterArgs a, const u32 *__restrict__ idx, u64 n, int tile) {
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int wpb = blockDim.x >> 6;
     const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    u64x2 *L = s_lohi[wid];
-    u64 *NB = s_nb[wid];
-    for (u64 t = (u64)blockIdx.x * LONG_WPB + wid; t < n; t += (u64)gridDim.x * LONG_WPB) {
+    u64x2 *L = (u64x2 *)(lds + (size_t)wid * tile * LDS_BLOCK_BYTES);
+    u64 *NB = (u64 *)(lds + (size_t)wid * tile * LDS_BLOCK_BYTES + (size_t)tile * 16);
+    for (u64 t = (u64)blockIdx.x * wpb + wid; t < n; t += (u64)gridDim.x * wpb) {
         const u64 p = idx[t];
         u32 r, g, err;
         int E;
@@ -245,36 +257,183 @@ __global__ __launch_bounds__(64 * LONG_WPB) void k_filter_long(FilterArgs a, con
     }
 }
 
-void launch_filter(const FilterArgs &a, u64 n_cap, u32 /*max_E*/, hipStream_t s) {
-    if (n_cap == 0) return;
-    DBuf<u32> count(N_CLASSES), cursor(N_CLASSES), base(N_CLASSES), idx(n_cap);
+// ------------------------------------------------------------- variants --
+
+namespace {
+
+struct BucketDesc {
+    const char *name;
+    int n_variants;
+    const char *variants[6];
+};
+
+// Variant v of a long bin: v < 4 -> strips in LDS with 1 << v wavefronts per
+// block (if its LDS fits a workgroup), v == 4 -> rows in lanes from global memory.
+const BucketDesc BUCKETS[N_CLASSES] = {
+    {"E<=7", 3, {"g16", "g32", "g64"}},
+    {"E<=15", 2, {"g32", "g64"}},
+    {"E<=31", 1, {"g64"}},
+    {"long<=96", 5, {"lds_w1", "lds_w2", "lds_w4", "lds_w8", "global"}},
+    {"long<=192", 5, {"lds_w1", "lds_w2", "lds_w4", "lds_w8", "global"}},
+    {"long<=384", 5, {"lds_w1", "lds_w2", "lds_w4", "lds_w8", "global"}},
+    {"long<=768", 5, {"lds_w1", "lds_w2", "lds_w4", "lds_w8", "global"}},
+    {"general", 1, {"global"}},
+};
+
+// Defaults: the narrowest groups for short E, the most wavefronts per block
+// whose LDS fits 64 KB for the long bins.
+const int DEFAULT_VARIANT[N_CLASSES] = {0, 0, 0, 3, 3, 2, 1, 0};
+
+std::mutex g_tune_mu;
+int g_variant[N_CLASSES] = {0, 0, 0, 3, 3, 2, 1, 0};
+float g_tune_ms[N_CLASSES][6];
+u64 g_tune_pairs[N_CLASSES];
+
+bool variant_ok(int bucket, int v) {
+    if (v < 0 || v >= BUCKETS[bucket].n_variants) return false;
+    if (bucket >= CLS_LONG && bucket < CLS_LONG + LONG_BINS && v < 4)
+        return (1 << v) * LONG_CAP[bucket - CLS_LONG] * LDS_BLOCK_BYTES <= LONG_LDS_MAX;
+    return true;
+}
+
+int current_variant(int bucket) {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    return g_variant[bucket];
+}
+
+}  // namespace
+
+// Launches the pairs idx[0, cnt) of one bucket with one of its variants.
+static void launch_bucket(const FilterArgs &a, const u32 *idx, u64 cnt, int bucket, int v, hipStream_t s) {
+    if (cnt == 0) return;
+    if (bucket == 0 || bucket == 1) {
+        const int g = std::string(BUCKETS[bucket].variants[v]) == "g16" ? 16
+                      : std::string(BUCKETS[bucket].variants[v]) == "g32" ? 32 : 64;
+        if (g == 16) k_filter<16><<<grid_for(cnt * 16, 256), 256, 0, s>>>(a, idx, cnt);
+        else if (g == 32) k_filter<32><<<grid_for(cnt * 32, 256), 256, 0, s>>>(a, idx, cnt);
+        else k_filter<64><<<grid_for(cnt * 64, 256), 256, 0, s>>>(a, idx, cnt);
+    } else if (bucket >= CLS_LONG && bucket < CLS_LONG + LONG_BINS && v < 4) {
+        const int tile = LONG_CAP[bucket - CLS_LONG], wpb = 1 << v;
+        u64 blocks = (cnt + wpb - 1) / wpb;
+        if (blocks > 16384) blocks = 16384;
+        k_filter_long<<<(unsigned)blocks, 64 * wpb, (size_t)wpb * tile * LDS_BLOCK_BYTES, s>>>(a, idx, cnt, tile);
+    } else {
+        k_filter<64><<<grid_for(cnt * 64, 256), 256, 0, s>>>(a, idx, cnt);
+    }
+    MT_HIP(hipGetLastError());
+}
+
+// Buckets the pairs (one synchronization for the bucket sizes); idx / counts
+// receive the bucketed pair indices and the per-bucket counts and offsets.
+static void bucket_pairs(const FilterArgs &a, u64 n_cap, DBuf<u32> &idx, u32 hc[N_CLASSES], u32 hb[N_CLASSES],
+                         hipStream_t s) {
+    DBuf<u32> count(N_CLASSES), cursor(N_CLASSES), base(N_CLASSES);
     DBuf<u8> cls(n_cap);
+    idx.alloc(n_cap);
     MT_HIP(hipMemsetAsync(count.p, 0, N_CLASSES * sizeof(u32), s));
     MT_HIP(hipMemsetAsync(cursor.p, 0, N_CLASSES * sizeof(u32), s));
     k_pair_class<<<grid_for(n_cap, 256), 256, 0, s>>>(a, n_cap, count.p, cls.p);
     MT_HIP(hipGetLastError());
-    u32 hc[N_CLASSES];
-    read_back(s, count.p, hc, sizeof hc);
-    u32 hb[N_CLASSES];
+    read_back(s, count.p, hc, N_CLASSES * sizeof(u32));
     u32 acc = 0;
     for (int c = 0; c < N_CLASSES; c++) {
         hb[c] = acc;
         acc += hc[c];
     }
     if (acc == 0) return;
-    MT_HIP(hipMemcpyAsync(base.p, hb, sizeof hb, hipMemcpyHostToDevice, s));
+    MT_HIP(hipMemcpyAsync(base.p, hb, N_CLASSES * sizeof(u32), hipMemcpyHostToDevice, s));
     k_pair_scatter<<<grid_for(n_cap, 256), 256, 0, s>>>(a, n_cap, cls.p, base.p, cursor.p, idx.p);
     MT_HIP(hipGetLastError());
-    if (hc[0]) k_filter<16><<<grid_for((u64)hc[0] * 16, 256), 256, 0, s>>>(a, idx.p + hb[0], hc[0]);
-    if (hc[1]) k_filter<32><<<grid_for((u64)hc[1] * 32, 256), 256, 0, s>>>(a, idx.p + hb[1], hc[1]);
-    if (hc[2]) k_filter<64><<<grid_for((u64)hc[2] * 64, 256), 256, 0, s>>>(a, idx.p + hb[2], hc[2]);
-    if (hc[3]) {
-        u64 blocks = ((u64)hc[3] + LONG_WPB - 1) / LONG_WPB;
-        if (blocks > 4096) blocks = 4096;
-        k_filter_long<<<(unsigned)blocks, 64 * LONG_WPB, 0, s>>>(a, idx.p + hb[3], hc[3]);
+    MT_HIP(hipStreamSynchronize(s));  // hb lives on this host stack frame
+}
+
+void launch_filter(const FilterArgs &a, u64 n_cap, u32 /*max_E*/, hipStream_t s) {
+    if (n_cap == 0) return;
+    DBuf<u32> idx;
+    u32 hc[N_CLASSES], hb[N_CLASSES];
+    bucket_pairs(a, n_cap, idx, hc, hb, s);
+    for (int c = 0; c < N_CLASSES; c++) launch_bucket(a, idx.p + hb[c], hc[c], c, current_variant(c), s);
+}
+
+// Times every variant of every bucket that holds pairs (best of `reps`
+// launches each, after one untimed launch) and keeps the fastest.
+void autotune_filter(const FilterArgs &a, u64 n_pairs, u32 reps, hipStream_t s) {
+    if (n_pairs == 0) return;
+    DBuf<u32> idx;
+    u32 hc[N_CLASSES], hb[N_CLASSES];
+    bucket_pairs(a, n_pairs, idx, hc, hb, s);
+    hipEvent_t e0, e1;
+    MT_HIP(hipEventCreate(&e0));
+    MT_HIP(hipEventCreate(&e1));
+    try {
+        for (int c = 0; c < N_CLASSES; c++) {
+            if (hc[c] == 0) continue;
+            float best_ms = 0;
+            int best = -1;
+            float ms_v[6] = {0, 0, 0, 0, 0, 0};
+            for (int v = 0; v < BUCKETS[c].n_variants; v++) {
+                if (!variant_ok(c, v)) continue;
+                launch_bucket(a, idx.p + hb[c], hc[c], c, v, s);
+                float mn = 0;
+                for (u32 r = 0; r < (reps ? reps : 1); r++) {
+                    MT_HIP(hipEventRecord(e0, s));
+                    launch_bucket(a, idx.p + hb[c], hc[c], c, v, s);
+                    MT_HIP(hipEventRecord(e1, s));
+                    MT_HIP(hipEventSynchronize(e1));
+                    float ms = 0;
+                    MT_HIP(hipEventElapsedTime(&ms, e0, e1));
+                    if (r == 0 || ms < mn) mn = ms;
+                }
+                ms_v[v] = mn;
+                if (best < 0 || mn < best_ms) {
+                    best_ms = mn;
+                    best = v;
+                }
+            }
+            std::lock_guard<std::mutex> g(g_tune_mu);
+            if (best >= 0) g_variant[c] = best;
+            for (int v = 0; v < 6; v++) g_tune_ms[c][v] = ms_v[v];
+            g_tune_pairs[c] = hc[c];
+        }
+    } catch (...) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        throw;
     }
-    if (hc[4]) k_filter<64><<<grid_for((u64)hc[4] * 64, 256), 256, 0, s>>>(a, idx.p + hb[4], hc[4]);
-    MT_HIP(hipGetLastError());
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+}
+
+int tune_buckets() { return N_CLASSES; }
+
+void tune_info(int bucket, mt_tune_bucket &out) {
+    MT_REQUIRE(bucket >= 0 && bucket < N_CLASSES, "no such filter bucket");
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    const BucketDesc &d = BUCKETS[bucket];
+    out.name = d.name;
+    out.n_variants = (u32)d.n_variants;
+    out.current = (u32)g_variant[bucket];
+    for (int v = 0; v < 6; v++) {
+        out.variant_names[v] = v < d.n_variants ? d.variants[v] : nullptr;
+        out.ms[v] = g_tune_ms[bucket][v];
+    }
+    out.pairs = g_tune_pairs[bucket];
+}
+
+void tune_set(int bucket, int variant) {
+    MT_REQUIRE(bucket >= 0 && bucket < N_CLASSES, "no such filter bucket");
+    MT_REQUIRE(variant_ok(bucket, variant), "variant not available for this bucket");
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_variant[bucket] = variant;
+}
+
+void tune_reset() {
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    for (int c = 0; c < N_CLASSES; c++) {
+        g_variant[c] = DEFAULT_VARIANT[c];
+        for (int v = 0; v < 6; v++) g_tune_ms[c][v] = 0;
+        g_tune_pairs[c] = 0;
+    }
 }
 
 }  // namespace mt

@@ -43,6 +43,7 @@ int main(void) {
          sizeof(mt_query_params), sizeof(mt_index_info), offsetof(mt_query_params, mode),
          offsetof(mt_index_info, k), sizeof(mt_server_params), offsetof(mt_server_params, pinned_arena_bytes),
          sizeof(mt_stats));
+  printf("%zu %zu %zu\n", sizeof(mt_tune_bucket), offsetof(mt_tune_bucket, ms), offsetof(mt_tune_bucket, pairs));
   return 0;
 }''')
     exe = tmp_path / "sizes"
@@ -51,7 +52,8 @@ int main(void) {
     want = [C.sizeof(_abi.mt_seqs), C.sizeof(_abi.mt_index_params), C.sizeof(_abi.mt_query_params),
             C.sizeof(_abi.mt_index_info), _abi.mt_query_params.mode.offset, _abi.mt_index_info.k.offset,
             C.sizeof(_abi.mt_server_params), _abi.mt_server_params.pinned_arena_bytes.offset,
-            C.sizeof(_abi.mt_stats)]
+            C.sizeof(_abi.mt_stats), C.sizeof(_abi.mt_tune_bucket), _abi.mt_tune_bucket.ms.offset,
+            _abi.mt_tune_bucket.pairs.offset]
     assert got == want
 
 
@@ -69,3 +71,12 @@ def test_null_arguments_are_errors_not_crashes():
     assert lib.mt_server_destroy(None) == _abi.MT_OK
     assert lib.mt_result_on_host(None) == 0
     assert lib.mt_result_times(None, None, None) == _abi.MT_EINVAL
+    n = C.c_uint32()
+    assert lib.mt_tune_buckets(C.byref(n)) == _abi.MT_OK and n.value == 8
+    tb = _abi.mt_tune_bucket()
+    assert lib.mt_tune_info(0, C.byref(tb)) == _abi.MT_OK and tb.name == b"E<=7" and tb.n_variants == 3
+    assert lib.mt_tune_info(8, C.byref(tb)) == _abi.MT_EINVAL
+    assert lib.mt_tune_set(0, 3) == _abi.MT_EINVAL
+    assert lib.mt_tune_set(6, 3) == _abi.MT_EINVAL  # 8 wavefronts x 768 blocks of LDS exceed a workgroup
+    assert lib.mt_autotune(None, None, None, 1, None) == _abi.MT_EINVAL
+    assert lib.mt_tune_load(None) == _abi.MT_EINVAL
