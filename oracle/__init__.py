@@ -66,10 +66,15 @@ def _declare(lib):
 
 
 def load(path: str | None = None):
-    """Loads the compiled oracle (building it first if it is not there)."""
+    """Loads the compiled oracle (building it first if it is not there).
+
+    ORACLE_LIB in the environment names another build of oracle.c to load
+    instead: the mutation tests point it at copies with a planted mistake."""
     global _lib
     if path is not None:
         return _declare(C.CDLL(path))
+    if _lib is None and os.environ.get("ORACLE_LIB"):
+        _lib = _declare(C.CDLL(os.environ["ORACLE_LIB"]))
     if _lib is None:
         if not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
             build()

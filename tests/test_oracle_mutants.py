@@ -1,0 +1,76 @@
+"""The pins are strong enough: each test here plants one plausible mistake in
+a copy of the oracle's C source (a dropped term, a wrong sign, index or
+comparison, a transposed operand), builds it, and runs the pin suite against
+it; at least one pin must fail.  Only copies are changed; oracle.c is read."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "oracle.c")
+
+# (name, original text, planted mistake); each original occurs exactly once.
+MUTANTS = [
+    ("code of T", "case 'T': case 't': return 3;", "case 'T': case 't': return 2;"),
+    ("N k-mers seed", "if (c == 4) ok = 0;", "if (c == 5) ok = 0;"),
+    ("k-mer base order", "v = v * 4 + (c & 3);", "v = v + ((uint64_t)(c & 3) << (2 * t));"),
+    ("hash drops a step", "return z ^ (z >> 31);", "return z;"),
+    ("hash shift", "z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;", "z = (z ^ (z >> 28)) * 0x94d049bb133111ebULL;"),
+    ("rightmost tie", "if (best < 0 || h[i] < h[best]) best = i;", "if (best < 0 || h[i] <= h[best]) best = i;"),
+    ("short sequence", "int64_t win = nk < w ? nk : w;", "int64_t win = w;"),
+    ("window one short", "for (int64_t i = s; i < s + win; i++) {", "for (int64_t i = s; i < s + win - 1; i++) {"),
+    ("diagonal sign", "hit[nh].diag = (int64_t)ix->occ[o].pos - mpos[i];",
+     "hit[nh].diag = mpos[i] - (int64_t)ix->occ[o].pos;"),
+    ("max_occ inclusive", "if (ix->max_occ > 0 && hi - lo > (int64_t)ix->max_occ) continue;",
+     "if (ix->max_occ > 0 && hi - lo >= (int64_t)ix->max_occ) continue;"),
+    ("strict min_hits", "if ((uint64_t)(j - i) >= min_hits) {", "if ((uint64_t)(j - i) > min_hits) {"),
+    ("hits ascending", "if (p->hits != q->hits) return p->hits > q->hits ? -1 : 1;",
+     "if (p->hits != q->hits) return p->hits < q->hits ? -1 : 1;"),
+    ("genome tie descending", "if (p->genome != q->genome) return p->genome < q->genome ? -1 : 1;\n    if (p->diag != q->diag) return p->diag < q->diag ? -1 : 1;\n    return 0;\n}\n\ntypedef struct or_result",
+     "if (p->genome != q->genome) return p->genome > q->genome ? -1 : 1;\n    if (p->diag != q->diag) return p->diag < q->diag ? -1 : 1;\n    return 0;\n}\n\ntypedef struct or_result"),
+    ("top_n off by one", "if (top_n > 0 && nc > (int64_t)top_n) nc = top_n;",
+     "if (top_n > 0 && nc > (int64_t)top_n + 1) nc = top_n + 1;"),
+    ("N is a fifth letter", "    if (qc == 4) return 1;\n    if (p < 0 || p >= glen) return 1;\n    uint8_t rc = gcode[p];\n    if (rc == 4) return 1;",
+     "    if (p < 0 || p >= glen) return 1;\n    uint8_t rc = gcode[p];"),
+    ("outside genome matches", "if (p < 0 || p >= glen) return 1;", "if (p < 0 || p >= glen) return 0;"),
+    ("band one row short", "int64_t rows = 2 * (int64_t)E + 1;", "int64_t rows = 2 * (int64_t)E;"),
+    ("no skip after obstacle", "        c += 1;\n        if (c > E) break;\n        j += 1;",
+     "        c += 1;\n        if (c > E) break;"),
+    ("early stop", "        c += 1;\n        if (c > E) break;", "        c += 1;\n        if (c >= E) break;"),
+    ("cap at E", "return c < E + 1 ? c : E + 1;", "return c < E ? c : E;"),
+    ("strict accept", "res->accept[res->n_cands - 1] = (uint8_t)(a <= E);",
+     "res->accept[res->n_cands - 1] = (uint8_t)(a < E);"),
+    ("E rounds down", "if (e_mode == 1) return (int)((num + 999) / 1000);", "if (e_mode == 1) return (int)(num / 1000);"),
+    ("worst accepted count", "if (a <= E && (best < 0 || a < best)) best = a;",
+     "if (a <= E && (best < 0 || a > best)) best = a;"),
+    ("multi counted once", "if (ntax > 1) res->multi_reads[t]++;", "if (ntax > 1 && t == only) res->multi_reads[t]++;"),
+    ("unique ignores ties", "if (ntax == 1) res->unique_reads[only]++;", "if (ntax >= 1) res->unique_reads[only]++;"),
+]
+
+
+@pytest.mark.parametrize("name,orig,mut", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_catch_planted_mistake(name, orig, mut, tmp_path):
+    src = open(SRC).read()
+    assert src.count(orig) == 1, f"mutation site of '{name}' not found exactly once"
+    mutant_c = tmp_path / "oracle_mutant.c"
+    mutant_c.write_text(src.replace(orig, mut))
+    lib = str(tmp_path / "liboracle_mutant.so")
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", lib, str(mutant_c)])
+    env = dict(os.environ, ORACLE_LIB=lib)
+    r = subprocess.run([sys.executable, "-m", "pytest", os.path.join(ROOT, "tests", "test_oracle_pins.py"), "-x",
+                        "-q", "-p", "no:cacheprovider"], cwd=ROOT, env=env, capture_output=True, text=True,
+                       timeout=600)
+    assert r.returncode != 0, f"no pin caught the planted mistake '{name}'"
+
+
+def test_unmutated_copy_passes_the_pins(tmp_path):
+    lib = str(tmp_path / "liboracle_copy.so")
+    oracle.build(lib)
+    env = dict(os.environ, ORACLE_LIB=lib)
+    r = subprocess.run([sys.executable, "-m", "pytest", os.path.join(ROOT, "tests", "test_oracle_pins.py"), "-q",
+                        "-p", "no:cacheprovider"], cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 0, r.stdout[-2000:]

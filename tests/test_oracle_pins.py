@@ -376,6 +376,16 @@ def test_filter_zero_iff_exact_occurrence_in_band(seed):
         assert oracle.approx(q, ref, st, rnd.randint(0, 5)) == 0
 
 
+def test_filter_N_never_matches_not_even_N():
+    """O1 worked by hand: an N in the read or the reference is an obstacle in
+    every row, also against another N."""
+    assert oracle.approx("ACGTNACGT", "ACGTNACGT", 0, 0) == 1
+    assert oracle.approx("ACGTNACGT", "ACGTNACGT", 0, 3) == 1   # row 0 has the only long runs
+    assert oracle.approx("ACGTAACGT", "ACGTNACGT", 0, 2) == 1
+    assert oracle.approx("NNNN", "NNNN", 0, 5) == 4             # four obstacles in every row
+    assert oracle.approx("NNNN", "NNNN", 0, 2) == 3             # saturated at E + 1
+
+
 def test_filter_E0_is_capped_hamming():
     rnd = random.Random(4000)
     for _ in range(3000):
