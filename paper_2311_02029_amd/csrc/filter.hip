@@ -9,8 +9,9 @@
 //   E > 31   long reads, four bins by the 64-base blocks of read plus
 //            reference window they stage in LDS (<= 96, 192, 384, 768): one
 //            pair per wavefront, each lane owning a contiguous strip of the
-//            2E+1 rows so that one 128-base window fetch per step serves its
-//            whole strip, with the bin's LDS tile and W wavefronts per block;
+//            2E+1 rows, compared 32 columns at a time from three window
+//            dwords per chunk of 32 rows, with the bin's LDS tile and W
+//            wavefronts per block;
 //            or the rows-in-lanes kernel reading the window from global memory
 //   larger   the rows-in-lanes kernel.
 // The variant of each bucket (G, W, layout) is chosen by the autotuner
@@ -164,6 +165,13 @@ __device__ inline Bits64 lds_bits(const u64x2 *lohi, const u64 *nb, i64 p) {
     return r;
 }
 
+// Dword k (bases 32k .. 32k+31) of the lo (pl = 0) or hi (pl = 1) plane of
+// {lo, hi} blocks staged in LDS, and of the nb plane.
+__device__ inline u32 plane_dw(const u64x2 *lohi, int pl, u32 k) {
+    return reinterpret_cast<const u32 *>(lohi)[(k >> 1) * 4 + pl * 2 + (k & 1)];
+}
+__device__ inline u32 nb_dw(const u64 *nb, u32 k) { return reinterpret_cast<const u32 *>(nb)[k]; }
+
 // Long reads / large E: one wavefront per pair, planes in LDS (`tile` blocks
 // per wavefront, at least the pairs' nrb + nwb; blockDim.x / 64 wavefronts).
 __global__ __launch_bounds__(512) void k_filter_long(FilterArgs a, const u32 *__restrict__ idx, u64 n, int tile) {
@@ -205,40 +213,62 @@ __global__ __launch_bounds__(512) void k_filter_long(FilterArgs a, const u32 *__
         const u64x2 *WL = L + nrb;
         const u64 *WN = NB + nrb;
         const i64 wbase = diag - 64 * b0;  // window offset of (row 0, column 0)
-        // lane owns the contiguous rows [r0, r1): one 128-base reference fetch
-        // per step serves all of them through funnel shifts
+        // lane owns the contiguous rows [r0, r1); per step each chunk of 32 of
+        // them is compared over 32 columns from three window dwords per plane
+        // (one alignbit per plane and row), and only a row with no obstacle
+        // in those columns continues 64 columns at a time
         const int rows = 2 * E + 1;
         const int S = (rows + 63) / 64;
         const int r0 = min(lane * S, rows), r1 = min(r0 + S, rows);
         int j = 0, c = 0;
         for (;;) {
-            const Bits64 q0 = lds_bits(L, NB, j);
+            // 32 read bases from j (one alignbit per plane)
+            const u32 kq = (u32)j >> 5, sq = (u32)j & 31u;
+            const u32 ql = __builtin_amdgcn_alignbit(plane_dw(L, 0, kq + 1), plane_dw(L, 0, kq), sq);
+            const u32 qh = __builtin_amdgcn_alignbit(plane_dw(L, 1, kq + 1), plane_dw(L, 1, kq), sq);
+            const u32 qn = __builtin_amdgcn_alignbit(nb_dw(NB, kq + 1), nb_dw(NB, kq), sq);
+            const int left = m - j;
             int best = 0;
-            for (int s0 = r0; s0 < r1; s0 += 64) {  // chunks of <= 64 rows (funnel shifts < 64)
-                const i64 pos = wbase + (s0 - E) + j;  // window offset of (row s0, column j)
-                const Bits64 wa = lds_bits(WL, WN, pos), wb = lds_bits(WL, WN, pos + 64);
-                const int cnt = min(64, r1 - s0);
+            for (int s0 = r0; s0 < r1; s0 += 32) {  // chunks of <= 32 rows
+                // window bases of rows s0.. at column j start at p0; three
+                // dwords per plane cover every row of the chunk
+                const i64 p0 = wbase + (s0 - E) + j;
+                const u32 k0 = (u32)((u64)p0 >> 5), sh0 = (u32)p0 & 31u;
+                const u32 l0 = plane_dw(WL, 0, k0), l1 = plane_dw(WL, 0, k0 + 1), l2 = plane_dw(WL, 0, k0 + 2);
+                const u32 h0 = plane_dw(WL, 1, k0), h1 = plane_dw(WL, 1, k0 + 1), h2 = plane_dw(WL, 1, k0 + 2);
+                const u32 n0 = nb_dw(WN, k0), n1 = nb_dw(WN, k0 + 1), n2 = nb_dw(WN, k0 + 2);
+                const int cnt = min(32, r1 - s0);
+                const int split = min(cnt, 32 - (int)sh0);  // rows whose window starts in dword k0
                 for (int i = 0; i < cnt; i++) {
-                    Bits64 w;
-                    w.lo = funnel(wa.lo, wb.lo, (u32)i);
-                    w.hi = funnel(wa.hi, wb.hi, (u32)i);
-                    w.nb = funnel(wa.nb, wb.nb, (u32)i);
-                    u64 mm = mismatch(q0, w);
+                    u32 wl, wh, wn;
+                    if (i < split) {
+                        const u32 sh = sh0 + (u32)i;
+                        wl = __builtin_amdgcn_alignbit(l1, l0, sh);
+                        wh = __builtin_amdgcn_alignbit(h1, h0, sh);
+                        wn = __builtin_amdgcn_alignbit(n1, n0, sh);
+                    } else {
+                        const u32 sh = sh0 + (u32)i - 32u;
+                        wl = __builtin_amdgcn_alignbit(l2, l1, sh);
+                        wh = __builtin_amdgcn_alignbit(h2, h1, sh);
+                        wn = __builtin_amdgcn_alignbit(n2, n1, sh);
+                    }
+                    const u32 mm = (ql ^ wl) | (qh ^ wh) | qn | wn;
                     int run;
                     if (mm) {
-                        run = (int)__builtin_ctzll(mm);
-                    } else {  // 64 matching columns: continue word by word
-                        run = 64;
+                        run = (int)__builtin_ctz(mm);
+                    } else {  // 32 matching columns: continue 64 at a time
+                        run = 32;
+                        const i64 pos = p0 + i;
                         while (j + run < m) {
-                            mm = mismatch(lds_bits(L, NB, j + run), lds_bits(WL, WN, pos + i + run));
-                            if (mm) {
-                                run += (int)__builtin_ctzll(mm);
+                            const u64 m2 = mismatch(lds_bits(L, NB, j + run), lds_bits(WL, WN, pos + run));
+                            if (m2) {
+                                run += (int)__builtin_ctzll(m2);
                                 break;
                             }
                             run += 64;
                         }
                     }
-                    best = max(best, min(run, m - j));
+                    best = max(best, min(run, left));
                 }
             }
             best = group_max<64>(best);
