@@ -251,22 +251,14 @@ __device__ inline void filter_batch(const FusedArgs &a, const QEntry *q, int qn,
         const u64 *rn = a.ref_nb + gm.blk;
         const i64 L = (i64)gm.len;
         const bool hn = meta_has_n(gm);
-        // words wholly past the read's end stay all obstacles (the read's own
-        // planes mark those bases as N, so computing them changes nothing)
         Bits64 w0 = fetch_ref(rl, rn, L, hn, base);
+        Bits64 w1 = fetch_ref(rl, rn, L, hn, base + 64);
+        Bits64 w2 = fetch_ref(rl, rn, L, hn, base + 128);
+        Bits64 w3 = fetch_ref(rl, rn, L, hn, base + 192);
         row.w0 = (pr.plane[0] ^ w0.lo) | (pr.plane[4] ^ w0.hi) | pr.plane[8] | w0.nb;
-        if (m > 64) {
-            Bits64 w1 = fetch_ref(rl, rn, L, hn, base + 64);
-            row.w1 = (pr.plane[1] ^ w1.lo) | (pr.plane[5] ^ w1.hi) | pr.plane[9] | w1.nb;
-        }
-        if (m > 128) {
-            Bits64 w2 = fetch_ref(rl, rn, L, hn, base + 128);
-            row.w2 = (pr.plane[2] ^ w2.lo) | (pr.plane[6] ^ w2.hi) | pr.plane[10] | w2.nb;
-        }
-        if (m > 192) {
-            Bits64 w3 = fetch_ref(rl, rn, L, hn, base + 192);
-            row.w3 = (pr.plane[3] ^ w3.lo) | (pr.plane[7] ^ w3.hi) | pr.plane[11] | w3.nb;
-        }
+        row.w1 = (pr.plane[1] ^ w1.lo) | (pr.plane[5] ^ w1.hi) | pr.plane[9] | w1.nb;
+        row.w2 = (pr.plane[2] ^ w2.lo) | (pr.plane[6] ^ w2.hi) | pr.plane[10] | w2.nb;
+        row.w3 = (pr.plane[3] ^ w3.lo) | (pr.plane[7] ^ w3.hi) | pr.plane[11] | w3.nb;
     }
     int j = 0, c = 0;
     for (;;) {

@@ -8,6 +8,10 @@ benchmark times (fused), against
     bit everywhere);
   * properties that hold at any size: canonical candidate order, >= min_hits,
     accept == (approx <= E), approx <= E + 1, per-taxon conservation.
+
+The uneven workload (2M reads up to 10 kbp) and the strain workload (4 Gbp,
+10M reads) are checked the same way: every read across the execution forms,
+and seeded samples (or a reduced strain database) against the oracle.
 """
 import numpy as np
 import pytest
@@ -22,10 +26,14 @@ FIELDS = ("cand_offsets", "read_accepted", "read_E", "genome", "diag", "hits", "
 
 
 @pytest.fixture(scope="module")
-def full():
+def gpu():
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
+
+
+@pytest.fixture(scope="module")
+def full(gpu):
     import paper_2311_02029_amd as mt
     db = synth.workload_batched_db()
     reads = synth.workload_batched_reads(db, 1_000_000)
@@ -41,7 +49,14 @@ def full():
     res = ix.classify(dr, min_hits=3, top_n=3, e_value=7, mode=mt.MT_MODE_FUSED_GRAPH)
     graph = res.to_host()
     res.free()
-    return dict(ga=ga, reads=reads, fused=fused, stage=stage, graph=graph)
+    cache = {}
+
+    def oracle_index():
+        if "ix" not in cache:
+            cache["ix"] = oracle.Index(ga, 21, 11)
+        return cache["ix"]
+
+    return dict(ga=ga, reads=reads, fused=fused, stage=stage, graph=graph, oracle=oracle_index)
 
 
 def _slice(res, idx):
@@ -69,8 +84,7 @@ def test_fused_equals_per_stage_on_every_read(full):
 def test_sampled_reads_match_oracle(full):
     reads = full["reads"]
     idx = np.sort(np.random.default_rng(2024).choice(reads.n, 3000, replace=False))
-    oix = oracle.Index(full["ga"], 21, 11)
-    ref = oix.classify(reads.subset(idx), 3, 3, 0, 7)
+    ref = full["oracle"]().classify(reads.subset(idx), 3, 3, 0, 7)
     got = _slice(full["fused"], idx)
     for f in ("cand_offsets", "read_accepted", "read_E", "genome", "diag", "hits", "approx", "accept"):
         a, b = np.asarray(got[f]), np.asarray(ref[f])
@@ -103,3 +117,87 @@ def test_properties_at_full_size(full):
     n_unique = int(res["unique"].sum())
     assert n_unique <= n_acc and int(res["multi"].sum()) >= 2 * (n_acc - n_unique)
     assert n_acc > 0.99 * n
+
+
+# ---------------------------------------------------------------- uneven --
+
+@pytest.fixture(scope="module")
+def uneven(full):
+    """The uneven workload at full size: 2M reads, 95% of 75-300 bp and 5% of
+    1-10 kbp, E = ceil(5% of length), on the same 500 Mbp database."""
+    import paper_2311_02029_amd as mt
+    db = synth.workload_batched_db()
+    reads = synth.workload_uneven_reads(db, 2_000_000)
+    ix = mt.Index(mt.to_device(full["ga"]), 21, 11)
+    dr = mt.to_device(reads)
+    out = {}
+    for name, mode in (("fused", mt.MT_MODE_FUSED), ("stage", mt.MT_MODE_PER_STAGE),
+                       ("graph", mt.MT_MODE_FUSED_GRAPH)):
+        res = ix.classify(dr, min_hits=3, top_n=3, e_mode=mt.MT_E_CEIL_PERMILLE, e_value=50, mode=mode)
+        out[name] = res.to_host()
+        res.free()
+    out["reads"] = reads
+    return out
+
+
+def test_uneven_all_forms_agree_on_every_read(uneven):
+    for other in ("stage", "graph"):
+        for f in FIELDS:
+            assert np.array_equal(uneven["fused"][f], uneven[other][f]), (other, f)
+        assert uneven["fused"]["unmapped"] == uneven[other]["unmapped"], other
+
+
+def test_uneven_sampled_reads_match_oracle(full, uneven):
+    """A seeded sample of 2000 short and 60 long reads against the oracle."""
+    reads = uneven["reads"]
+    lens = reads.lengths()
+    rng = np.random.default_rng(2025)
+    idx = np.sort(np.concatenate([rng.choice(np.flatnonzero(lens <= 300), 2000, replace=False),
+                                  rng.choice(np.flatnonzero(lens > 300), 60, replace=False)]))
+    ref = full["oracle"]().classify(reads.subset(idx), 3, 3, 1, 50)
+    got = _slice(uneven["fused"], idx)
+    for f in ("cand_offsets", "read_accepted", "read_E", "genome", "diag", "hits", "approx", "accept"):
+        a, b = np.asarray(got[f]), np.asarray(ref[f])
+        assert a.shape == b.shape and np.array_equal(a.astype(b.dtype), b), f
+
+
+# --------------------------------------------------------------- strains --
+
+def test_strains_full_size_forms_agree(gpu):
+    """The dense-candidate workload at full size (2,000 strain genomes = 4 Gbp,
+    10M reads): fused and per-stage agree on every read, and the candidate
+    lists are dense (several near-duplicate strains per read)."""
+    import paper_2311_02029_amd as mt
+    db = synth.workload_strains_db()
+    reads = synth.workload_strain_reads(db, 10_000_000)
+    ix = mt.Index(mt.to_device(db.ascii()), 21, 11)
+    del db
+    dr = mt.to_device(reads)
+    res = ix.classify(dr, mode=mt.MT_MODE_FUSED)
+    fused = res.to_host()
+    res.free()
+    res = ix.classify(dr, mode=mt.MT_MODE_PER_STAGE)
+    stage = res.to_host()
+    res.free()
+    for f in FIELDS:
+        assert np.array_equal(fused[f], stage[f]), f
+    assert len(fused["genome"]) > 2.5 * reads.n
+
+
+def test_strains_reduced_database_matches_oracle(gpu):
+    """The strain structure on a database the oracle indexes in seconds (40
+    roots x 5 strains x 2 Mbp = 400 Mbp): 2000 reads against the oracle."""
+    import paper_2311_02029_amd as mt
+    db = synth.workload_strains_db(n_roots=40)
+    reads = synth.workload_strain_reads(db, 2000)
+    ga = db.ascii()
+    ix = mt.Index(mt.to_device(ga), 21, 11)
+    res = ix.classify(mt.to_device(reads), mode=mt.MT_MODE_FUSED)
+    got = res.to_host()
+    res.free()
+    ref = oracle.Index(ga, 21, 11).classify(reads, 3, 3, 0, 7)
+    for f in ("cand_offsets", "read_accepted", "read_E", "genome", "diag", "hits", "approx", "accept", "unique",
+              "multi"):
+        assert np.array_equal(np.asarray(got[f]), np.asarray(ref[f]).astype(got[f].dtype)), f
+    assert got["unmapped"] == ref["unmapped"]
+    assert int(got["multi"].sum()) > 0
