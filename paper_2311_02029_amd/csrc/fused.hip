@@ -101,6 +101,12 @@ __device__ inline void wave_sync() {
 
 __device__ inline u64 ballot64(bool p) { return __ballot(p); }
 
+// Value of v in lane l (l wave-uniform).
+__device__ inline u64 readlane64(u64 v, int l) {
+    const u32 lo = __builtin_amdgcn_readlane((u32)v, l), hi = __builtin_amdgcn_readlane((u32)(v >> 32), l);
+    return ((u64)hi << 32) | lo;
+}
+
 // Number of set bits of m below this lane.
 __device__ inline u32 lanes_below(u64 m, int lane) {
     return (u32)__popcll(lane ? m & ((~0ull) >> (64 - lane)) : 0ull);
@@ -510,9 +516,12 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
             wave_sync();
         }
 
-        // 4. table probes -> seed hits in LDS
-        int H = 0;
-        bool overflow = false;
+        // 4. table probes -> seed hits.  When every minimizer fits one round
+        // and each probe found at most one occurrence (the common case), the
+        // hits are counted in registers: one ballot per distinct location;
+        // otherwise they go through the per-read LDS table.
+        int H = 0, C = 0;
+        bool overflow = false, counted = false;
         for (int t0 = 0; t0 < nmin; t0 += 64) {
             int j = t0 + lane;
             u64 v = SLOT_NONE;
@@ -523,14 +532,32 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
                 v = bucket_lookup(a.table, a.nbuckets, stream_kmer(stream, p, k));
                 cnt = v == SLOT_NONE ? 0u : slot_count(v);
             }
-            u32 pre = cnt;
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                u32 y = __shfl_up(pre, o, 64);
-                if (lane >= o) pre += y;
+            const bool single = cnt == 1 && !(v & SLOT_MULTI);
+            const u64 sm = ballot64(single);
+            const u64 mm = ballot64(cnt != 0 && !single);  // probes with several occurrences
+            if (t0 == 0 && nmin <= 64 && mm == 0) {
+                const u64 key = single ? cand_key((u32)(v >> 32), (i64)(u32)v - p) : 0ull;
+                H = __popcll(sm);
+                for (u64 rem = sm; rem;) {
+                    const int ld = __builtin_amdgcn_readfirstlane(__builtin_ctzll(rem));
+                    const u64 kl = readlane64(key, ld);
+                    const u64 eq = ballot64(single && key == kl);
+                    const u32 c = (u32)__popcll(eq);
+                    if (c >= T) {
+                        if (lane == 0) {
+                            hh[C] = kl;
+                            ccnt[C] = (u16)c;
+                        }
+                        C++;
+                    }
+                    rem &= ~eq;
+                }
+                counted = true;
+                break;
             }
-            const u32 tot = __builtin_amdgcn_readfirstlane(__shfl(pre, 63, 64));
-            pre -= cnt;
+            u32 tot = (u32)__popcll(sm);
+            for (u64 rem = mm; rem; rem &= rem - 1)
+                tot += __builtin_amdgcn_readlane(cnt, __builtin_amdgcn_readfirstlane(__builtin_ctzll(rem)));
             if (H + (int)tot > F_HIT_CAP) {
                 overflow = true;
                 break;
@@ -576,8 +603,7 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
 
         // 5. locations with >= min_hits hits become candidates (the table is
         // emptied as it is read), then top_n by rank
-        int C = 0;
-        if (H > 0) {
+        if (!counted && H > 0) {
 #pragma unroll
             for (int q = 0; q < F_TSLOTS / 64; q++) {
                 const int t = 64 * q + lane;
