@@ -59,7 +59,7 @@ def _pct(v, q):
 
 
 def serving_bench(mt, ix, pool, seconds: float = 2.0, loads=(0.5, 0.8, 0.95), threads: int = 8,
-                  baseline_s: float = 4.0) -> dict:
+                  baseline_s: float = 4.0, n_streams: int = 0, max_batch_reads: int = 0) -> dict:
     """The served workload: requests of U{1..50,000} reads of one length in
     100-250 bp at 0.5% error, E = ceil(5% of length), against the resident
     index.  Measures
@@ -87,7 +87,8 @@ def serving_bench(mt, ix, pool, seconds: float = 2.0, loads=(0.5, 0.8, 0.95), th
         recs = [None] * len(tr)
         ids = [None] * len(tr)
         errs = []
-        with mt.Server(ix, pinned_arena_bytes=4 << 30, max_queued_requests=8192) as sv:
+        with mt.Server(ix, pinned_arena_bytes=4 << 30, max_queued_requests=8192, n_streams=n_streams,
+                       max_batch_reads=max_batch_reads) as sv:
             t0 = time.monotonic_ns()
             stop_at = None if stop_after is None else t0 + int(stop_after * 1e9)
             avail = [threading.Semaphore(0) for _ in range(threads)]
@@ -163,7 +164,7 @@ def serving_bench(mt, ix, pool, seconds: float = 2.0, loads=(0.5, 0.8, 0.95), th
 
     out = {"workload": "requests of U{1..50,000} reads x one length in {100..250} bp (16 lengths), 0.5% error, "
                        "E=ceil(5% of length), min_hits=3, top_n=3, 500 Mbp index resident; Poisson arrivals",
-           "threads": threads}
+           "threads": threads, "n_streams": n_streams or 2, "max_batch_reads": max_batch_reads or 1 << 18}
     # warm up the server path (allocator, pinned buffers)
     recs, t0 = run_served(trace(99, 64, 1.0), paced=False)
     # saturation: back to back for `seconds`
@@ -182,6 +183,8 @@ def serving_bench(mt, ix, pool, seconds: float = 2.0, loads=(0.5, 0.8, 0.95), th
         out["traces"].append(sm)
         log(f"[serve] load {load}: {sm}")
 
+    if baseline_s <= 0:
+        return out
     # sequential per-request solves on the 80% trace
     qps = 0.8 * sat_rps / mean_reads
     tr = trace(4, max(20, int(qps * seconds)), qps)
@@ -255,6 +258,11 @@ def main() -> int:
     ap.add_argument("--serving", type=int, default=1,
                     help="1: also measure the served workload (batched workload only); 0: skip it")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="length of each served trace")
+    ap.add_argument("--serve-streams", type=int, default=0, help="server worker streams (0: library default, 2)")
+    ap.add_argument("--serve-max-batch", type=int, default=0,
+                    help="reads per served device batch (0: library default, 262,144)")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="only the served workload (no batched timing, no sequential baselines)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times), to scale HBM byte counters")
     args = ap.parse_args()
@@ -326,6 +334,12 @@ def main() -> int:
     log(f"[bench] index built in {index_s:.2f}s: {info['n_minimizers']} minimizers, {info['n_keys']} keys, "
         f"{info['device_bytes'] / 2**30:.2f} GiB")
     del dgen
+
+    if args.serve_only:
+        sv = serving_bench(mt, ix, pool, seconds=args.serve_seconds, n_streams=args.serve_streams,
+                           max_batch_reads=args.serve_max_batch, baseline_s=0)
+        print(json.dumps({"metric": "served reads/s; p50/p99 request latency", "serving": sv}), flush=True)
+        return 0
 
     mode = {"fused": mt.MT_MODE_FUSED, "graph": mt.MT_MODE_FUSED_GRAPH, "per_stage": mt.MT_MODE_PER_STAGE}[args.mode]
     q = dict(min_hits=3, top_n=3, e_mode=e_mode, e_value=e_value, mode=mode)
@@ -402,7 +416,8 @@ def main() -> int:
 
     serving = None
     if pool is not None:
-        serving = serving_bench(mt, ix, pool, seconds=args.serve_seconds)
+        serving = serving_bench(mt, ix, pool, seconds=args.serve_seconds, n_streams=args.serve_streams,
+                                max_batch_reads=args.serve_max_batch)
 
     cpu = None
     if args.cpu_reads > 0:

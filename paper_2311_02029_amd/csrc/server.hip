@@ -482,7 +482,7 @@ extern "C" int mt_server_create(const mt_index *index, const mt_server_params *p
         MT_REQUIRE(p.reserved[0] == 0 && p.reserved[1] == 0 && p.reserved[2] == 0 && p.reserved[3] == 0,
                    "reserved fields must be 0");
         if (!p.mem_budget_bytes) p.mem_budget_bytes = 4ull << 30;
-        if (!p.max_batch_reads) p.max_batch_reads = 1ull << 20;
+        if (!p.max_batch_reads) p.max_batch_reads = 1ull << 18;
         if (!p.n_streams) p.n_streams = 2;
         if (!p.max_queued_requests) p.max_queued_requests = 4096;
         if (!p.pinned_arena_bytes) p.pinned_arena_bytes = 1ull << 30;
