@@ -164,7 +164,7 @@ def serving_bench(mt, ix, pool, seconds: float = 2.0, loads=(0.5, 0.8, 0.95), th
 
     out = {"workload": "requests of U{1..50,000} reads x one length in {100..250} bp (16 lengths), 0.5% error, "
                        "E=ceil(5% of length), min_hits=3, top_n=3, 500 Mbp index resident; Poisson arrivals",
-           "threads": threads, "n_streams": n_streams or 2, "max_batch_reads": max_batch_reads or 1 << 18}
+           "threads": threads, "n_streams": n_streams or 4, "max_batch_reads": max_batch_reads or 1 << 18}
     # warm up the server path (allocator, pinned buffers)
     recs, t0 = run_served(trace(99, 64, 1.0), paced=False)
     # saturation: back to back for `seconds`
@@ -258,7 +258,7 @@ def main() -> int:
     ap.add_argument("--serving", type=int, default=1,
                     help="1: also measure the served workload (batched workload only); 0: skip it")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="length of each served trace")
-    ap.add_argument("--serve-streams", type=int, default=0, help="server worker streams (0: library default, 2)")
+    ap.add_argument("--serve-streams", type=int, default=0, help="server worker streams (0: library default, 4)")
     ap.add_argument("--serve-max-batch", type=int, default=0,
                     help="reads per served device batch (0: library default, 262,144)")
     ap.add_argument("--serve-only", action="store_true",

@@ -224,7 +224,7 @@ typedef struct mt_server_params {
     uint64_t mem_budget_bytes;      /* device bytes admitted at once; 0 = 4 GiB */
     uint64_t max_batch_reads;       /* reads per device batch; 0 = 262,144 (smaller batches
                                        cut the latency tail, larger ones raise throughput) */
-    uint32_t n_streams;             /* batches in flight (worker threads); 0 = 2 */
+    uint32_t n_streams;             /* batches in flight (worker threads); 0 = 4 */
     uint32_t max_queued_requests;   /* submitted and not yet waited for; 0 = 4096 */
     uint64_t pinned_arena_bytes;    /* pinned host memory for queued reads; 0 = 1 GiB */
     uint32_t reserved[4];           /* must be 0 */

@@ -128,6 +128,7 @@ struct Request {
     u64 next = 0;              // first read not yet in a batch
     u32 open = 0;              // batches holding reads of this request
     unsigned long long *counts = nullptr;  // device: unique[n_taxa], multi[n_taxa], unmapped
+    hipEvent_t zeroed = nullptr;           // recorded on the control stream once counts are zero
     std::map<u64, Piece> pieces;           // by first read
     int status = MT_OK;
     std::string error;
@@ -166,15 +167,26 @@ inline u64 batch_bytes(u64 reads, u64 bases, const mt_query_params &q) {
 }
 
 // Copies n bases and reports whether each is A, C, G, T or N in either case.
-inline bool copy_bases(u8 *__restrict__ dst, const u8 *__restrict__ src, u64 n) {
-    u32 bad = 0;
-    for (u64 i = 0; i < n; i++) {
-        const u8 c = src[i];
-        const u8 u = c & 0xDF;  // upper case; no other byte maps onto these letters
-        bad |= (u32)((u != 'A') & (u != 'C') & (u != 'G') & (u != 'T') & (u != 'N'));
-        dst[i] = c;
-    }
+#define MT_COPY_BASES_BODY                                                                                  \
+    u8 bad = 0;                                                                                              \
+    for (u64 i = 0; i < n; i++) {                                                                            \
+        const u8 c = src[i];                                                                                 \
+        const u8 u = c & 0xDF; /* upper case; no other byte maps onto these letters */                      \
+        bad |= (u8)((u != 'A') & (u != 'C') & (u != 'G') & (u != 'T') & (u != 'N'));                        \
+        dst[i] = c;                                                                                          \
+    }                                                                                                        \
     return bad == 0;
+
+__attribute__((target("avx2"))) static bool copy_bases_avx2(u8 *__restrict__ dst, const u8 *__restrict__ src,
+                                                             u64 n) {
+    MT_COPY_BASES_BODY
+}
+static bool copy_bases_plain(u8 *__restrict__ dst, const u8 *__restrict__ src, u64 n) { MT_COPY_BASES_BODY }
+#undef MT_COPY_BASES_BODY
+
+inline bool copy_bases(u8 *dst, const u8 *src, u64 n) {
+    static const bool avx2 = __builtin_cpu_supports("avx2");
+    return avx2 ? copy_bases_avx2(dst, src, n) : copy_bases_plain(dst, src, n);
 }
 
 }  // namespace serve
@@ -192,8 +204,8 @@ struct mt_server {
     int device = 0;
     PinnedArena arena;
     hipStream_t ctl = nullptr;  // zeroes request counters at submit
-    std::mutex ctl_mu;
     std::mutex mu;
+    std::vector<hipEvent_t> free_events;  // guarded by mu
     std::condition_variable cv_work, cv_done;
     std::unordered_map<u64, std::unique_ptr<Request>> reqs;
     std::deque<Request *> queue;  // requests with reads not yet in a batch
@@ -295,6 +307,7 @@ void mt_server::run_batch(Batch &b, hipStream_t s, Pinned &h_in, Pinned &h_out, 
     mt_result_init(res, n, ix->n_taxa, s);
     classify_fused(*ix, q, seqs, rb, res, tm, s, false);
     const u64 nc = res.n_cands;
+    for (u32 i = 0; i < ns; i++) MT_HIP(hipStreamWaitEvent(s, b.slices[i].req->zeroed, 0));
     launch_reduce_slots(res, *ix, d_slot, ns, d_cnt, s);
 
     // Outputs back to the host in one pinned block.
@@ -399,6 +412,8 @@ void mt_server::finish(Request *r, hipStream_t s) {
     pool_free(r->counts);
     r->counts = nullptr;
     std::lock_guard<std::mutex> lk(mu);
+    if (r->zeroed) free_events.push_back(r->zeroed);
+    r->zeroed = nullptr;
     arena.release(r->arena_off, r->arena_bytes);
     if (res) res->done_ns = now_ns();
     r->result = std::move(res);
@@ -483,7 +498,7 @@ extern "C" int mt_server_create(const mt_index *index, const mt_server_params *p
                    "reserved fields must be 0");
         if (!p.mem_budget_bytes) p.mem_budget_bytes = 4ull << 30;
         if (!p.max_batch_reads) p.max_batch_reads = 1ull << 18;
-        if (!p.n_streams) p.n_streams = 2;
+        if (!p.n_streams) p.n_streams = 4;
         if (!p.max_queued_requests) p.max_queued_requests = 4096;
         if (!p.pinned_arena_bytes) p.pinned_arena_bytes = 1ull << 30;
         MT_REQUIRE(p.n_streams <= 16, "n_streams must be at most 16");
@@ -562,12 +577,21 @@ extern "C" int mt_server_submit(mt_server *sv, const mt_query_params *params, co
         r->seq = dst + off_bytes;
         const u64 nt = sv->ix->n_taxa;
         try {
+            // zeroed asynchronously; workers wait for the event before adding
+            {
+                std::lock_guard<std::mutex> lk(sv->mu);
+                if (!sv->free_events.empty()) {
+                    r->zeroed = sv->free_events.back();
+                    sv->free_events.pop_back();
+                }
+            }
+            if (!r->zeroed) MT_HIP(hipEventCreateWithFlags(&r->zeroed, hipEventDisableTiming));
             r->counts = (unsigned long long *)pool_alloc((2 * nt + 1) * 8);
-            std::lock_guard<std::mutex> lk(sv->ctl_mu);
             MT_HIP(hipMemsetAsync(r->counts, 0, (2 * nt + 1) * 8, sv->ctl));
-            MT_HIP(hipStreamSynchronize(sv->ctl));
+            MT_HIP(hipEventRecord(r->zeroed, sv->ctl));
         } catch (...) {
             if (r->counts) pool_free(r->counts);
+            if (r->zeroed) (void)hipEventDestroy(r->zeroed);
             give_back();
             throw;
         }
@@ -629,9 +653,12 @@ extern "C" int mt_server_destroy(mt_server *sv) {
     }
     sv->cv_work.notify_all();
     for (auto &t : sv->workers) t.join();
-    for (auto &kv : sv->reqs)
+    for (auto &kv : sv->reqs) {
         if (kv.second->counts) mt::pool_free(kv.second->counts);
+        if (kv.second->zeroed) (void)hipEventDestroy(kv.second->zeroed);
+    }
     sv->reqs.clear();
+    for (hipEvent_t e : sv->free_events) (void)hipEventDestroy(e);
     if (sv->ctl) (void)hipStreamDestroy(sv->ctl);
     delete sv;
     return MT_OK;
