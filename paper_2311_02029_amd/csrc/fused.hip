@@ -142,20 +142,23 @@ __device__ inline int reg_run(RowBits r, int j) {
     }
 }
 
-// The 4-slot bucket probe: all four slots are loaded before any compare.
+// The 4-slot bucket probe: all four slots are loaded before any compare, and
+// the first slot (in slot order) that holds x or is empty decides, through a
+// chain of selects rather than branches.  Slots fill in order, so a bucket
+// with an empty slot and no x means x is absent; a full bucket without x
+// sends the probe on to the next bucket.
 __device__ inline u64 bucket_lookup(const u64x2 *__restrict__ table, u64 nbuckets, u64 x) {
     u64 b = bucket_of(x, nbuckets);
     for (;;) {
         const u64x2 *bk = table + b * 4;
-        u64x2 e0 = bk[0], e1 = bk[1], e2 = bk[2], e3 = bk[3];
-        if (e0.lo == x) return e0.hi;
-        if (e0.lo == SLOT_EMPTY_KEY) return SLOT_NONE;
-        if (e1.lo == x) return e1.hi;
-        if (e1.lo == SLOT_EMPTY_KEY) return SLOT_NONE;
-        if (e2.lo == x) return e2.hi;
-        if (e2.lo == SLOT_EMPTY_KEY) return SLOT_NONE;
-        if (e3.lo == x) return e3.hi;
-        if (e3.lo == SLOT_EMPTY_KEY) return SLOT_NONE;
+        const u64x2 e0 = bk[0], e1 = bk[1], e2 = bk[2], e3 = bk[3];
+        const bool d0 = e0.lo == x || e0.lo == SLOT_EMPTY_KEY, d1 = e1.lo == x || e1.lo == SLOT_EMPTY_KEY;
+        const bool d2 = e2.lo == x || e2.lo == SLOT_EMPTY_KEY, d3 = e3.lo == x || e3.lo == SLOT_EMPTY_KEY;
+        u64 v = e3.lo == x ? e3.hi : SLOT_NONE;
+        v = d2 ? (e2.lo == x ? e2.hi : SLOT_NONE) : v;
+        v = d1 ? (e1.lo == x ? e1.hi : SLOT_NONE) : v;
+        v = d0 ? (e0.lo == x ? e0.hi : SLOT_NONE) : v;
+        if (d0 | d1 | d2 | d3) return v;
         b = (b + 1 == nbuckets) ? 0 : b + 1;
     }
 }
