@@ -568,11 +568,15 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
             if (cnt) {
                 if (!(v & SLOT_MULTI)) {
                     table_add(tkey, tcnt, cand_key((u32)(v >> 32), (i64)(u32)v - p));
-                } else {
-                    u64 st = slot_start(v);
-                    for (u32 u = 0; u < cnt; u++) {
-                        u64 gp = a.occ[st + u];
-                        table_add(tkey, tcnt, cand_key((u32)(gp >> 32), (i64)(u32)gp - p));
+                } else {  // several occurrences: four loads in flight at a time
+                    const u64 st = slot_start(v);
+                    for (u32 u0 = 0; u0 < cnt; u0 += 4) {
+                        u64 gp[4];
+#pragma unroll
+                        for (int t = 0; t < 4; t++) gp[t] = u0 + t < cnt ? a.occ[st + u0 + t] : 0ull;
+#pragma unroll
+                        for (int t = 0; t < 4; t++)
+                            if (u0 + t < cnt) table_add(tkey, tcnt, cand_key((u32)(gp[t] >> 32), (i64)(u32)gp[t] - p));
                     }
                 }
             }
