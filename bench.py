@@ -357,6 +357,7 @@ def main() -> int:
             + "; ".join(f"{b['name']} ({b['pairs']} pairs): " + ", ".join(f"{k} {v:.3f} ms" for k, v in b["ms"].items())
                         for b in info if b["pairs"]))
 
+    n_cands = 0
     for i in range(args.warmup):
         t = time.time()
         r = ix.classify(dreads, **q)
