@@ -243,6 +243,7 @@ def main() -> int:
                          "HIP graph; per_stage: one launch per step")
     ap.add_argument("--E", type=int, default=7)
     ap.add_argument("--reads", type=int, default=1_000_000)
+    ap.add_argument("--top-n", type=int, default=3, help="candidates kept per read (0 keeps all)")
     ap.add_argument("--workload", default="batched", choices=["batched", "uneven", "strains"],
                     help="batched: 500 Mbp, 1M x 150 bp, E=7 (the metric's workload); uneven: same database, "
                          "2M reads of 75-300 bp plus 5%% of 1-10 kbp, E=ceil(5%% of length); strains: 2,000 "
@@ -297,18 +298,18 @@ def main() -> int:
         db = synth.workload_strains_db()
         reads = synth.workload_strain_reads(db, args.reads if args.reads != 1_000_000 else 10_000_000)
         workload = (f"strains: 2,000 genomes (400 roots x 5 strains, 1-5% divergence) = 4 Gbp, {reads.n} x 150 bp "
-                    f"at 1% error, k=21 w=11, min_hits=3, top_n=3, E={args.E}")
+                    f"at 1% error, k=21 w=11, min_hits=3, top_n={args.top_n}, E={args.E}")
     elif args.workload == "uneven":
         log("[bench] generating the database and the uneven reads ...")
         db = synth.workload_batched_db(n_genomes=args.genomes)
         reads = synth.workload_uneven_reads(db, args.reads if args.reads != 1_000_000 else 2_000_000)
         e_mode, e_value = mt.MT_E_CEIL_PERMILLE, 50
         workload = (f"uneven: 500 Mbp / 200 genomes, {reads.n} reads (95% of 75-300 bp, 5% of 1-10 kbp), k=21 w=11, "
-                    "min_hits=3, top_n=3, E=ceil(5% of length)")
+                    f"min_hits=3, top_n={args.top_n}, E=ceil(5% of length)")
     else:
         db = synth.workload_batched_db(n_genomes=args.genomes)
         reads = synth.workload_batched_reads(db, args.reads)
-        workload = (f"500 Mbp / 200 genomes, {reads.n // 1000}k x 150 bp reads, k=21 w=11, min_hits=3, top_n=3, "
+        workload = (f"500 Mbp / 200 genomes, {reads.n // 1000}k x 150 bp reads, k=21 w=11, min_hits=3, top_n={args.top_n}, "
                     f"E={args.E}")
     log(f"[bench] data generated in {time.time() - t:.1f}s: {db.n} genomes, {reads.n} reads, "
         f"{int(reads.offsets[-1])} bases")
@@ -342,7 +343,7 @@ def main() -> int:
         return 0
 
     mode = {"fused": mt.MT_MODE_FUSED, "graph": mt.MT_MODE_FUSED_GRAPH, "per_stage": mt.MT_MODE_PER_STAGE}[args.mode]
-    q = dict(min_hits=3, top_n=3, e_mode=e_mode, e_value=e_value, mode=mode)
+    q = dict(min_hits=3, top_n=args.top_n, e_mode=e_mode, e_value=e_value, mode=mode)
 
     tune = None
     if args.autotune < 0:
@@ -428,7 +429,7 @@ def main() -> int:
         log(f"[bench] oracle index built in {time.time() - t:.1f}s (not timed)")
         sample = reads.subset(np.arange(min(args.cpu_reads, reads.n)))
         t = time.perf_counter()
-        out = oix.classify(sample, 3, 3, e_mode, e_value)
+        out = oix.classify(sample, 3, args.top_n, e_mode, e_value)
         dt = time.perf_counter() - t
         cpu = {"value": round(len(out["genome"]) / dt, 1), "unit": "pairs/s", "cores": 1, "kind": "oracle",
                "reads_per_s": round(sample.n / dt, 1),

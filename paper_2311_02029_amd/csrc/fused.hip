@@ -18,8 +18,9 @@
 //      ctz of the row bits plus a max over the group;
 //   7. the read's accept flag and its per-taxon unique / multi count.
 // Reads beyond the kernel's limits (longer than 256 bases, E above 31, more
-// than 256 seed hits) are queued and finished by the per-stage kernels, so
-// every read gets the same result as in per-stage mode.
+// than 256 seed hits, or more than 8 candidates when every candidate is kept)
+// are queued and finished by the per-stage kernels, so every read gets the
+// same result as in per-stage mode; top_n above 8 runs per stage throughout.
 #include "classify.hpp"
 
 namespace mt {
@@ -39,7 +40,7 @@ constexpr int F_MAX_M = 256;     // longest read the fused kernel takes
 constexpr int F_HIT_CAP = 256;   // seed hits per read (distinct locations fit the table)
 constexpr int F_TSLOTS = 256;    // per-read LDS hash table of locations
 constexpr int F_MAX_E = 31;      // 2E + 1 rows fit one wavefront
-constexpr int F_MAX_TOPN = 4;
+constexpr int F_MAX_TOPN = 8;  // staged candidates per read (top_n = 0 keeps up to this many)
 constexpr int F_QCAP = 4;        // queued (read, candidate) pairs per wave: one per 16-lane group
 constexpr int F_PCAP = 8;        // reads per wave waiting for their filter results
 constexpr int F_WORDS = F_MAX_M / 16 + 2;  // 2-bit stream words (16 bases per word) + padding
@@ -51,6 +52,7 @@ struct FusedArgs {
     const u64 *off;
     u64 n;
     u32 k, w, min_hits, top_n, e_mode, e_value;
+    u32 ncap;  // staging slots per read: top_n, or F_MAX_TOPN when top_n = 0 (keep all)
     const u64x2 *table;
     u64 nbuckets;
     const u64 *occ;
@@ -407,7 +409,7 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
         tcnt[t] = 0;
     }
 
-    const u32 k = a.k, T = a.min_hits ? a.min_hits : 1u, N = a.top_n;
+    const u32 k = a.k, T = a.min_hits ? a.min_hits : 1u, N = a.ncap;
     const u64 kmask = (1ull << k) - 1;
     const u64 stride = (u64)gridDim.x * F_WPB;
     u32 wflags = 0;
@@ -631,6 +633,16 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
             }
         }
         wave_sync();
+        if (a.top_n == 0 && C > (int)N) {
+            // keep-all with more candidates than staging slots: per-stage finish
+            if (lane == 0) {
+                a.fb_list[atomicAdd(a.fb_count, 1u)] = (u32)r;
+                a.ncand[r] = 0;
+            }
+            cur = nxt;
+            wave_sync();
+            continue;
+        }
         const int nc = C < (int)N ? C : (int)N;
         for (int t0 = 0; t0 < C; t0 += 64) {
             int cidx = t0 + lane;
@@ -768,7 +780,7 @@ __global__ void k_subset_copy(const u8 *__restrict__ seq, const u64 *__restrict_
     for (u64 t = threadIdx.x; t < len; t += blockDim.x) sub_seq[dst + t] = seq[src + t];
 }
 
-__global__ void k_subset_scatter(const u32 *__restrict__ list, u64 n, u32 top_n, const u64 *__restrict__ sub_off,
+__global__ void k_subset_scatter(const u32 *__restrict__ list, u64 n, u32 stride, const u64 *__restrict__ sub_off,
                                  const u8 *__restrict__ sub_acc, const u32 *__restrict__ sg,
                                  const i64 *__restrict__ sd, const u32 *__restrict__ sh,
                                  const u16 *__restrict__ sa, const u8 *__restrict__ sc, u32 *__restrict__ ncand,
@@ -781,13 +793,34 @@ __global__ void k_subset_scatter(const u32 *__restrict__ list, u64 n, u32 top_n,
     u64 b = sub_off[i], e = sub_off[i + 1];
     ncand[r] = (u32)(e - b);
     read_accepted[r] = sub_acc[i];
-    for (u64 c = b; c < e; c++) {
-        u64 o = r * top_n + (c - b);
+    for (u64 c = b; c < e && c - b < stride; c++) {  // the rest (keep-all) is placed by k_subset_place
+        u64 o = r * stride + (c - b);
         st_genome[o] = sg[c];
         st_diag[o] = sd[c];
         st_hits[o] = sh[c];
         st_approx[o] = sa[c];
         st_accept[o] = sc[c];
+    }
+}
+
+// Candidates of the per-stage finished reads straight into the final arrays
+// (keep-all reads may have more candidates than staging slots).
+__global__ void k_subset_place(const u32 *__restrict__ list, u64 n, const u64 *__restrict__ sub_off,
+                               const u32 *__restrict__ sg, const i64 *__restrict__ sd, const u32 *__restrict__ sh,
+                               const u16 *__restrict__ sa, const u8 *__restrict__ sc,
+                               const u64 *__restrict__ cand_off, u64 cap, u32 *__restrict__ genome,
+                               i64 *__restrict__ diag, u32 *__restrict__ hits, u16 *__restrict__ approx,
+                               u8 *__restrict__ accept) {
+    u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const u64 r = list[i], b = sub_off[i], e = sub_off[i + 1], o = cand_off[r];
+    if (o + (e - b) > cap) return;  // never past the candidate capacity
+    for (u64 c = b; c < e; c++) {
+        genome[o + c - b] = sg[c];
+        diag[o + c - b] = sd[c];
+        hits[o + c - b] = sh[c];
+        approx[o + c - b] = sa[c];
+        accept[o + c - b] = sc[c];
     }
 }
 
@@ -797,6 +830,7 @@ __global__ void k_add_u64(unsigned long long *__restrict__ dst, const u64 *__res
 }
 
 __global__ void k_compact_staged(const u32 *__restrict__ gate, const u64 *__restrict__ cand_off, u64 n, u32 top_n,
+                                 u64 cap,
                                  const u32 *__restrict__ st_genome, const i64 *__restrict__ st_diag,
                                  const u32 *__restrict__ st_hits, const u16 *__restrict__ st_approx,
                                  const u8 *__restrict__ st_accept, u32 *__restrict__ genome, i64 *__restrict__ diag,
@@ -805,7 +839,7 @@ __global__ void k_compact_staged(const u32 *__restrict__ gate, const u64 *__rest
     if (r >= n || *gate) return;
     u64 o = cand_off[r], c = cand_off[r + 1] - o;
     if (c > top_n) c = top_n;
-    if (o > n * top_n - c) return;  // never past the candidate capacity
+    if (o > cap || c > cap - o) return;  // never past the candidate capacity
     for (u64 i = 0; i < c; i++) {
         u64 s = r * top_n + i;
         genome[o + i] = st_genome[s];
@@ -838,7 +872,8 @@ static void enqueue_fused(const FusedLaunch &L, Timer *tm, hipStream_t s) {
     k_fused<<<L.blocks, 64 * F_WPB, 0, s>>>(a);
     if (tm) tm->mark("fused");
     scan_u32(a.ncand, L.res->cand_off.p, L.n, s);
-    k_compact_staged<<<grid_for(L.n, 256), 256, 0, s>>>(L.ctl + CTL_GATE, L.res->cand_off.p, L.n, L.N, a.st_genome,
+    k_compact_staged<<<grid_for(L.n, 256), 256, 0, s>>>(L.ctl + CTL_GATE, L.res->cand_off.p, L.n, L.N, L.res->cap,
+                                                        a.st_genome,
                                                         a.st_diag, a.st_hits, a.st_approx, a.st_accept,
                                                         L.res->genome.p, L.res->diag.p, L.res->hits.p,
                                                         L.res->approx.p, L.res->accept.p);
@@ -891,9 +926,11 @@ static void launch_fused_graph(const FusedLaunch &L, hipStream_t s) {
 void classify_fused(const mt_index &ix, const mt_query_params &q, const mt_seqs &reads, ReadBatch &rb,
                     mt_result &res, Timer &tm, hipStream_t s, bool graph) {
     const u64 n = reads.n;
-    const u32 N = q.top_n;
-    if (N == 0 || N > (u32)F_MAX_TOPN) {
-        // Unbounded or long candidate lists: the per-stage kernels handle them.
+    // staging slots per read: top_n, or F_MAX_TOPN for keep-all (top_n = 0;
+    // reads with more candidates are finished per stage)
+    const u32 N = q.top_n ? q.top_n : (u32)F_MAX_TOPN;
+    if (q.top_n > (u32)F_MAX_TOPN) {
+        // Long candidate lists: the per-stage kernels handle them.
         rb.prepare(reads, q.e_mode, q.e_value, s);
         MT_HIP(hipMemcpyAsync(res.read_E.p, rb.read_E.p, (n ? n : 1) * sizeof(u16), hipMemcpyDeviceToDevice, s));
         tm.mark("pack");
@@ -933,7 +970,8 @@ void classify_fused(const mt_index &ix, const mt_query_params &q, const mt_seqs 
     a.k = ix.k;
     a.w = ix.w;
     a.min_hits = q.min_hits;
-    a.top_n = N;
+    a.top_n = q.top_n;
+    a.ncap = N;
     a.e_mode = q.e_mode;
     a.e_value = q.e_value;
     a.table = ix.table.p;
@@ -1019,11 +1057,23 @@ void classify_fused(const mt_index &ix, const mt_query_params &q, const mt_seqs 
     }
     k_add_u64<<<1, 64, 0, s>>>((unsigned long long *)res.unmapped.p, tmp.unmapped.p, 1);
     scan_u32(ncand.p, res.cand_off.p, n, s);
-    k_compact_staged<<<grid_for(n, 256), 256, 0, s>>>(ctl.p + CTL_GATE, res.cand_off.p, n, N, st_genome.p,
+    u64 total = 0;
+    read_back(s, res.cand_off.p + n, &total, sizeof total);
+    if (total > res.cap) res.alloc_cands(total);  // keep-all reads with many candidates
+    k_compact_staged<<<grid_for(n, 256), 256, 0, s>>>(ctl.p + CTL_GATE, res.cand_off.p, n, N, res.cap, st_genome.p,
                                                       st_diag.p, st_hits.p, st_approx.p, st_accept.p, res.genome.p,
                                                       res.diag.p, res.hits.p, res.approx.p, res.accept.p);
     MT_HIP(hipGetLastError());
-    read_back(s, res.cand_off.p + n, &res.n_cands, sizeof(u64));
+    if (q.top_n == 0) {
+        // the finished reads' full lists, after the compaction (which copied
+        // at most N staged entries of theirs)
+        k_subset_place<<<grid_for(nfb, 256), 256, 0, s>>>(fb_list.p, nfb, tmp.cand_off.p, tmp.genome.p, tmp.diag.p,
+                                                          tmp.hits.p, tmp.approx.p, tmp.accept.p, res.cand_off.p,
+                                                          res.cap, res.genome.p, res.diag.p, res.hits.p,
+                                                          res.approx.p, res.accept.p);
+        MT_HIP(hipGetLastError());
+    }
+    res.n_cands = total;
     tm.mark("fallback");
 }
 

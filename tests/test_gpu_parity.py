@@ -138,6 +138,26 @@ def test_fused_fallback_for_hit_overflow(mt):
 
 
 @pytest.mark.parametrize("mode", MODES)
+def test_keep_all_candidates_short_reads(mt, mode):
+    """top_n = 0 with short reads: near-identical genome families give reads
+    with up to 8 candidates (fused staging) and with more (per-stage finish,
+    placed after the compaction), in one call."""
+    rnd = np.random.default_rng(41)
+    base6 = synth.random_codes(rnd, 20_000)
+    base12 = synth.random_codes(rnd, 20_000)
+    fam = [synth.substitute(rnd, base6, 0.002) for _ in range(6)] + \
+          [synth.substitute(rnd, base12, 0.002) for _ in range(12)]
+    genomes = synth.SeqSet.from_list([synth.ACGT[f].tobytes() for f in fam])
+    starts = rnd.integers(0, 19_800, 300)
+    src = rnd.integers(0, len(fam), 300)
+    reads = synth.SeqSet.from_list([synth.ACGT[fam[g][st:st + 150]].tobytes() for g, st in zip(src, starts)])
+    got, ref = run_both(mt, genomes, reads, 15, 10, min_hits=2, top_n=0, e_value=7, mode=mode)
+    assert_same(got, ref, "keep-all")
+    nc = np.diff(ref["cand_offsets"].astype(np.int64))
+    assert (nc > 8).any() and ((nc > 0) & (nc <= 8)).any()
+
+
+@pytest.mark.parametrize("mode", MODES)
 def test_long_reads_large_E_bit_exact(mt, mode):
     rnd = np.random.default_rng(5)
     gen = synth.make_genomes(rnd, 3, 60_000, 0.5)
