@@ -367,7 +367,10 @@ void classify_per_stage(const mt_index &ix, const mt_query_params &q, const mt_s
     u64 n = reads.n;
     // seeds
     MinimizerPlan mp;
-    minimizer_plan(reads, rb.planes, ix.k, ix.w, 256, mp, s);
+    // tiles of 256 k-mer starts fit short reads; long reads amortize the
+    // window halo and the block over tiles of 1024
+    const int tile = reads.n && reads.total / reads.n > 512 ? 1024 : 256;
+    minimizer_plan(reads, rb.planes, ix.k, ix.w, tile, mp, s);
     tm.mark("seed_count");
     u32 hf[2];
     u64 n_min = 0;
