@@ -260,6 +260,7 @@ def main() -> int:
                     help="1: also measure the served workload (batched workload only); 0: skip it")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="length of each served trace")
     ap.add_argument("--serve-streams", type=int, default=0, help="server worker streams (0: library default, 4)")
+    ap.add_argument("--serve-threads", type=int, default=8, help="client threads submitting served requests")
     ap.add_argument("--serve-max-batch", type=int, default=0,
                     help="reads per served device batch (0: library default, 262,144)")
     ap.add_argument("--serve-only", action="store_true",
@@ -338,7 +339,7 @@ def main() -> int:
 
     if args.serve_only:
         sv = serving_bench(mt, ix, pool, seconds=args.serve_seconds, n_streams=args.serve_streams,
-                           max_batch_reads=args.serve_max_batch, baseline_s=0)
+                           max_batch_reads=args.serve_max_batch, baseline_s=0, threads=args.serve_threads)
         print(json.dumps({"metric": "served reads/s; p50/p99 request latency", "serving": sv}), flush=True)
         return 0
 
@@ -419,7 +420,7 @@ def main() -> int:
     serving = None
     if pool is not None:
         serving = serving_bench(mt, ix, pool, seconds=args.serve_seconds, n_streams=args.serve_streams,
-                                max_batch_reads=args.serve_max_batch)
+                                max_batch_reads=args.serve_max_batch, threads=args.serve_threads)
 
     cpu = None
     if args.cpu_reads > 0:

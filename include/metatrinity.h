@@ -259,7 +259,8 @@ int mt_server_submit(mt_server *server, const mt_query_params *params, const cha
 int mt_server_wait(mt_server *server, uint64_t request_id, int64_t timeout_us, mt_result **out);
 
 /* Stops accepting requests, finishes the queued ones, joins the threads.
- * Results not yet waited for are released. */
+ * Results not yet waited for are released; results already handed over stay
+ * valid.  No other call on this server may be in progress or follow. */
 int mt_server_destroy(mt_server *server);
 
 /* 1 if the result's arrays live in host memory (served results), 0 if on

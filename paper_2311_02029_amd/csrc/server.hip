@@ -262,7 +262,9 @@ struct mt_server {
 
     void run_batch(Batch &b, hipStream_t s, Pinned &h_in, Pinned &h_out, std::vector<Piece> &pieces);
     void worker();
-    void finish(Request *r, hipStream_t s);
+    // Completes a request whose reads are all classified; counts = its taxon
+    // counts already on the host (2 * n_taxa + 1 values; unused on error).
+    void finish(Request *r, const u64 *counts);
 };
 
 void mt_server::run_batch(Batch &b, hipStream_t s, Pinned &h_in, Pinned &h_out, std::vector<Piece> &pieces) {
@@ -354,7 +356,7 @@ void mt_server::run_batch(Batch &b, hipStream_t s, Pinned &h_in, Pinned &h_out, 
 
 // Completes a request whose reads are all classified (lock not held; no
 // other thread touches the request until done is set).
-void mt_server::finish(Request *r, hipStream_t s) {
+void mt_server::finish(Request *r, const u64 *counts) {
     using namespace mt;
     std::unique_ptr<mt_result> res;
     if (r->status == MT_OK) {
@@ -365,9 +367,7 @@ void mt_server::finish(Request *r, hipStream_t s) {
             res->n_taxa = ix->n_taxa;
             res->submit_ns = r->submit_ns;
             auto &h = res->h;
-            h.counts.resize(2 * (u64)ix->n_taxa + 1);
-            MT_HIP(hipMemcpyAsync(h.counts.data(), r->counts, h.counts.size() * 8, hipMemcpyDeviceToHost, s));
-            MT_HIP(hipStreamSynchronize(s));
+            h.counts.assign(counts, counts + 2 * (u64)ix->n_taxa + 1);
             u64 nc = 0;
             for (auto &kv : r->pieces) nc += kv.second.genome.size();
             res->n_cands = nc;
@@ -409,7 +409,11 @@ void mt_server::finish(Request *r, hipStream_t s) {
         }
     }
     r->pieces.clear();
-    pool_free(r->counts);
+    if (r->counts) {
+        // the zero fill is long done unless a batch failed before waiting on it
+        if (r->zeroed) (void)hipEventSynchronize(r->zeroed);
+        pool_free(r->counts);
+    }
     r->counts = nullptr;
     std::lock_guard<std::mutex> lk(mu);
     if (r->zeroed) free_events.push_back(r->zeroed);
@@ -430,7 +434,7 @@ void mt_server::worker() {
         setup_error = "worker stream creation failed";
         s = nullptr;
     }
-    Pinned h_in, h_out;
+    Pinned h_in, h_out, h_cnt;
     for (;;) {
         Batch b;
         {
@@ -476,7 +480,28 @@ void mt_server::worker() {
             }
         }
         cv_work.notify_all();
-        for (Request *r : closed) finish(r, s);
+        // the closed requests' counters: one pinned download and one wait
+        const u64 nt = 2 * (u64)ix->n_taxa + 1;
+        bool got = false;
+        if (!closed.empty() && s) {
+            try {
+                h_cnt.ensure(closed.size() * nt * 8);
+                for (size_t i = 0; i < closed.size(); i++)
+                    if (closed[i]->status == MT_OK)
+                        MT_HIP(hipMemcpyAsync(h_cnt.p + i * nt * 8, closed[i]->counts, nt * 8, hipMemcpyDeviceToHost,
+                                              s));
+                MT_HIP(hipStreamSynchronize(s));
+                got = true;
+            } catch (const Error &e) {
+                for (Request *r : closed)
+                    if (r->status == MT_OK) {
+                        r->status = e.status;
+                        r->error = e.what();
+                    }
+            }
+        }
+        for (size_t i = 0; i < closed.size(); i++)
+            finish(closed[i], got ? (const u64 *)(h_cnt.p + i * nt * 8) : nullptr);
     }
 out:
     if (s) (void)hipStreamDestroy(s);
@@ -576,24 +601,25 @@ extern "C" int mt_server_submit(mt_server *sv, const mt_query_params *params, co
         r->off = (const u64 *)dst;
         r->seq = dst + off_bytes;
         const u64 nt = sv->ix->n_taxa;
-        try {
-            // zeroed asynchronously; workers wait for the event before adding
-            {
-                std::lock_guard<std::mutex> lk(sv->mu);
-                if (!sv->free_events.empty()) {
-                    r->zeroed = sv->free_events.back();
-                    sv->free_events.pop_back();
+        if (n) {  // zeroed asynchronously; workers wait for the event before adding
+            try {
+                {
+                    std::lock_guard<std::mutex> lk(sv->mu);
+                    if (!sv->free_events.empty()) {
+                        r->zeroed = sv->free_events.back();
+                        sv->free_events.pop_back();
+                    }
                 }
+                if (!r->zeroed) MT_HIP(hipEventCreateWithFlags(&r->zeroed, hipEventDisableTiming));
+                r->counts = (unsigned long long *)pool_alloc((2 * nt + 1) * 8);
+                MT_HIP(hipMemsetAsync(r->counts, 0, (2 * nt + 1) * 8, sv->ctl));
+                MT_HIP(hipEventRecord(r->zeroed, sv->ctl));
+            } catch (...) {
+                if (r->counts) pool_free(r->counts);
+                if (r->zeroed) (void)hipEventDestroy(r->zeroed);
+                give_back();
+                throw;
             }
-            if (!r->zeroed) MT_HIP(hipEventCreateWithFlags(&r->zeroed, hipEventDisableTiming));
-            r->counts = (unsigned long long *)pool_alloc((2 * nt + 1) * 8);
-            MT_HIP(hipMemsetAsync(r->counts, 0, (2 * nt + 1) * 8, sv->ctl));
-            MT_HIP(hipEventRecord(r->zeroed, sv->ctl));
-        } catch (...) {
-            if (r->counts) pool_free(r->counts);
-            if (r->zeroed) (void)hipEventDestroy(r->zeroed);
-            give_back();
-            throw;
         }
         Request *rp = r.get();
         {
@@ -604,7 +630,8 @@ extern "C" int mt_server_submit(mt_server *sv, const mt_query_params *params, co
             if (n) sv->queue.push_back(rp);
         }
         if (n == 0) {
-            sv->finish(rp, sv->ctl);  // nothing to classify
+            const std::vector<u64> zeros(2 * nt + 1, 0);
+            sv->finish(rp, zeros.data());  // nothing to classify
         } else {
             sv->cv_work.notify_one();
         }
