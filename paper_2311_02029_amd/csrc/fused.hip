@@ -730,27 +730,32 @@ __global__ void k_fused_init(u32 *__restrict__ ctl) {
     if (threadIdx.x < CTL_WORDS) ctl[threadIdx.x] = 0;
 }
 
-__global__ void k_fused_summary(const u32 *__restrict__ ctl, const u64 *__restrict__ cand_end,
-                                const u64 *__restrict__ stats_part, u32 blocks, FusedSummary *__restrict__ out) {
-    __shared__ u64 part[ST_COUNT][64];
-    const int t = threadIdx.x;  // 64 * ST_COUNT threads
-    const int st = t / 64, l = t % 64;
+// Block s < ST_COUNT sums work count s over the kernel's blocks; block 0
+// also copies the control words and the candidate total.
+constexpr int SUM_TPB = 1024;
+__global__ __launch_bounds__(SUM_TPB) void k_fused_summary(const u32 *__restrict__ ctl,
+                                                           const u64 *__restrict__ cand_end,
+                                                           const u64 *__restrict__ stats_part, u32 blocks,
+                                                           FusedSummary *__restrict__ out) {
+    __shared__ u64 part[SUM_TPB / 64];
+    const int st = blockIdx.x, t = threadIdx.x;
     u64 acc = 0;
     if (!ctl[CTL_GATE])
-        for (u32 b = l; b < blocks; b += 64) acc += stats_part[(u64)b * ST_COUNT + st];
-    part[st][l] = acc;
+        for (u32 b = t; b < blocks; b += SUM_TPB) acc += stats_part[(u64)b * ST_COUNT + st];
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+    if ((t & 63) == 0) part[t >> 6] = acc;
     __syncthreads();
-    if (l == 0) {
-        u64 v = 0;
-        for (int i = 0; i < 64; i++) v += part[st][i];
-        out->stats[st] = v;
-    }
     if (t == 0) {
-        out->gate = ctl[CTL_GATE];
-        out->flags = ctl[CTL_FLAGS];
-        out->nfb = ctl[CTL_FB];
-        out->pad = 0;
-        out->n_cands = ctl[CTL_GATE] ? 0 : *cand_end;
+        u64 v = 0;
+        for (int i = 0; i < SUM_TPB / 64; i++) v += part[i];
+        out->stats[st] = v;
+        if (st == 0) {
+            out->gate = ctl[CTL_GATE];
+            out->flags = ctl[CTL_FLAGS];
+            out->nfb = ctl[CTL_FB];
+            out->pad = 0;
+            out->n_cands = ctl[CTL_GATE] ? 0 : *cand_end;
+        }
     }
 }
 
@@ -877,7 +882,7 @@ static void enqueue_fused(const FusedLaunch &L, Timer *tm, hipStream_t s) {
                                                         a.st_diag, a.st_hits, a.st_approx, a.st_accept,
                                                         L.res->genome.p, L.res->diag.p, L.res->hits.p,
                                                         L.res->approx.p, L.res->accept.p);
-    k_fused_summary<<<1, 64 * ST_COUNT, 0, s>>>(L.ctl, L.res->cand_off.p + L.n, a.stats_part, L.blocks, L.sum);
+    k_fused_summary<<<ST_COUNT, SUM_TPB, 0, s>>>(L.ctl, L.res->cand_off.p + L.n, a.stats_part, L.blocks, L.sum);
     MT_HIP(hipGetLastError());
     if (tm) tm->mark("compact");
 }
@@ -951,7 +956,7 @@ void classify_fused(const mt_index &ix, const mt_query_params &q, const mt_seqs 
     MT_HIP(hipGetDevice(&dev));
     MT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     u64 blocks = (n + F_WPB - 1) / F_WPB;
-    const u64 cap = (u64)cus * 16;
+    const u64 cap = (u64)cus * 64;  // many short blocks: resident blocks finish together
     if (blocks > cap) blocks = cap;
 
     DBuf<u32> st_genome(n * N), st_hits(n * N), ncand(n), fb_list(n), ctl(CTL_WORDS);
