@@ -97,73 +97,174 @@ __device__ inline bool cand_before(u32 ha, u64 ka, u32 hb, u64 kb) { return ha >
 
 constexpr int COUNT_TPB = 256;
 constexpr int COUNT_CAP = 2048;
+constexpr int WAVE_CAP = 256;  // most hits one wavefront counts in registers
+constexpr int CW_WPB = 4;      // reads (wavefronts) per block of k_count_wave
 
-// One block per read whose hits fit in LDS; larger reads are queued for
-// k_count_large.
-__global__ __launch_bounds__(COUNT_TPB) void k_count_small(const u64 *__restrict__ hit_key,
-                                                           const u64 *__restrict__ read_hs, u64 n, u32 min_hits,
-                                                           u32 top_n, u64 *__restrict__ stage_key,
-                                                           u32 *__restrict__ stage_hits, u32 *__restrict__ ncand,
-                                                           u32 *__restrict__ large_list, u32 *__restrict__ n_large) {
+__device__ inline u64 wave_readlane64(u64 v, int l) {
+    const u32 lo = __builtin_amdgcn_readlane((u32)v, l), hi = __builtin_amdgcn_readlane((u32)(v >> 32), l);
+    return ((u64)hi << 32) | lo;
+}
+
+// Hit counting of one read by one wavefront, the read's H <= 64 * S hits held
+// S to a lane (hit i in lane i % 64, slot i / 64).  Each distinct key is
+// counted with one ballot per slot and its count kept by the lane of its first
+// hit; the candidates (count >= T) are then ranked in registers in the
+// canonical order and the first top_n (all if 0) are written to the read's
+// staging area.  Returns the number of candidates before the top-N cut.
+template <int S>
+__device__ inline u32 count_in_wave(const u64 *__restrict__ hit_key, u64 hs, u32 H, u32 lane, u32 T, u32 top_n,
+                                    u64 *__restrict__ stage_key, u32 *__restrict__ stage_hits) {
+    u64 key[S], pend[S];
+    u32 cnt[S];
+#pragma unroll
+    for (int s = 0; s < S; s++) {
+        const u32 i = lane + 64 * s;
+        key[s] = i < H ? hit_key[hs + i] : 0;
+        pend[s] = __ballot(i < H);
+        cnt[s] = 0;
+    }
+#pragma unroll
+    for (int s0 = 0; s0 < S; s0++) {
+        while (pend[s0]) {
+            const int ld = __builtin_ctzll(pend[s0]);
+            const u64 k = wave_readlane64(key[s0], ld);
+            u32 c = 0;
+#pragma unroll
+            for (int s = s0; s < S; s++) {
+                const u64 eq = __ballot(((pend[s] >> lane) & 1) && key[s] == k);
+                c += (u32)__popcll(eq);
+                pend[s] &= ~eq;
+            }
+            if (lane == (u32)ld) cnt[s0] = c;
+        }
+    }
+    u32 C = 0, rank[S];
+    u64 cm[S];
+#pragma unroll
+    for (int s = 0; s < S; s++) {
+        cm[s] = __ballot(cnt[s] >= T);
+        C += (u32)__popcll(cm[s]);
+        rank[s] = 0;
+    }
+#pragma unroll
+    for (int sb = 0; sb < S; sb++) {
+        u64 it = cm[sb];
+        while (it) {
+            const int b = __builtin_ctzll(it);
+            it &= it - 1;
+            const u64 kb = wave_readlane64(key[sb], b);
+            const u32 hb = __builtin_amdgcn_readlane(cnt[sb], b);
+#pragma unroll
+            for (int s = 0; s < S; s++) rank[s] += cand_before(hb, kb, cnt[s], key[s]);
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < S; s++)
+        if (cnt[s] >= T && (top_n == 0 || rank[s] < top_n)) {
+            stage_key[hs + rank[s]] = key[s];
+            stage_hits[hs + rank[s]] = cnt[s];
+        }
+    return C;
+}
+
+// One wavefront per read with at most WAVE_CAP hits; larger reads are queued
+// for k_count_block.
+__global__ __launch_bounds__(64 * CW_WPB) void k_count_wave(const u64 *__restrict__ hit_key,
+                                                            const u64 *__restrict__ read_hs, u64 n, u32 min_hits,
+                                                            u32 top_n, u64 *__restrict__ stage_key,
+                                                            u32 *__restrict__ stage_hits, u32 *__restrict__ ncand,
+                                                            u32 *__restrict__ mid_list, u32 *__restrict__ n_mid) {
+    const u32 lane = threadIdx.x & 63;
+    const u64 r = (u64)blockIdx.x * CW_WPB + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    if (r >= n) return;
+    const u64 hs = read_hs[r], H = read_hs[r + 1] - hs;
+    const u32 T = min_hits ? min_hits : 1;
+    u32 C;
+    if (H <= 64) {
+        C = count_in_wave<1>(hit_key, hs, (u32)H, lane, T, top_n, stage_key, stage_hits);
+    } else if (H <= WAVE_CAP) {
+        C = count_in_wave<4>(hit_key, hs, (u32)H, lane, T, top_n, stage_key, stage_hits);
+    } else {
+        if (lane == 0) mid_list[atomicAdd(n_mid, 1u)] = (u32)r;
+        return;
+    }
+    if (lane == 0) ncand[r] = top_n && C > top_n ? top_n : C;
+}
+
+// Blocks of k_count_block: a few per CU, each looping over the queue (its
+// length is known only on the device).
+static unsigned count_blocks() {
+    int dev = 0, cus = 0;
+    MT_HIP(hipGetDevice(&dev));
+    MT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    return (unsigned)std::max(cus, 1) * 4;
+}
+
+// One block per queued read whose hits fit in LDS (sorted there); reads with
+// more are queued again for k_count_large.
+__global__ __launch_bounds__(COUNT_TPB) void k_count_block(const u64 *__restrict__ hit_key,
+                                                           const u64 *__restrict__ read_hs, u32 min_hits, u32 top_n,
+                                                           u64 *__restrict__ stage_key, u32 *__restrict__ stage_hits,
+                                                           u32 *__restrict__ ncand, const u32 *__restrict__ mid_list,
+                                                           const u32 *__restrict__ n_mid, u32 *__restrict__ large_list,
+                                                           u32 *__restrict__ n_large) {
     __shared__ u64 key[COUNT_CAP];
     __shared__ u64 ck[COUNT_CAP];
     __shared__ u32 ch[COUNT_CAP];
     __shared__ u32 nc;
-    u64 r = blockIdx.x;
-    if (r >= n) return;
-    u64 hs = read_hs[r], he = read_hs[r + 1];
-    u64 H = he - hs;
-    if (H == 0) {
-        if (threadIdx.x == 0) ncand[r] = 0;
-        return;
-    }
-    if (H > COUNT_CAP) {
-        if (threadIdx.x == 0) large_list[atomicAdd(n_large, 1u)] = (u32)r;
-        return;
-    }
-    for (u64 i = threadIdx.x; i < H; i += COUNT_TPB) key[i] = hit_key[hs + i];
-    if (threadIdx.x == 0) nc = 0;
-    u64 P = 1;
-    while (P < H) P <<= 1;
-    __syncthreads();
-    for (u64 k = 2; k <= P; k <<= 1) {
-        for (u64 j = k >> 1; j > 0; j >>= 1) {
-            bool mirror = j == (k >> 1);
-            for (u64 t = threadIdx.x; t < P / 2; t += COUNT_TPB) {
-                u64 i, l;
-                bitonic_pair(t, k, j, mirror, i, l);
-                if (l < H && key[i] > key[l]) {
-                    u64 tmp = key[i];
-                    key[i] = key[l];
-                    key[l] = tmp;
+    const u32 nm = *n_mid;
+    for (u32 li = blockIdx.x; li < nm; li += gridDim.x) {
+        __syncthreads();  // the previous read is done with the LDS arrays
+        const u64 r = mid_list[li];
+        const u64 hs = read_hs[r], H = read_hs[r + 1] - hs;
+        if (H > COUNT_CAP) {
+            if (threadIdx.x == 0) large_list[atomicAdd(n_large, 1u)] = (u32)r;
+            continue;
+        }
+        for (u64 i = threadIdx.x; i < H; i += COUNT_TPB) key[i] = hit_key[hs + i];
+        if (threadIdx.x == 0) nc = 0;
+        u64 P = 1;
+        while (P < H) P <<= 1;
+        __syncthreads();
+        for (u64 k = 2; k <= P; k <<= 1) {
+            for (u64 j = k >> 1; j > 0; j >>= 1) {
+                bool mirror = j == (k >> 1);
+                for (u64 t = threadIdx.x; t < P / 2; t += COUNT_TPB) {
+                    u64 i, l;
+                    bitonic_pair(t, k, j, mirror, i, l);
+                    if (l < H && key[i] > key[l]) {
+                        u64 tmp = key[i];
+                        key[i] = key[l];
+                        key[l] = tmp;
+                    }
                 }
+                __syncthreads();
             }
-            __syncthreads();
         }
-    }
-    u32 T = min_hits ? min_hits : 1;
-    for (u64 i = threadIdx.x; i < H; i += COUNT_TPB) {
-        if (i > 0 && key[i] == key[i - 1]) continue;
-        u64 j = i + 1;
-        while (j < H && key[j] == key[i]) j++;
-        u32 c = (u32)(j - i);
-        if (c >= T) {
-            u32 s = atomicAdd(&nc, 1u);
-            ck[s] = key[i];
-            ch[s] = c;
+        u32 T = min_hits ? min_hits : 1;
+        for (u64 i = threadIdx.x; i < H; i += COUNT_TPB) {
+            if (i > 0 && key[i] == key[i - 1]) continue;
+            u64 j = i + 1;
+            while (j < H && key[j] == key[i]) j++;
+            u32 c = (u32)(j - i);
+            if (c >= T) {
+                u32 s = atomicAdd(&nc, 1u);
+                ck[s] = key[i];
+                ch[s] = c;
+            }
         }
-    }
-    __syncthreads();
-    u32 C = nc;
-    for (u32 a = threadIdx.x; a < C; a += COUNT_TPB) {
-        u32 rank = 0;
-        for (u32 b = 0; b < C; b++) rank += cand_before(ch[b], ck[b], ch[a], ck[a]);
-        if (top_n == 0 || rank < top_n) {
-            stage_key[hs + rank] = ck[a];
-            stage_hits[hs + rank] = ch[a];
+        __syncthreads();
+        u32 C = nc;
+        for (u32 a = threadIdx.x; a < C; a += COUNT_TPB) {
+            u32 rank = 0;
+            for (u32 b = 0; b < C; b++) rank += cand_before(ch[b], ck[b], ch[a], ck[a]);
+            if (top_n == 0 || rank < top_n) {
+                stage_key[hs + rank] = ck[a];
+                stage_hits[hs + rank] = ch[a];
+            }
         }
+        if (threadIdx.x == 0) ncand[r] = top_n && C > top_n ? top_n : C;
     }
-    if (threadIdx.x == 0) ncand[r] = top_n && C > top_n ? top_n : C;
 }
 
 // Reads with more hits than fit in LDS: sort in global memory, one block per
@@ -258,19 +359,37 @@ __global__ void k_compact(const u64 *__restrict__ read_hs, const u32 *__restrict
 
 // ----------------------------------------------------------------- reduce --
 
+// Where a read's taxon counts go: global 64-bit counters, or a block's LDS
+// counters {unique[n_taxa], multi[n_taxa], unmapped} added to the global ones
+// when the block ends.
+struct GlobalCounts {
+    unsigned long long *uniq, *multi, *unmapped;
+    __device__ void unique_read(u32 t) const { atomicAdd(&uniq[t], 1ull); }
+    __device__ void multi_read(u32 t) const { atomicAdd(&multi[t], 1ull); }
+    __device__ void unmapped_read() const { atomicAdd(unmapped, 1ull); }
+};
+
+struct LdsCounts {
+    u32 *c;
+    u32 n_taxa;
+    __device__ void unique_read(u32 t) const { atomicAdd(&c[t], 1u); }
+    __device__ void multi_read(u32 t) const { atomicAdd(&c[n_taxa + t], 1u); }
+    __device__ void unmapped_read() const { atomicAdd(&c[2 * n_taxa], 1u); }
+};
+
 // One read of the taxon step (Fig. 1 step 3a): its mapped taxa are the taxa of
 // its accepted candidates at the smallest count; one taxon counts as unique,
 // several as multi-mapped for each, none as unmapped.  Returns whether the
 // read has an accepted candidate.
+template <class Counts>
 __device__ inline bool reduce_read(u64 cs, u64 ce, u32 E, const u32 *__restrict__ genome,
                                    const u16 *__restrict__ approx, const u32 *__restrict__ taxon,
-                                   unsigned long long *uniq, unsigned long long *multi,
-                                   unsigned long long *unmapped) {
+                                   const Counts &out) {
     u32 best = 0xFFFFFFFFu;
     for (u64 c = cs; c < ce; c++)
         if (approx[c] <= E && approx[c] < best) best = approx[c];
     if (best == 0xFFFFFFFFu) {
-        atomicAdd(unmapped, 1ull);
+        out.unmapped_read();
         return false;
     }
     // Distinct taxa of the accepted candidates at the best count.
@@ -286,7 +405,7 @@ __device__ inline bool reduce_read(u64 cs, u64 ce, u32 E, const u32 *__restrict_
         ntax++;
     }
     if (ntax == 1) {
-        atomicAdd(&uniq[first], 1ull);
+        out.unique_read(first);
         return true;
     }
     for (u64 c = cs; c < ce; c++) {
@@ -295,20 +414,45 @@ __device__ inline bool reduce_read(u64 cs, u64 ce, u32 E, const u32 *__restrict_
         bool seen = false;
         for (u64 d = cs; d < c; d++)
             if (approx[d] == best && taxon[genome[d]] == t) seen = true;
-        if (!seen) atomicAdd(&multi[t], 1ull);
+        if (!seen) out.multi_read(t);
     }
     return true;
 }
 
-__global__ void k_reduce(const u64 *__restrict__ cand_off, u64 n, const u32 *__restrict__ genome,
-                         const u16 *__restrict__ approx, const u16 *__restrict__ read_E,
-                         const u32 *__restrict__ taxon, u8 *__restrict__ read_accepted,
-                         unsigned long long *__restrict__ uniq, unsigned long long *__restrict__ multi,
-                         unsigned long long *__restrict__ unmapped) {
-    u64 r = (u64)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= n) return;
-    read_accepted[r] = reduce_read(cand_off[r], cand_off[r + 1], read_E[r], genome, approx, taxon, uniq, multi,
-                                   unmapped);
+constexpr int RED_TPB = 256;
+constexpr u32 RED_LDS_TAXA = 2048;  // taxa counted per block in LDS
+
+// Grid-stride over the reads.  Up to RED_LDS_TAXA taxa each block counts in
+// LDS and adds its nonzero counters to the global ones at the end (one atomic
+// per counter and block instead of one per read); more taxa count globally.
+__global__ __launch_bounds__(RED_TPB) void k_reduce(const u64 *__restrict__ cand_off, u64 n,
+                                                    const u32 *__restrict__ genome, const u16 *__restrict__ approx,
+                                                    const u16 *__restrict__ read_E, const u32 *__restrict__ taxon,
+                                                    u32 n_taxa, u8 *__restrict__ read_accepted,
+                                                    unsigned long long *__restrict__ uniq,
+                                                    unsigned long long *__restrict__ multi,
+                                                    unsigned long long *__restrict__ unmapped) {
+    __shared__ u32 cnt[2 * RED_LDS_TAXA + 1];
+    const u64 stride = (u64)gridDim.x * RED_TPB;
+    if (n_taxa > RED_LDS_TAXA) {
+        const GlobalCounts out{uniq, multi, unmapped};
+        for (u64 r = (u64)blockIdx.x * RED_TPB + threadIdx.x; r < n; r += stride)
+            read_accepted[r] = reduce_read(cand_off[r], cand_off[r + 1], read_E[r], genome, approx, taxon, out);
+        return;
+    }
+    const u32 nc = 2 * n_taxa + 1;
+    for (u32 i = threadIdx.x; i < nc; i += RED_TPB) cnt[i] = 0;
+    __syncthreads();
+    const LdsCounts out{cnt, n_taxa};
+    for (u64 r = (u64)blockIdx.x * RED_TPB + threadIdx.x; r < n; r += stride)
+        read_accepted[r] = reduce_read(cand_off[r], cand_off[r + 1], read_E[r], genome, approx, taxon, out);
+    __syncthreads();
+    for (u32 i = threadIdx.x; i < nc; i += RED_TPB) {
+        const u32 v = cnt[i];
+        if (!v) continue;
+        unsigned long long *dst = i < n_taxa ? &uniq[i] : i < 2 * n_taxa ? &multi[i - n_taxa] : unmapped;
+        atomicAdd(dst, (unsigned long long)v);
+    }
 }
 
 // The taxon step per request slot of a served batch: reads [slot_off[s],
@@ -326,7 +470,8 @@ __global__ void k_reduce_slots(const u64 *__restrict__ cand_off, u64 n, const u3
         if (slot_off[mid] <= r) lo = mid; else hi = mid;
     }
     unsigned long long *c = counts[lo];
-    reduce_read(cand_off[r], cand_off[r + 1], read_E[r], genome, approx, taxon, c, c + n_taxa, c + 2 * (u64)n_taxa);
+    const GlobalCounts out{c, c + n_taxa, c + 2 * (u64)n_taxa};
+    reduce_read(cand_off[r], cand_off[r + 1], read_E[r], genome, approx, taxon, out);
 }
 
 void launch_reduce_slots(const mt_result &res, const mt_index &ix, const u64 *slot_off, u32 n_slots,
@@ -404,17 +549,22 @@ void classify_per_stage(const mt_index &ix, const mt_query_params &q, const mt_s
     tm.mark("gather");
     // count + select
     DBuf<u64> stage_key(H);
-    DBuf<u32> stage_hits(H), ncand(n), large_list(n), n_large(1);
-    MT_HIP(hipMemsetAsync(n_large.p, 0, sizeof(u32), s));
+    DBuf<u32> stage_hits(H), ncand(n), mid_list(n), large_list(n), lists(2);
+    u32 *n_mid = lists.p, *n_large = lists.p + 1;
+    MT_HIP(hipMemsetAsync(lists.p, 0, 2 * sizeof(u32), s));
     last_stats().n_minimizers += n_min;
     last_stats().n_hits += H;
     if (n) {
-        k_count_small<<<grid_for(n, 1), COUNT_TPB, 0, s>>>(hit_key.p, read_hs.p, n, q.min_hits, q.top_n,
-                                                           stage_key.p, stage_hits.p, ncand.p, large_list.p,
-                                                           n_large.p);
+        k_count_wave<<<grid_for(n, CW_WPB), 64 * CW_WPB, 0, s>>>(hit_key.p, read_hs.p, n, q.min_hits, q.top_n,
+                                                                  stage_key.p, stage_hits.p, ncand.p, mid_list.p,
+                                                                  n_mid);
+        MT_HIP(hipGetLastError());
+        k_count_block<<<count_blocks(), COUNT_TPB, 0, s>>>(hit_key.p, read_hs.p, q.min_hits, q.top_n, stage_key.p,
+                                                           stage_hits.p, ncand.p, mid_list.p, n_mid, large_list.p,
+                                                           n_large);
         MT_HIP(hipGetLastError());
         k_count_large<<<256, COUNT_TPB, 0, s>>>(hit_key.p, read_hs.p, q.min_hits, q.top_n, stage_key.p,
-                                                stage_hits.p, ncand.p, large_list.p, n_large.p);
+                                                stage_hits.p, ncand.p, large_list.p, n_large);
         MT_HIP(hipGetLastError());
     }
     tm.mark("count_select");
@@ -454,11 +604,11 @@ void classify_per_stage(const mt_index &ix, const mt_query_params &q, const mt_s
     tm.mark("filter");
     // reduce
     if (n) {
-        k_reduce<<<grid_for(n, 256), 256, 0, s>>>(res.cand_off.p, n, res.genome.p, res.approx.p, rb.read_E.p,
-                                                  ix.taxon.p, res.read_accepted.p,
-                                                  (unsigned long long *)res.uniq.p,
-                                                  (unsigned long long *)res.multi.p,
-                                                  (unsigned long long *)res.unmapped.p);
+        const unsigned blocks = std::min<u64>(grid_for(n, RED_TPB), (u64)count_blocks() / 2);
+        k_reduce<<<blocks, RED_TPB, 0, s>>>(res.cand_off.p, n, res.genome.p, res.approx.p, rb.read_E.p, ix.taxon.p,
+                                            ix.n_taxa, res.read_accepted.p, (unsigned long long *)res.uniq.p,
+                                            (unsigned long long *)res.multi.p,
+                                            (unsigned long long *)res.unmapped.p);
         MT_HIP(hipGetLastError());
     }
     tm.mark("reduce");

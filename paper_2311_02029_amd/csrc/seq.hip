@@ -114,102 +114,171 @@ __global__ void k_seq_tiles(const u64 *__restrict__ off, u64 n, u32 k, u64 tile,
     ntile[s] = nk > 0 ? ((u64)nk + tile - 1) / tile : 0;
 }
 
+// Leftmost smallest of the W hashes sh[i..i + W) (an invalid k-mer reads as
+// ~0, which no valid k-mer hashes to: the hash is a bijection and the preimage
+// of ~0 is above every 62-bit k-mer value); -1 when the window has no valid
+// k-mer.  All W hashes are read before the compare chain.
+template <int W>
+__device__ inline int lds_window_argmin(const u64 *sh, int i) {
+    u64 v[W];
+#pragma unroll
+    for (int t = 0; t < W; t++) v[t] = sh[i + t];
+    u64 bh = ~0ull;
+    int bt = -1;
+#pragma unroll
+    for (int t = 0; t < W; t++)
+        if (v[t] < bh) {
+            bh = v[t];
+            bt = t;
+        }
+    return bt < 0 ? -1 : i + bt;
+}
+
+__device__ inline int lds_window_argmin_any(const u64 *sh, int i, int win) {
+    switch (win) {
+#define MT_WIN(W) \
+    case W:       \
+        return lds_window_argmin<W>(sh, i);
+        MT_WIN(1) MT_WIN(2) MT_WIN(3) MT_WIN(4) MT_WIN(5) MT_WIN(6) MT_WIN(7) MT_WIN(8)
+        MT_WIN(9) MT_WIN(10) MT_WIN(11) MT_WIN(12)
+#undef MT_WIN
+    default: {
+        u64 bh = ~0ull;
+        int best = -1;
+        for (int t = 0; t < win; t++)
+            if (sh[i + t] < bh) {
+                bh = sh[i + t];
+                best = i + t;
+            }
+        return best;
+    }
+    }
+}
+
 // One block per tile of TILE consecutive k-mer starts of one sequence.  The
 // hashes of the tile plus a halo of w - 1 starts on each side go to LDS; every
 // window that overlaps the tile picks its smallest (hash, position) among the
-// valid k-mers, and picks inside the tile are marked.  Pass 1 (out_x null)
-// stores the tile's count; pass 2 writes (x, sequence, position) in order.
+// valid k-mers, and picks inside the tile are marked.  The marks leave as one
+// 64-bit word per 64 starts (tile_bits, TILE / 64 words per tile) with their
+// count in tile_count.
 template <int TPB, int TILE>
 __global__ __launch_bounds__(TPB) void k_min_tiles(const u64x2 *__restrict__ lohi, const u64 *__restrict__ nbp,
                                                    const u64 *__restrict__ blk_off, const u64 *__restrict__ off,
                                                    const u64 *__restrict__ tile_off, const u32 *__restrict__ tile_map,
                                                    u64 n, u32 k, u32 w, u32 *__restrict__ tile_count,
-                                                   const u64 *__restrict__ min_off, u64 *__restrict__ out_x,
-                                                   u32 *__restrict__ out_seq, u32 *__restrict__ out_pos) {
+                                                   u64 *__restrict__ tile_bits) {
+    static_assert(TILE % TPB == 0 && TPB % 64 == 0, "tile of whole wavefront passes");
     constexpr int SPAN = TILE + 2 * MAX_HALO;
     __shared__ u64 sh_h[SPAN];
-    __shared__ u64 sh_x[SPAN];
-    __shared__ u8 sh_ok[SPAN];
     __shared__ u8 chosen[TILE];
-    u64 t = blockIdx.x;
+    __shared__ u32 total;
+    const u64 t = blockIdx.x;
     if (t >= tile_off[n]) return;
-    u32 s = tile_map[t];
-    i64 lt = (i64)(t - tile_off[s]);
-    i64 len = (i64)(off[s + 1] - off[s]);
-    i64 nk = len - (i64)k + 1;
-    i64 win = nk < (i64)w ? nk : (i64)w;
-    i64 t0 = lt * TILE, t1 = t0 + TILE < nk ? t0 + TILE : nk;
-    i64 h0 = t0 - win + 1 > 0 ? t0 - win + 1 : 0;
-    i64 h1 = t1 + win - 1 < nk ? t1 + win - 1 : nk;
+    const u32 s = tile_map[t];
+    const i64 lt = (i64)(t - tile_off[s]);
+    const i64 len = (i64)(off[s + 1] - off[s]);
+    const i64 nk = len - (i64)k + 1;
+    const i64 win = nk < (i64)w ? nk : (i64)w;
+    const i64 t0 = lt * TILE, t1 = t0 + TILE < nk ? t0 + TILE : nk;
+    const i64 h0 = t0 - win + 1 > 0 ? t0 - win + 1 : 0;
+    const i64 h1 = t1 + win - 1 < nk ? t1 + win - 1 : nk;
     const u64x2 *ql = lohi + blk_off[s];
     const u64 *qn = nbp + blk_off[s];
-    u64 kmask = (1ull << k) - 1;
+    const u64 kmask = (1ull << k) - 1;
     for (i64 i = h0 + threadIdx.x; i < h1; i += TPB) {
-        Bits64 b = fetch_planes(ql, qn, i);
-        u64 x = kmer_value(b.lo, b.hi, k);
-        int idx = (int)(i - h0);
-        sh_x[idx] = x;
-        sh_h[idx] = mix64(x);
-        sh_ok[idx] = (b.nb & kmask) == 0;
+        const Bits64 b = fetch_planes(ql, qn, i);
+        sh_h[i - h0] = (b.nb & kmask) == 0 ? mix64(kmer_value(b.lo, b.hi, k)) : ~0ull;
     }
     for (int i = threadIdx.x; i < TILE; i += TPB) chosen[i] = 0;
+    if (threadIdx.x == 0) total = 0;
     __syncthreads();
-    i64 ws1 = t1 - 1 < nk - win ? t1 - 1 : nk - win;
+    const i64 ws1 = t1 - 1 < nk - win ? t1 - 1 : nk - win;
     for (i64 ws = h0 + threadIdx.x; ws <= ws1; ws += TPB) {
-        i64 best = -1;
-        u64 bh = 0;
-        for (i64 i = ws; i < ws + win; i++) {
-            int idx = (int)(i - h0);
-            if (!sh_ok[idx]) continue;
-            u64 hv = sh_h[idx];
-            if (best < 0 || hv < bh) {  // strict: the leftmost of equal hashes wins
-                best = i;
-                bh = hv;
-            }
+        const int best = lds_window_argmin_any(sh_h, (int)(ws - h0), (int)win);
+        if (best >= 0) {
+            const i64 p = h0 + best;
+            if (p >= t0 && p < t1) chosen[p - t0] = 1;
         }
-        if (best >= t0 && best < t1) chosen[best - t0] = 1;
     }
     __syncthreads();
-    constexpr int PER = TILE / TPB;
-    u32 cnt = 0;
+    const u32 lane = threadIdx.x & 63;
 #pragma unroll
-    for (int u = 0; u < PER; u++) cnt += chosen[threadIdx.x * PER + u];
-    u32 total;
-    u32 pre = block_exclusive_sum<TPB, u32>(cnt, &total);
-    if (!out_x) {
-        if (threadIdx.x == 0) tile_count[t] = total;
-        return;
+    for (int u = 0; u < TILE / TPB; u++) {
+        const int i = u * TPB + (int)threadIdx.x;  // 64 consecutive starts per wavefront
+        const u64 m = __ballot(chosen[i] != 0);
+        if (lane == 0) {
+            tile_bits[t * (TILE / 64) + i / 64] = m;
+            if (m) atomicAdd(&total, (u32)__popcll(m));
+        }
     }
-    u64 o = min_off[t] + pre;
-#pragma unroll
-    for (int u = 0; u < PER; u++) {
-        int li = threadIdx.x * PER + u;
-        if (!chosen[li]) continue;
-        i64 i = t0 + li;
-        out_x[o] = sh_x[i - h0];
-        out_seq[o] = s;
-        out_pos[o] = (u32)i;
-        o++;
+    __syncthreads();
+    if (threadIdx.x == 0) tile_count[t] = total;
+}
+
+// One wavefront per tile: the marked starts are first listed in LDS, then
+// their k-mer values computed 64 at a time (one lane per start) and written in
+// start order at the tile's output offset with sequence and position.
+constexpr int EMIT_WPB = 4;
+
+template <int TILE>
+__global__ __launch_bounds__(64 * EMIT_WPB) void k_min_emit(const u64x2 *__restrict__ lohi,
+                                                            const u64 *__restrict__ nbp,
+                                                            const u64 *__restrict__ blk_off,
+                                                            const u64 *__restrict__ tile_off,
+                                                            const u32 *__restrict__ tile_map, u64 n, u32 k,
+                                                            const u64 *__restrict__ tile_bits,
+                                                            const u64 *__restrict__ min_off, u64 *__restrict__ out_x,
+                                                            u32 *__restrict__ out_seq, u32 *__restrict__ out_pos) {
+    static_assert(TILE <= 65536, "starts within a tile fit 16 bits");
+    __shared__ u16 list_all[EMIT_WPB][TILE];
+    const u32 lane = threadIdx.x & 63;
+    const u32 wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const u64 t = (u64)blockIdx.x * EMIT_WPB + wid;
+    if (t >= tile_off[n]) return;
+    u16 *list = list_all[wid];
+    const u32 s = tile_map[t];
+    const i64 t0 = (i64)(t - tile_off[s]) * TILE;
+    const u64 below = lane ? (~0ull) >> (64 - lane) : 0ull;
+    u32 nl = 0;
+#pragma unroll 1
+    for (int q = 0; q < TILE / 64; q++) {
+        const u64 m = tile_bits[t * (TILE / 64) + q];
+        if ((m >> lane) & 1) list[nl + (u32)__popcll(m & below)] = (u16)(64 * q + lane);
+        nl += (u32)__popcll(m);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const u64x2 *ql = lohi + blk_off[s];
+    const u64 *qn = nbp + blk_off[s];
+    const u64 o = min_off[t];
+#pragma unroll 1
+    for (u32 b = 0; b < nl; b += 64) {
+        if (b + lane < nl) {
+            const i64 i = t0 + list[b + lane];
+            const Bits64 bits = fetch_planes(ql, qn, i);
+            out_x[o + b + lane] = kmer_value(bits.lo, bits.hi, k);
+            out_seq[o + b + lane] = s;
+            out_pos[o + b + lane] = (u32)i;
+        }
     }
 }
 
 template <int TPB, int TILE>
-static void launch_tiles(const mt_seqs &in, const PackedSeqs &ps, u32 k, u32 w, MinimizerPlan &mp, u64 *out_x,
-                         u32 *out_seq, u32 *out_pos, hipStream_t s) {
-    k_min_tiles<TPB, TILE><<<grid_for(mp.tiles_cap, 1), TPB, 0, s>>>(
-        ps.lohi.p, ps.nb.p, ps.blk_off.p, in.offsets, mp.tile_off.p, mp.tile_map.p, in.n, k, w, mp.tile_count.p,
-        mp.min_off.p, out_x, out_seq, out_pos);
+static void launch_tiles(const mt_seqs &in, const PackedSeqs &ps, u32 k, u32 w, MinimizerPlan &mp, hipStream_t s) {
+    k_min_tiles<TPB, TILE><<<grid_for(mp.tiles_cap, 1), TPB, 0, s>>>(ps.lohi.p, ps.nb.p, ps.blk_off.p, in.offsets,
+                                                                      mp.tile_off.p, mp.tile_map.p, in.n, k, w,
+                                                                      mp.tile_count.p, mp.tile_bits.p);
     MT_HIP(hipGetLastError());
 }
 
-static void run_tiles(const mt_seqs &in, const PackedSeqs &ps, u32 k, u32 w, MinimizerPlan &mp, u64 *out_x,
-                      u32 *out_seq, u32 *out_pos, hipStream_t s) {
-    if (mp.tile == 1024)
-        launch_tiles<256, 1024>(in, ps, k, w, mp, out_x, out_seq, out_pos, s);
-    else if (mp.tile == 256)
-        launch_tiles<128, 256>(in, ps, k, w, mp, out_x, out_seq, out_pos, s);
-    else
-        throw Error(MT_EINTERNAL, "unsupported minimizer tile");
+template <int TILE>
+static void launch_emit(const mt_seqs &in, const PackedSeqs &ps, u32 k, MinimizerPlan &mp, u64 *out_x,
+                        u32 *out_seq, u32 *out_pos, hipStream_t s) {
+    k_min_emit<TILE><<<grid_for(mp.tiles_cap, EMIT_WPB), 64 * EMIT_WPB, 0, s>>>(
+        ps.lohi.p, ps.nb.p, ps.blk_off.p, mp.tile_off.p, mp.tile_map.p, in.n, k, mp.tile_bits.p, mp.min_off.p, out_x,
+        out_seq, out_pos);
+    MT_HIP(hipGetLastError());
 }
 
 void minimizer_plan(const mt_seqs &in, const PackedSeqs &ps, u32 k, u32 w, int tile, MinimizerPlan &mp,
@@ -220,6 +289,8 @@ void minimizer_plan(const mt_seqs &in, const PackedSeqs &ps, u32 k, u32 w, int t
     mp.tile_map.alloc(mp.tiles_cap);
     mp.tile_count.alloc(mp.tiles_cap);
     mp.min_off.alloc(mp.tiles_cap + 1);
+    mp.tile_bits.alloc(mp.tiles_cap * (u64)(tile / 64));
+    if (tile != 256 && tile != 1024) throw Error(MT_EINTERNAL, "unsupported minimizer tile");
     if (in.n == 0) {  // no tiles: every offset is 0 (callers read min_off[tiles_cap])
         MT_HIP(hipMemsetAsync(mp.tile_off.p, 0, sizeof(u64), s));
         MT_HIP(hipMemsetAsync(mp.min_off.p, 0, (mp.tiles_cap + 1) * sizeof(u64), s));
@@ -231,15 +302,22 @@ void minimizer_plan(const mt_seqs &in, const PackedSeqs &ps, u32 k, u32 w, int t
     scan_u64(ntile.p, mp.tile_off.p, in.n, s);
     segment_map(mp.tile_off.p, in.n, mp.tile_map.p, mp.tiles_cap, s);
     MT_HIP(hipMemsetAsync(mp.tile_count.p, 0, mp.tiles_cap * sizeof(u32), s));
-    run_tiles(in, ps, k, w, mp, nullptr, nullptr, nullptr, s);
+    if (tile == 1024)
+        launch_tiles<256, 1024>(in, ps, k, w, mp, s);
+    else
+        launch_tiles<128, 256>(in, ps, k, w, mp, s);
     // min_off over the full tile bound: tiles past the real count hold 0.
     scan_u32(mp.tile_count.p, mp.min_off.p, mp.tiles_cap, s);
 }
 
 void minimizer_emit(const mt_seqs &in, const PackedSeqs &ps, u32 k, u32 w, MinimizerPlan &mp, u64 *out_x,
                     u32 *out_seq, u32 *out_pos, hipStream_t s) {
+    (void)w;
     if (in.n == 0) return;
-    run_tiles(in, ps, k, w, mp, out_x, out_seq, out_pos, s);
+    if (mp.tile == 1024)
+        launch_emit<1024>(in, ps, k, mp, out_x, out_seq, out_pos, s);
+    else
+        launch_emit<256>(in, ps, k, mp, out_x, out_seq, out_pos, s);
 }
 
 }  // namespace mt

@@ -31,6 +31,7 @@ struct MinimizerPlan {
     DBuf<u64> tile_off;   // n + 1
     DBuf<u32> tile_map;   // tile -> sequence
     DBuf<u32> tile_count;
+    DBuf<u64> tile_bits;  // TILE / 64 words of chosen starts per tile
     DBuf<u64> min_off;    // n_tiles + 1 (allocated for the tile bound)
     u64 tiles_cap = 0;
 };

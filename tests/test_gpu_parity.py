@@ -124,6 +124,74 @@ def test_many_hits_per_read_uses_large_path(mt, mode):
     assert np.diff(co).max() > 100
 
 
+@pytest.mark.parametrize("seed", range(8))
+def test_minimizer_counts_match_oracle(mt, seed):
+    """Reference and read minimizers counted exactly: both tile sizes (reads
+    averaging over 512 bases take the 1024-start tiles), windows of 1 to 20
+    (unrolled and looped), N bases, repeats and sequences shorter than one
+    window."""
+    rnd = random.Random(500 + seed)
+    k, w = rnd.choice([3, 5, 11, 15, 21, 31]), rnd.choice([1, 2, 10, 11, 12, 13, 20])
+    motif = "".join(rnd.choice("ACGT") for _ in range(rnd.randint(3, 12)))
+
+    def seq(L):
+        s = []
+        while len(s) < L:
+            u = rnd.random()
+            s.extend(motif if u < 0.2 else ("N" if u < 0.22 else rnd.choice("ACGT")))
+        return "".join(s[:L])
+
+    genomes = [seq(rnd.randint(1, 5000)) for _ in range(rnd.randint(1, 6))]
+    long_reads = seed % 2 == 1
+    reads = [seq(rnd.choice([0, 1, k - 1, k, k + w - 2, rnd.randint(20, 300)] +
+                            ([rnd.randint(600, 4000)] * 4 if long_reads else []))) for _ in range(80)]
+    ix = mt.Index(synth.SeqSet.from_list(genomes), k, w)
+    gm = [oracle.minimizers(g.encode(), k, w) for g in genomes]
+    info = ix.info()
+    assert info["n_minimizers"] == sum(len(p) for p, _ in gm)
+    assert info["n_keys"] == len({x for _, xs in gm for x in xs.tolist()})
+    res = ix.classify(mt.to_device(synth.SeqSet.from_list(reads)), min_hits=1, top_n=0, mode=0)
+    res.free()
+    rm = [oracle.minimizers(r.encode(), k, w) for r in reads]
+    assert mt.last_stats()["n_minimizers"] == sum(len(p) for p, _ in rm)
+    assert (np.mean([len(r) for r in reads]) > 512) == long_reads
+
+
+def _hits_per_read(genomes, reads, k, w):
+    """Seed hits of every read: each read minimizer counts every occurrence
+    of its k-mer value among the genomes' minimizers."""
+    occ = {}
+    for g in genomes:
+        for x in oracle.minimizers(g.encode(), k, w)[1].tolist():
+            occ[x] = occ.get(x, 0) + 1
+    return np.array([sum(occ.get(x, 0) for x in oracle.minimizers(r.encode(), k, w)[1].tolist()) for r in reads])
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("top_n", [0, 3])
+def test_hit_count_tiers(mt, mode, top_n):
+    """Reads whose seed-hit totals fall in every counting tier of the
+    per-stage kernels (one wavefront holding one or four hits per lane, one
+    block sorting in LDS, the global-memory sort), many with tied counts."""
+    rnd = random.Random(91)
+    unit = "".join(rnd.choice("ACGT") for _ in range(40))
+    rand = "".join(rnd.choice("ACGT") for _ in range(12_000))
+    rep = "".join(unit if rnd.random() < 0.8 else rnd.choice("ACGT") * 40 for _ in range(150))
+    genomes = [rand[:6000] + rep[:3000], rand[6000:] + rep[3000:]]
+    reads = []
+    for L in (20, 40, 60, 100, 150, 250, 400, 700, 1000, 1500):
+        for _ in range(3):
+            g = genomes[rnd.randrange(2)]
+            st = rnd.randrange(0, 6000 - L) if rnd.random() < 0.7 else rnd.randrange(5000, 9000 - L)
+            reads.append(g[st:st + L])
+    H = _hits_per_read(genomes, reads, 8, 3)
+    assert (H <= 64).any() and ((H > 64) & (H <= 256)).any()
+    assert ((H > 256) & (H <= 2048)).any() and (H > 2048).any()
+    got, ref = run_both(mt, synth.SeqSet.from_list(genomes), synth.SeqSet.from_list(reads), 8, 3, min_hits=2,
+                        top_n=top_n, e_value=5, mode=mode)
+    assert_same(got, ref, f"tiers mode {mode} top_n {top_n}")
+
+
 def test_fused_fallback_for_hit_overflow(mt):
     """Short reads with more seed hits than the fused kernel holds go to the
     per-stage kernels and still match the oracle."""
@@ -155,6 +223,27 @@ def test_keep_all_candidates_short_reads(mt, mode):
     assert_same(got, ref, "keep-all")
     nc = np.diff(ref["cand_offsets"].astype(np.int64))
     assert (nc > 8).any() and ((nc > 0) & (nc <= 8)).any()
+
+
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("n_taxa", [3, 5000])
+def test_taxon_counts_few_and_many_taxa(mt, mode, n_taxa):
+    """Per-taxon unique/multi/unmapped counts with several genomes per taxon
+    and with more taxa than a block of the taxon step counts in LDS; genome
+    families make reads map to several genomes at the same count."""
+    rnd = np.random.default_rng(n_taxa)
+    bases = [synth.random_codes(rnd, 15_000) for _ in range(3)]
+    fam = [synth.substitute(rnd, b, 0.003) for b in bases for _ in range(4)] + [synth.random_codes(rnd, 15_000)]
+    genomes = synth.SeqSet.from_list([synth.ACGT[f].tobytes() for f in fam])
+    starts = rnd.integers(0, 14_800, 3000)
+    src = rnd.integers(0, len(fam), 3000)
+    reads = [synth.ACGT[fam[g][st:st + 150]].tobytes() for g, st in zip(src, starts)]
+    reads += [synth.ACGT[synth.random_codes(rnd, 150)].tobytes() for _ in range(100)]  # unmapped
+    taxon = rnd.integers(0, n_taxa, len(fam)).astype(np.uint32)
+    got, ref = run_both(mt, genomes, synth.SeqSet.from_list(reads), 15, 10, taxon=taxon, n_taxa=n_taxa, min_hits=2,
+                        top_n=0, e_value=7, mode=mode)
+    assert_same(got, ref, f"taxa {n_taxa} mode {mode}")
+    assert ref["multi"].sum() > 100 and ref["unique"].sum() > 100 and ref["unmapped"] >= 100
 
 
 @pytest.mark.parametrize("mode", MODES)

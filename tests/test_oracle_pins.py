@@ -68,6 +68,15 @@ def test_mix64_is_a_bijection():
         assert _mix64_inverse(oracle.mix64(x)) == x
 
 
+def test_no_kmer_hashes_to_all_ones():
+    """The one 64-bit value whose hash is all ones lies above every k-mer
+    value (k <= 31 gives values below 2^62), so an all-ones hash can stand
+    for an invalid k-mer in a window minimum."""
+    x = _mix64_inverse(M64)
+    assert oracle.mix64(x) == M64
+    assert x >= 1 << 62
+
+
 # -------------------------------------------------------------- minimizers ---
 
 def _kmers(seq, k):
