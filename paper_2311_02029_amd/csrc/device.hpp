@@ -244,17 +244,28 @@ __host__ __device__ inline u64 bucket_of(u64 x, u64 nbuckets) {
     return ((mix64(x ^ 0x632be59bd9b4e019ull) >> 32) * nbuckets) >> 32;
 }
 
-// Looks k-mer x up; returns the slot value or SLOT_NONE if absent.
+// Looks k-mer x up; returns the slot value or SLOT_NONE if absent.  The
+// 4-slot bucket probe: all four slots are loaded before any compare, and
+// the first slot (in slot order) that holds x or is empty decides, through a
+// chain of selects rather than branches.  Slots fill in order, so a bucket
+// with an empty slot and no x means x is absent; a full bucket without x
+// sends the probe on to the next bucket.
 __device__ inline u64 table_lookup(const u64x2 *__restrict__ table, u64 nbuckets, u64 x) {
     u64 b = bucket_of(x, nbuckets);
     for (;;) {
         const u64x2 *bk = table + b * 4;
-#pragma unroll
-        for (int s = 0; s < 4; s++) {
-            u64x2 e = bk[s];
-            if (e.lo == x) return e.hi;
-            if (e.lo == SLOT_EMPTY_KEY) return SLOT_NONE;
-        }
+        const u64x2 e0 = bk[0], e1 = bk[1], e2 = bk[2], e3 = bk[3];
+        // Use every value here: otherwise the compiler loads only the keys in
+        // the loop and fetches the chosen value afterwards, a second round
+        // trip to memory per probe.
+        asm volatile("" ::"v"(e0.hi), "v"(e1.hi), "v"(e2.hi), "v"(e3.hi));
+        const bool d0 = e0.lo == x || e0.lo == SLOT_EMPTY_KEY, d1 = e1.lo == x || e1.lo == SLOT_EMPTY_KEY;
+        const bool d2 = e2.lo == x || e2.lo == SLOT_EMPTY_KEY, d3 = e3.lo == x || e3.lo == SLOT_EMPTY_KEY;
+        u64 v = e3.lo == x ? e3.hi : SLOT_NONE;
+        v = d2 ? (e2.lo == x ? e2.hi : SLOT_NONE) : v;
+        v = d1 ? (e1.lo == x ? e1.hi : SLOT_NONE) : v;
+        v = d0 ? (e0.lo == x ? e0.hi : SLOT_NONE) : v;
+        if (d0 | d1 | d2 | d3) return v;
         b = (b + 1 == nbuckets) ? 0 : b + 1;
     }
 }

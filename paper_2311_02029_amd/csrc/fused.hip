@@ -21,6 +21,9 @@
 // than 256 seed hits, or more than 8 candidates when every candidate is kept)
 // are queued and finished by the per-stage kernels, so every read gets the
 // same result as in per-stage mode; top_n above 8 runs per stage throughout.
+#include <cstddef>
+#include <type_traits>
+
 #include "classify.hpp"
 
 namespace mt {
@@ -75,6 +78,21 @@ struct FusedArgs {
     const u32 *gate;  // offsets check result: nonzero skips the whole launch
     u64 *stats_part;  // ST_COUNT work counts per block
 };
+static_assert(std::is_standard_layout<FusedArgs>::value, "FusedArgs fields are read by offset");
+
+// A field of the launch's arguments read from the kernel-argument segment
+// where it is used rather than held in scalar registers throughout: the
+// fields used once per read or per pair would otherwise crowd out the
+// registers the loop needs, and spilled scalar registers cost a vector
+// instruction at every use.  FusedArgs is the kernel's only argument, so it
+// starts the segment.
+template <class T>
+__device__ inline T karg_field(size_t off) {
+    const __attribute__((address_space(4))) char *base =
+        (const __attribute__((address_space(4))) char *)__builtin_amdgcn_kernarg_segment_ptr();
+    return *(volatile const __attribute__((address_space(4))) T *)(base + off);
+}
+#define KA(field) karg_field<decltype(FusedArgs::field)>(offsetof(FusedArgs, field))
 
 // A read whose candidates wait in the filter queue (per-wave LDS).
 struct PendRead {
@@ -141,27 +159,6 @@ __device__ inline int reg_run(RowBits r, int j) {
         if (v) return run + (int)__builtin_ctzll(v);
         run += 64;
         w += 1;
-    }
-}
-
-// The 4-slot bucket probe: all four slots are loaded before any compare, and
-// the first slot (in slot order) that holds x or is empty decides, through a
-// chain of selects rather than branches.  Slots fill in order, so a bucket
-// with an empty slot and no x means x is absent; a full bucket without x
-// sends the probe on to the next bucket.
-__device__ inline u64 bucket_lookup(const u64x2 *__restrict__ table, u64 nbuckets, u64 x) {
-    u64 b = bucket_of(x, nbuckets);
-    for (;;) {
-        const u64x2 *bk = table + b * 4;
-        const u64x2 e0 = bk[0], e1 = bk[1], e2 = bk[2], e3 = bk[3];
-        const bool d0 = e0.lo == x || e0.lo == SLOT_EMPTY_KEY, d1 = e1.lo == x || e1.lo == SLOT_EMPTY_KEY;
-        const bool d2 = e2.lo == x || e2.lo == SLOT_EMPTY_KEY, d3 = e3.lo == x || e3.lo == SLOT_EMPTY_KEY;
-        u64 v = e3.lo == x ? e3.hi : SLOT_NONE;
-        v = d2 ? (e2.lo == x ? e2.hi : SLOT_NONE) : v;
-        v = d1 ? (e1.lo == x ? e1.hi : SLOT_NONE) : v;
-        v = d0 ? (e0.lo == x ? e0.hi : SLOT_NONE) : v;
-        if (d0 | d1 | d2 | d3) return v;
-        b = (b + 1 == nbuckets) ? 0 : b + 1;
     }
 }
 
@@ -254,12 +251,12 @@ __device__ inline void filter_batch(const FusedArgs &a, const QEntry *q, int qn,
     const int E = pr.E, m = pr.m;
     const u32 g = key_genome(e.key);
     const i64 diag = key_diag(e.key);
-    const GenomeMeta gm = a.meta[g];
+    const GenomeMeta gm = KA(meta)[g];
     RowBits row{~0ull, ~0ull, ~0ull, ~0ull};
     if (lane_g < 2 * E + 1) {
         const i64 base = diag + (lane_g - E);
-        const u64x2 *rl = a.ref_lohi + gm.blk;
-        const u64 *rn = a.ref_nb + gm.blk;
+        const u64x2 *rl = KA(ref_lohi) + gm.blk;
+        const u64 *rn = KA(ref_nb) + gm.blk;
         const i64 L = (i64)gm.len;
         const bool hn = meta_has_n(gm);
         Bits64 w0 = fetch_ref(rl, rn, L, hn, base);
@@ -282,11 +279,11 @@ __device__ inline void filter_batch(const FusedArgs &a, const QEntry *q, int qn,
     }
     const int ap = c < E + 1 ? c : E + 1;
     if (lane_g == 0) {
-        a.st_genome[e.out] = g;
-        a.st_diag[e.out] = diag;
-        a.st_hits[e.out] = e.hits;
-        a.st_approx[e.out] = (u16)ap;
-        a.st_accept[e.out] = ap <= E;
+        KA(st_genome)[e.out] = g;
+        KA(st_diag)[e.out] = diag;
+        KA(st_hits)[e.out] = e.hits;
+        KA(st_approx)[e.out] = (u16)ap;
+        KA(st_accept)[e.out] = ap <= E;
         pr.apx[e.cidx] = (u16)ap;
         pr.tax[e.cidx] = meta_taxon(gm);
     }
@@ -301,11 +298,11 @@ __device__ inline void finalize_read(const FusedArgs &a, const PendRead &pr) {
     for (int c = 0; c < nc; c++)
         if (pr.apx[c] <= E && pr.apx[c] < best) best = pr.apx[c];
     if (best == 0x7fffffff) {
-        a.read_accepted[pr.r] = 0;
-        atomicAdd(a.unmapped, 1ull);
+        KA(read_accepted)[pr.r] = 0;
+        atomicAdd(KA(unmapped), 1ull);
         return;
     }
-    a.read_accepted[pr.r] = 1;
+    KA(read_accepted)[pr.r] = 1;
     int nt = 0;
     u32 first = 0;
     for (int c = 0; c < nc; c++) {
@@ -317,14 +314,14 @@ __device__ inline void finalize_read(const FusedArgs &a, const PendRead &pr) {
         nt++;
     }
     if (nt == 1) {
-        atomicAdd(&a.uniq[first], 1ull);
+        atomicAdd(&KA(uniq)[first], 1ull);
         return;
     }
     for (int c = 0; c < nc; c++) {
         if (pr.apx[c] != best) continue;
         bool seen = false;
         for (int b = 0; b < c; b++) seen |= pr.apx[b] == best && pr.tax[b] == pr.tax[c];
-        if (!seen) atomicAdd(&a.multi[pr.tax[c]], 1ull);
+        if (!seen) atomicAdd(&KA(multi)[pr.tax[c]], 1ull);
     }
 }
 
@@ -422,16 +419,16 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
     for (; r < a.n; r += stride) {
         const u64 rn = r + stride;
         const int m = cur.m;
-        u64 Ewide = a.e_mode == MT_E_FIXED ? a.e_value
-                    : a.e_mode == MT_E_CEIL_PERMILLE ? ((u64)m * a.e_value + 999) / 1000
-                                                     : ((u64)m * a.e_value) / 1000;
+        u64 Ewide = KA(e_mode) == MT_E_FIXED ? KA(e_value)
+                    : KA(e_mode) == MT_E_CEIL_PERMILLE ? ((u64)m * KA(e_value) + 999) / 1000
+                                                     : ((u64)m * KA(e_value)) / 1000;
         if (Ewide > 65534) wflags |= ERR_E_TOO_LARGE;
         const int E = Ewide > 65535 ? 65535 : (int)Ewide;
-        if (lane == 0) a.read_E[r] = (u16)E;
+        if (lane == 0) KA(read_E)[r] = (u16)E;
         if (m > F_MAX_M || E > F_MAX_E) {
             if (lane == 0) {
-                a.fb_list[atomicAdd(a.fb_count, 1u)] = (u32)r;
-                a.ncand[r] = 0;  // until the per-stage kernels fill it in
+                KA(fb_list)[atomicAdd(KA(fb_count), 1u)] = (u32)r;
+                KA(ncand)[r] = 0;  // until the per-stage kernels fill it in
             }
             if (rn < a.n) issue_read_bytes(a, rn, lane, cur);
             continue;
@@ -467,7 +464,7 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
         }
         if (ballot64(bad)) {
             wflags |= ERR_BAD_BYTE;
-            if (lane == 0) a.ncand[r] = 0;  // the call fails; its compaction still runs
+            if (lane == 0) KA(ncand)[r] = 0;  // the call fails; its compaction still runs
             if (rn < a.n) issue_read_bytes(a, rn, lane, cur);
             continue;
         }
@@ -534,7 +531,7 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
             u32 cnt = 0;
             if (j < nmin) {
                 p = mpos[j];
-                v = bucket_lookup(a.table, a.nbuckets, stream_kmer(stream, p, k));
+                v = table_lookup(a.table, a.nbuckets, stream_kmer(stream, p, k));
                 cnt = v == SLOT_NONE ? 0u : slot_count(v);
             }
             const bool single = cnt == 1 && !(v & SLOT_MULTI);
@@ -575,7 +572,7 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
                     for (u32 u0 = 0; u0 < cnt; u0 += 4) {
                         u64 gp[4];
 #pragma unroll
-                        for (int t = 0; t < 4; t++) gp[t] = u0 + t < cnt ? a.occ[st + u0 + t] : 0ull;
+                        for (int t = 0; t < 4; t++) gp[t] = u0 + t < cnt ? KA(occ)[st + u0 + t] : 0ull;
 #pragma unroll
                         for (int t = 0; t < 4; t++)
                             if (u0 + t < cnt) table_add(tkey, tcnt, cand_key((u32)(gp[t] >> 32), (i64)(u32)gp[t] - p));
@@ -602,8 +599,8 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
                 tcnt[t] = 0;
             }
             if (lane == 0) {
-                a.fb_list[atomicAdd(a.fb_count, 1u)] = (u32)r;
-                a.ncand[r] = 0;
+                KA(fb_list)[atomicAdd(KA(fb_count), 1u)] = (u32)r;
+                KA(ncand)[r] = 0;
             }
             cur = nxt;
             wave_sync();
@@ -636,8 +633,8 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
         if (a.top_n == 0 && C > (int)N) {
             // keep-all with more candidates than staging slots: per-stage finish
             if (lane == 0) {
-                a.fb_list[atomicAdd(a.fb_count, 1u)] = (u32)r;
-                a.ncand[r] = 0;
+                KA(fb_list)[atomicAdd(KA(fb_count), 1u)] = (u32)r;
+                KA(ncand)[r] = 0;
             }
             cur = nxt;
             wave_sync();
@@ -660,11 +657,11 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
         wave_sync();
 
         // 6. queue the kept candidates for batched filtering
-        if (lane == 0) a.ncand[r] = (u32)nc;
+        if (lane == 0) KA(ncand)[r] = (u32)nc;
         if (nc == 0) {
             if (lane == 0) {
-                a.read_accepted[r] = 0;
-                atomicAdd(a.unmapped, 1ull);
+                KA(read_accepted)[r] = 0;
+                atomicAdd(KA(unmapped), 1ull);
             }
         } else {
             const int rows = 2 * E + 1;
@@ -704,14 +701,14 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
     used = flush_queue(a, queue, qn, qG, pend, used, lane);
     if (lane == 0) {
         if (used) wflags |= ERR_INTERNAL;  // every queued read is finalized by now
-        if (wflags) atomicOr(a.flags, wflags);
+        if (wflags) atomicOr(KA(flags), wflags);
     }
     // work counts: one record per block, summed by k_fused_summary
     __syncthreads();
     if (threadIdx.x < ST_COUNT) {
         u64 t = 0;
         for (int w = 0; w < F_WPB; w++) t += sh_stats[w][threadIdx.x];
-        a.stats_part[(u64)blockIdx.x * ST_COUNT + threadIdx.x] = t;
+        KA(stats_part)[(u64)blockIdx.x * ST_COUNT + threadIdx.x] = t;
     }
 }
 
