@@ -196,8 +196,9 @@ __device__ inline u64 stream_kmer(const u32 *st, int i, u32 k) {
 }
 
 // Smallest hash of window [ws, ws + W) (leftmost on ties), all W hashes read
-// before the compare chain; -1 when every hash reads ~0.  Unrolled for
-// W <= 12 (the usual minimizer windows); wider windows take a loop.
+// before the compare chain; -1 when every hash reads ~0 (no valid k-mer in
+// the window).  Unrolled for W <= 12 (the usual minimizer windows); wider
+// windows take a loop.
 template <int W>
 __device__ inline int window_argmin(const u64 *hh, int ws) {
     u64 v[W];
@@ -376,7 +377,6 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
     __shared__ u32 sh_tcnt[F_WPB][F_TSLOTS]; // ... and their seed-hit counts
     __shared__ u16 sh_pos[F_WPB][F_MAX_M];   // minimizer positions; later candidate hit counts
     __shared__ u8 sh_pick[F_WPB][F_MAX_M];   // window picks
-    __shared__ u8 sh_ok[F_WPB][F_MAX_M];     // k-mer has no N
     __shared__ u32 sh_st[F_WPB][F_WORDS];    // big-endian 2-bit stream of the read
     __shared__ u32 sh_sel[F_WPB][F_MAX_TOPN];
     __shared__ QEntry sh_q[F_WPB][F_QCAP];
@@ -393,7 +393,6 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
     u16 *ccnt = sh_pos[wid];  // candidate hit counts reuse the minimizer positions (dead after the probes)
     u16 *mpos = sh_pos[wid];
     u8 *pick = sh_pick[wid];
-    u8 *okk = sh_ok[wid];
     u32 *stream = sh_st[wid];
     u32 *sel = sh_sel[wid];
     QEntry *queue = sh_q[wid];
@@ -475,19 +474,17 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
 #pragma unroll
         for (int q = 0; q < 4; q++) {
             int i = 64 * q + lane;
-            bool ok = false;
             if (i < nk) {
                 u64 nb = funnel(pr.plane[8 + q], q < 3 ? pr.plane[9 + q] : ~0ull, (u32)lane);
-                ok = (nb & kmask) == 0;
-                hh[i] = ok ? mix64(stream_kmer(stream, i, k)) : ~0ull;
+                hh[i] = (nb & kmask) == 0 ? mix64(stream_kmer(stream, i, k)) : ~0ull;
             }
-            okk[i] = ok;
             pick[i] = 0;
         }
         wave_sync();
 
-        // 3. window minima: an invalid k-mer reads as ~0 and never wins unless
-        // the whole window is ~0, which the slow path resolves exactly.
+        // 3. window minima: an invalid k-mer reads as ~0, a hash no valid k-mer
+        // has (the hash is a bijection and the preimage of ~0 lies above every
+        // 62-bit k-mer value), so a window of ~0 alone has no minimizer.
         int nmin = 0;
         if (nk > 0) {
             const int win = nk < (int)a.w ? nk : (int)a.w;
@@ -496,13 +493,7 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
             for (int q = 0; q < 4; q++) {
                 int ws = 64 * q + lane;
                 if (ws < nws) {
-                    int best = window_argmin_any(hh, ws, win);
-                    if (best < 0)  // every hash read ~0: leftmost valid k-mer, if any
-                        for (int t = 0; t < win; t++)
-                            if (okk[ws + t]) {
-                                best = ws + t;
-                                break;
-                            }
+                    const int best = window_argmin_any(hh, ws, win);
                     if (best >= 0) pick[best] = 1;
                 }
             }
