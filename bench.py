@@ -54,6 +54,19 @@ def measured_traffic(kernel: str):
     return int(rec["traffic_bytes_per_dispatch"])
 
 
+def filter_useful_ops(host: dict, lengths) -> int:
+    """Useful int32 lane-ops of the filter over a result's pairs: building
+    the (2E+1) rows of ceil(m/64) mismatch words at 6 ops a word, plus 8 ops
+    per row for each step of the obstacle walk (min(approx, E) + 1 steps)."""
+    co = np.asarray(host["cand_offsets"], dtype=np.int64)
+    pr = np.repeat(np.arange(len(co) - 1), np.diff(co))
+    E = np.asarray(host["read_E"], dtype=np.int64)[pr]
+    m = np.asarray(lengths, dtype=np.int64)[pr]
+    ap = np.asarray(host["approx"], dtype=np.int64)
+    rows = 2 * E + 1
+    return int((6 * rows * ((m + 63) // 64) + 8 * rows * (np.minimum(ap, E) + 1)).sum())
+
+
 def _pct(v, q):
     return float(np.percentile(np.asarray(v, dtype=np.float64), q)) if len(v) else None
 
@@ -408,11 +421,24 @@ def main() -> int:
                         "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                         "traffic": measured_traffic(dom) if args.workload == "batched" else None,
                         "avg_ms": round(stages[dom], 4), "algorithmic_bytes": int(alg)}
+            if roofline["traffic"]:
+                # the same launch against its counter-measured HBM bytes
+                roofline["traffic_gbs"] = round(roofline["traffic"] / dur_s / 1e9, 1)
+                roofline["traffic_frac"] = round(roofline["traffic_gbs"] / HBM_PEAK_GBS, 4)
             vi = measured_valu(dom) if args.workload == "batched" and args.E == 7 else None
             if vi is not None:
                 # counter-measured VALU issue against the integer VALU peak (same live duration)
                 roofline["valu"] = {"wave_instructions": int(vi), "peak_lane_ops_per_s": VALU_WAVE_INSTR_PEAK * 64,
                                     "issue_frac": round(vi / (dur_s * VALU_WAVE_INSTR_PEAK), 4)}
+            if dom == "fused":
+                # the filter's useful integer work by the op model (one more, untimed classification)
+                r = ix.classify(dreads, **q)
+                useful = filter_useful_ops(r.to_host(), reads.lengths())
+                r.free()
+                roofline["filter_useful_ops"] = {
+                    "lane_ops": int(useful),
+                    "model": "per pair 6*(2E+1)*ceil(m/64) + 8*(2E+1)*(min(approx,E)+1) int32 ops",
+                    "frac_of_peak_over_kernel_time": round(useful / (dur_s * VALU_WAVE_INSTR_PEAK * 64), 5)}
         else:
             roofline = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": None, "traffic": None, "avg_ms": round(stages[dom], 4)}

@@ -247,6 +247,21 @@ def test_taxon_counts_few_and_many_taxa(mt, mode, n_taxa):
 
 
 @pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("E", [0, 31, 32])
+def test_fused_limit_boundaries(mt, mode, E):
+    """Reads at the fused kernel's limits and just past them (256 / 257 bases,
+    E 31 / 32) and at the 64-base word boundaries of its planes and band rows
+    give the oracle's result in every form."""
+    rnd = np.random.default_rng(17)
+    gen = synth.make_genomes(rnd, 4, 30_000, 0.5)
+    lens = np.array([1, 20, 63, 64, 65, 127, 128, 129, 191, 192, 193, 255, 256, 257, 300] * 12)
+    reads, _ = synth.make_reads(rnd, gen, lens, 0.01, 0.002)
+    got, ref = run_both(mt, gen.ascii(), reads, 15, 10, min_hits=2, top_n=3, e_value=E, mode=mode)
+    assert_same(got, ref, f"E={E} mode {mode}")
+    assert ref["read_accepted"].sum() > (10 if E == 0 else len(lens) // 2)
+
+
+@pytest.mark.parametrize("mode", MODES)
 def test_long_reads_large_E_bit_exact(mt, mode):
     rnd = np.random.default_rng(5)
     gen = synth.make_genomes(rnd, 3, 60_000, 0.5)
