@@ -168,6 +168,7 @@ __global__ __launch_bounds__(TPB) void k_min_tiles(const u64x2 *__restrict__ loh
                                                    u64 n, u32 k, u32 w, u32 *__restrict__ tile_count,
                                                    u64 *__restrict__ tile_bits) {
     static_assert(TILE % TPB == 0 && TPB % 64 == 0, "tile of whole wavefront passes");
+    static_assert((TILE + 2 * MAX_HALO) / TPB + 1 + 31 <= 64, "a thread's starts and k-mers fit its 64-base window");
     constexpr int SPAN = TILE + 2 * MAX_HALO;
     __shared__ u64 sh_h[SPAN];
     __shared__ u8 chosen[TILE];
@@ -184,10 +185,23 @@ __global__ __launch_bounds__(TPB) void k_min_tiles(const u64x2 *__restrict__ loh
     const i64 h1 = t1 + win - 1 < nk ? t1 + win - 1 : nk;
     const u64x2 *ql = lohi + blk_off[s];
     const u64 *qn = nbp + blk_off[s];
-    const u64 kmask = (1ull << k) - 1;
-    for (i64 i = h0 + threadIdx.x; i < h1; i += TPB) {
-        const Bits64 b = fetch_planes(ql, qn, i);
-        sh_h[i - h0] = (b.nb & kmask) == 0 ? mix64(kmer_value(b.lo, b.hi, k)) : ~0ull;
+    // Each thread hashes a run of consecutive starts: the first k-mer value
+    // from its 64-base window, the next ones rolled in one base at a time.
+    const u64 kmask = (1ull << k) - 1, xmask = (1ull << (2 * k)) - 1;
+    const int span = (int)(h1 - h0);
+    const int run = (span + TPB - 1) / TPB;  // at most (TILE + 2 * MAX_HALO) / TPB + 1 <= 64 - 31
+    const int c0 = (int)threadIdx.x * run;
+    if (c0 < span) {
+        const Bits64 b = fetch_planes(ql, qn, h0 + c0);
+        u64 x = kmer_value(b.lo, b.hi, k);
+        const int cn = min(run, span - c0);
+        for (int j = 0; j < cn; j++) {
+            if (j > 0) {
+                const u32 t = (u32)j + k - 1;  // the base entering the k-mer
+                x = ((x << 2) | (((b.hi >> t) & 1ull) << 1) | ((b.lo >> t) & 1ull)) & xmask;
+            }
+            sh_h[c0 + j] = ((b.nb >> j) & kmask) == 0 ? mix64(x) : ~0ull;
+        }
     }
     for (int i = threadIdx.x; i < TILE; i += TPB) chosen[i] = 0;
     if (threadIdx.x == 0) total = 0;
