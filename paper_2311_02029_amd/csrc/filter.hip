@@ -153,7 +153,9 @@ __device__ inline void lds_wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// 64 bases from position p of planes staged in LDS (p >= 0, block p/64 + 1 staged).
+// 64 bases from position p of planes staged in LDS (p >= 0, block p/64 + 1
+// staged); kWithN = false reads the N plane as zero.
+template <bool kWithN = true>
 __device__ inline Bits64 lds_bits(const u64x2 *lohi, const u64 *nb, i64 p) {
     u64 b = (u64)p >> 6;
     u32 s = (u32)p & 63u;
@@ -161,7 +163,7 @@ __device__ inline Bits64 lds_bits(const u64x2 *lohi, const u64 *nb, i64 p) {
     Bits64 r;
     r.lo = funnel(x0.lo, x1.lo, s);
     r.hi = funnel(x0.hi, x1.hi, s);
-    r.nb = funnel(nb[b], nb[b + 1], s);
+    r.nb = kWithN ? funnel(nb[b], nb[b + 1], s) : 0ull;
     return r;
 }
 
@@ -171,6 +173,87 @@ __device__ inline u32 plane_dw(const u64x2 *lohi, int pl, u32 k) {
     return reinterpret_cast<const u32 *>(lohi)[(k >> 1) * 4 + pl * 2 + (k & 1)];
 }
 __device__ inline u32 nb_dw(const u64 *nb, u32 k) { return reinterpret_cast<const u32 *>(nb)[k]; }
+
+// The obstacle walk of one pair over planes staged in LDS (read at L / NB,
+// window at WL / WN, row 0 and column 0 at window offset wbase), rows in
+// contiguous strips per lane; returns the obstacle count.  kWithN = false
+// leaves the window's N plane out: only for pairs whose compared window lies
+// inside a genome without N, where that plane is zero.
+template <bool kWithN>
+__device__ inline int long_walk(const u64x2 *L, const u64 *NB, const u64x2 *WL, const u64 *WN, i64 wbase, int m,
+                                int E, int lane) {
+    // lane owns the contiguous rows [r0, r1); per step each chunk of 32 of
+    // them is compared over 32 columns from three window dwords per plane
+    // (one alignbit per plane and row), and only a row with no obstacle
+    // in those columns continues 64 columns at a time
+    const int rows = 2 * E + 1;
+    const int S = (rows + 63) / 64;
+    const int r0 = min(lane * S, rows), r1 = min(r0 + S, rows);
+    int j = 0, c = 0;
+    for (;;) {
+        // 32 read bases from j (one alignbit per plane)
+        const u32 kq = (u32)j >> 5, sq = (u32)j & 31u;
+        const u32 ql = __builtin_amdgcn_alignbit(plane_dw(L, 0, kq + 1), plane_dw(L, 0, kq), sq);
+        const u32 qh = __builtin_amdgcn_alignbit(plane_dw(L, 1, kq + 1), plane_dw(L, 1, kq), sq);
+        const u32 qn = __builtin_amdgcn_alignbit(nb_dw(NB, kq + 1), nb_dw(NB, kq), sq);
+        const int left = m - j;
+        int best = 0;
+        for (int s0 = r0; s0 < r1; s0 += 32) {  // chunks of <= 32 rows
+            // window bases of rows s0.. at column j start at p0; three
+            // dwords per plane cover every row of the chunk
+            const i64 p0 = wbase + (s0 - E) + j;
+            const u32 k0 = (u32)((u64)p0 >> 5), sh0 = (u32)p0 & 31u;
+            const u32 l0 = plane_dw(WL, 0, k0), l1 = plane_dw(WL, 0, k0 + 1), l2 = plane_dw(WL, 0, k0 + 2);
+            const u32 h0 = plane_dw(WL, 1, k0), h1 = plane_dw(WL, 1, k0 + 1), h2 = plane_dw(WL, 1, k0 + 2);
+            u32 n0 = 0, n1 = 0, n2 = 0;
+            if constexpr (kWithN) {
+                n0 = nb_dw(WN, k0);
+                n1 = nb_dw(WN, k0 + 1);
+                n2 = nb_dw(WN, k0 + 2);
+            }
+            const int cnt = min(32, r1 - s0);
+            const int split = min(cnt, 32 - (int)sh0);  // rows whose window starts in dword k0
+            for (int i = 0; i < cnt; i++) {
+                u32 wl, wh, wn;
+                if (i < split) {
+                    const u32 sh = sh0 + (u32)i;
+                    wl = __builtin_amdgcn_alignbit(l1, l0, sh);
+                    wh = __builtin_amdgcn_alignbit(h1, h0, sh);
+                    wn = kWithN ? __builtin_amdgcn_alignbit(n1, n0, sh) : 0u;
+                } else {
+                    const u32 sh = sh0 + (u32)i - 32u;
+                    wl = __builtin_amdgcn_alignbit(l2, l1, sh);
+                    wh = __builtin_amdgcn_alignbit(h2, h1, sh);
+                    wn = kWithN ? __builtin_amdgcn_alignbit(n2, n1, sh) : 0u;
+                }
+                const u32 mm = (ql ^ wl) | (qh ^ wh) | qn | wn;
+                int run;
+                if (mm) {
+                    run = (int)__builtin_ctz(mm);
+                } else {  // 32 matching columns: continue 64 at a time
+                    run = 32;
+                    const i64 pos = p0 + i;
+                    while (j + run < m) {
+                        const u64 m2 = mismatch(lds_bits(L, NB, j + run), lds_bits<kWithN>(WL, WN, pos + run));
+                        if (m2) {
+                            run += (int)__builtin_ctzll(m2);
+                            break;
+                        }
+                        run += 64;
+                    }
+                }
+                best = max(best, min(run, left));
+            }
+        }
+        best = group_max<64>(best);
+        j += best;
+        if (j >= m) break;
+        c += 1;
+        if (c > E) break;
+        j += 1;
+    }
+    return c;
+}
 
 // Long reads / large E: one wavefront per pair, planes in LDS (`tile` blocks
 // per wavefront, at least the pairs' nrb + nwb; blockDim.x / 64 wavefronts).
@@ -194,6 +277,7 @@ __global__ __launch_bounds__(512) void k_filter_long(FilterArgs a, const u32 *__
         const i64 b0 = (diag - E) >> 6;  // first window block (floor)
         const i64 gblocks = ((i64)gm.len + 63) / 64 + 1;
         const u64 rb = a.read_blk[r];
+        const bool with_n = meta_has_n(gm) || diag - E < 0 || diag + m + E > (i64)gm.len;
         for (int b = lane; b < nrb; b += 64) {
             L[b] = a.read_lohi[rb + b];
             NB[b] = a.read_nb[rb + b];
@@ -204,7 +288,7 @@ __global__ __launch_bounds__(512) void k_filter_long(FilterArgs a, const u32 *__
             u64 nbv = ~0ull;
             if (gb >= 0 && gb < gblocks) {
                 v = a.ref_lohi[gm.blk + (u64)gb];
-                nbv = a.ref_nb[gm.blk + (u64)gb];
+                nbv = with_n ? a.ref_nb[gm.blk + (u64)gb] : 0ull;
             }
             L[nrb + b] = v;
             NB[nrb + b] = nbv;
@@ -213,71 +297,9 @@ __global__ __launch_bounds__(512) void k_filter_long(FilterArgs a, const u32 *__
         const u64x2 *WL = L + nrb;
         const u64 *WN = NB + nrb;
         const i64 wbase = diag - 64 * b0;  // window offset of (row 0, column 0)
-        // lane owns the contiguous rows [r0, r1); per step each chunk of 32 of
-        // them is compared over 32 columns from three window dwords per plane
-        // (one alignbit per plane and row), and only a row with no obstacle
-        // in those columns continues 64 columns at a time
-        const int rows = 2 * E + 1;
-        const int S = (rows + 63) / 64;
-        const int r0 = min(lane * S, rows), r1 = min(r0 + S, rows);
-        int j = 0, c = 0;
-        for (;;) {
-            // 32 read bases from j (one alignbit per plane)
-            const u32 kq = (u32)j >> 5, sq = (u32)j & 31u;
-            const u32 ql = __builtin_amdgcn_alignbit(plane_dw(L, 0, kq + 1), plane_dw(L, 0, kq), sq);
-            const u32 qh = __builtin_amdgcn_alignbit(plane_dw(L, 1, kq + 1), plane_dw(L, 1, kq), sq);
-            const u32 qn = __builtin_amdgcn_alignbit(nb_dw(NB, kq + 1), nb_dw(NB, kq), sq);
-            const int left = m - j;
-            int best = 0;
-            for (int s0 = r0; s0 < r1; s0 += 32) {  // chunks of <= 32 rows
-                // window bases of rows s0.. at column j start at p0; three
-                // dwords per plane cover every row of the chunk
-                const i64 p0 = wbase + (s0 - E) + j;
-                const u32 k0 = (u32)((u64)p0 >> 5), sh0 = (u32)p0 & 31u;
-                const u32 l0 = plane_dw(WL, 0, k0), l1 = plane_dw(WL, 0, k0 + 1), l2 = plane_dw(WL, 0, k0 + 2);
-                const u32 h0 = plane_dw(WL, 1, k0), h1 = plane_dw(WL, 1, k0 + 1), h2 = plane_dw(WL, 1, k0 + 2);
-                const u32 n0 = nb_dw(WN, k0), n1 = nb_dw(WN, k0 + 1), n2 = nb_dw(WN, k0 + 2);
-                const int cnt = min(32, r1 - s0);
-                const int split = min(cnt, 32 - (int)sh0);  // rows whose window starts in dword k0
-                for (int i = 0; i < cnt; i++) {
-                    u32 wl, wh, wn;
-                    if (i < split) {
-                        const u32 sh = sh0 + (u32)i;
-                        wl = __builtin_amdgcn_alignbit(l1, l0, sh);
-                        wh = __builtin_amdgcn_alignbit(h1, h0, sh);
-                        wn = __builtin_amdgcn_alignbit(n1, n0, sh);
-                    } else {
-                        const u32 sh = sh0 + (u32)i - 32u;
-                        wl = __builtin_amdgcn_alignbit(l2, l1, sh);
-                        wh = __builtin_amdgcn_alignbit(h2, h1, sh);
-                        wn = __builtin_amdgcn_alignbit(n2, n1, sh);
-                    }
-                    const u32 mm = (ql ^ wl) | (qh ^ wh) | qn | wn;
-                    int run;
-                    if (mm) {
-                        run = (int)__builtin_ctz(mm);
-                    } else {  // 32 matching columns: continue 64 at a time
-                        run = 32;
-                        const i64 pos = p0 + i;
-                        while (j + run < m) {
-                            const u64 m2 = mismatch(lds_bits(L, NB, j + run), lds_bits(WL, WN, pos + run));
-                            if (m2) {
-                                run += (int)__builtin_ctzll(m2);
-                                break;
-                            }
-                            run += 64;
-                        }
-                    }
-                    best = max(best, min(run, left));
-                }
-            }
-            best = group_max<64>(best);
-            j += best;
-            if (j >= m) break;
-            c += 1;
-            if (c > E) break;
-            j += 1;
-        }
+        // every compared window position inside a genome without N: no N plane
+        const int c = with_n ? long_walk<true>(L, NB, WL, WN, wbase, m, E, lane)
+                             : long_walk<false>(L, NB, WL, WN, wbase, m, E, lane);
         const int ap = c < E + 1 ? c : E + 1;
         if (lane == 0) {
             a.approx[p] = (u16)ap;

@@ -321,6 +321,41 @@ def test_filter_pairs_against_oracle(mt):
     assert (oap <= pe).mean() > 0.3 and (oap > pe).mean() > 0.05
 
 
+def test_filter_long_pairs_at_edges_and_n(mt):
+    """Long-read pairs (E > 31, LDS kernel) whose window runs past either end
+    of the genome, lies in a genome with N bases, or lies inside a genome
+    without N (the kernel drops the window's N plane only there)."""
+    import torch
+    rnd = np.random.default_rng(23)
+    gen = synth.make_genomes(rnd, 3, 40_000, 0.5)
+    lens = rnd.integers(800, 4000, 60)
+    reads, origin = synth.make_reads(rnd, gen, lens, 0.02, 0.02)
+    reads = synth.inject_n(rnd, reads, 0.001)
+    ga = gen.ascii()
+    seq = ga.seq.copy()  # genome 2 gets N bases
+    g2 = slice(int(ga.offsets[2]), int(ga.offsets[3]))
+    hit = rnd.random(g2.stop - g2.start) < 0.002
+    seq[g2][hit] = ord("N")
+    ga = synth.SeqSet(seq=seq, offsets=ga.offsets)
+    n = 900
+    pr = rnd.integers(0, reads.n, n).astype(np.uint32)
+    pg = origin[pr, 0].astype(np.uint32)
+    pdg = (origin[pr, 1] + rnd.integers(-30, 31, n)).astype(np.int64)
+    pdg[:100] = rnd.integers(-600, 40, 100)  # window before the genome start
+    pdg[100:200] = 40_000 - lens[pr[100:200]] + rnd.integers(-40, 600, 100)  # past the end
+    pe = rnd.integers(32, 260, n).astype(np.uint16)
+    ix = mt.Index(ga, 15, 10)
+    ap, ac = ix.filter_pairs(mt.to_device(reads), torch.from_numpy(pr.view(np.int32)).cuda(),
+                             torch.from_numpy(pg.view(np.int32)).cuda(), torch.from_numpy(pdg).cuda(),
+                             torch.from_numpy(pe.view(np.int16)).cuda())
+    ap = ap.cpu().numpy().view(np.uint16)
+    oap, oac = oracle.Index(ga, 15, 10).filter_pairs(reads, pr, pg, pdg, pe)
+    assert np.array_equal(ap, oap), np.flatnonzero(ap != oap)[:10]
+    assert np.array_equal(ac.cpu().numpy(), oac)
+    inside = (pdg - pe >= 0) & (pdg + lens[pr] + pe <= 40_000) & (pg != 2)
+    assert inside.sum() > 100 and (~inside).sum() > 100 and (oap <= pe).mean() > 0.2
+
+
 def test_repeat_calls_and_modes_identical(mt):
     gen, reads, p = synth.workload_small(3000)
     ix = mt.Index(gen.ascii(), p["k"], p["w"])
