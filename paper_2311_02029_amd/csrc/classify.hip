@@ -200,19 +200,29 @@ static unsigned count_blocks() {
     return (unsigned)std::max(cus, 1) * 4;
 }
 
-// One block per queued read whose hits fit in LDS (sorted there); reads with
-// more are queued again for k_count_large.
+constexpr u32 COUNT_SLOTS = 2 * COUNT_CAP;  // LDS hash table of a read's locations
+
+// Slot of a location key in a table of `slots` (a power of two) slots.
+__device__ inline u32 count_slot(u64 key, u32 slots) {
+    const u32 x = (u32)key ^ (u32)(key >> 29);
+    return (x * 0x9E3779B1u) >> (32 - __builtin_ctz(slots));
+}
+
+// One block per queued read whose hits fit in LDS: its hits are counted in an
+// LDS hash table of locations (CAS on the key, atomic add on the count; ~0 is
+// never a key, since genomes number fewer than 2^31), the locations with at
+// least min_hits hits are compacted in place and ranked in the canonical
+// order.  Reads with more hits are queued again for k_count_large.
 __global__ __launch_bounds__(COUNT_TPB) void k_count_block(const u64 *__restrict__ hit_key,
                                                            const u64 *__restrict__ read_hs, u32 min_hits, u32 top_n,
                                                            u64 *__restrict__ stage_key, u32 *__restrict__ stage_hits,
                                                            u32 *__restrict__ ncand, const u32 *__restrict__ mid_list,
                                                            const u32 *__restrict__ n_mid, u32 *__restrict__ large_list,
                                                            u32 *__restrict__ n_large) {
-    __shared__ u64 key[COUNT_CAP];
-    __shared__ u64 ck[COUNT_CAP];
-    __shared__ u32 ch[COUNT_CAP];
-    __shared__ u32 nc;
+    __shared__ u64 tkey[COUNT_SLOTS];
+    __shared__ u32 tcnt[COUNT_SLOTS];
     const u32 nm = *n_mid;
+    const u32 T = min_hits ? min_hits : 1;
     for (u32 li = blockIdx.x; li < nm; li += gridDim.x) {
         __syncthreads();  // the previous read is done with the LDS arrays
         const u64 r = mid_list[li];
@@ -221,46 +231,54 @@ __global__ __launch_bounds__(COUNT_TPB) void k_count_block(const u64 *__restrict
             if (threadIdx.x == 0) large_list[atomicAdd(n_large, 1u)] = (u32)r;
             continue;
         }
-        for (u64 i = threadIdx.x; i < H; i += COUNT_TPB) key[i] = hit_key[hs + i];
-        if (threadIdx.x == 0) nc = 0;
-        u64 P = 1;
-        while (P < H) P <<= 1;
-        __syncthreads();
-        for (u64 k = 2; k <= P; k <<= 1) {
-            for (u64 j = k >> 1; j > 0; j >>= 1) {
-                bool mirror = j == (k >> 1);
-                for (u64 t = threadIdx.x; t < P / 2; t += COUNT_TPB) {
-                    u64 i, l;
-                    bitonic_pair(t, k, j, mirror, i, l);
-                    if (l < H && key[i] > key[l]) {
-                        u64 tmp = key[i];
-                        key[i] = key[l];
-                        key[l] = tmp;
-                    }
-                }
-                __syncthreads();
-            }
+        u32 slots = COUNT_TPB;  // a power of two >= 2H: load at most one half
+        while (slots < 2 * H) slots <<= 1;
+        for (u32 i = threadIdx.x; i < slots; i += COUNT_TPB) {
+            tkey[i] = ~0ull;
+            tcnt[i] = 0;
         }
-        u32 T = min_hits ? min_hits : 1;
+        __syncthreads();
         for (u64 i = threadIdx.x; i < H; i += COUNT_TPB) {
-            if (i > 0 && key[i] == key[i - 1]) continue;
-            u64 j = i + 1;
-            while (j < H && key[j] == key[i]) j++;
-            u32 c = (u32)(j - i);
-            if (c >= T) {
-                u32 s = atomicAdd(&nc, 1u);
-                ck[s] = key[i];
-                ch[s] = c;
+            const u64 key = hit_key[hs + i];
+            for (u32 sl = count_slot(key, slots);; sl = (sl + 1) & (slots - 1)) {
+                u64 cur = tkey[sl];
+                if (cur == ~0ull) {
+                    cur = atomicCAS((unsigned long long *)&tkey[sl], ~0ull, (unsigned long long)key);
+                    if (cur == ~0ull) cur = key;
+                }
+                if (cur == key) {
+                    atomicAdd(&tcnt[sl], 1u);
+                    break;
+                }
             }
         }
         __syncthreads();
-        u32 C = nc;
+        // candidates to the front of the table, in slot order: a candidate
+        // moves to index <= its slot, and every slot of a round is read
+        // before the round's barrier, every move made after it
+        u32 C = 0;
+        for (u32 base = 0; base < slots; base += COUNT_TPB) {
+            const u32 t = base + threadIdx.x;
+            const u64 key = tkey[t];
+            const u32 c = tcnt[t];
+            const u32 is_c = key != ~0ull && c >= T;
+            u32 tot;
+            const u32 pre = block_exclusive_sum<COUNT_TPB, u32>(is_c, &tot);
+            if (is_c) {
+                tkey[C + pre] = key;
+                tcnt[C + pre] = c;
+            }
+            C += tot;
+        }
+        __syncthreads();
         for (u32 a = threadIdx.x; a < C; a += COUNT_TPB) {
+            const u64 ka = tkey[a];
+            const u32 ha = tcnt[a];
             u32 rank = 0;
-            for (u32 b = 0; b < C; b++) rank += cand_before(ch[b], ck[b], ch[a], ck[a]);
+            for (u32 b = 0; b < C; b++) rank += cand_before(tcnt[b], tkey[b], ha, ka);
             if (top_n == 0 || rank < top_n) {
-                stage_key[hs + rank] = ck[a];
-                stage_hits[hs + rank] = ch[a];
+                stage_key[hs + rank] = ka;
+                stage_hits[hs + rank] = ha;
             }
         }
         if (threadIdx.x == 0) ncand[r] = top_n && C > top_n ? top_n : C;
