@@ -267,7 +267,7 @@ def main() -> int:
     ap.add_argument("--no-timing", action="store_true", help="do not record per-stage HIP events")
     ap.add_argument("--genomes", type=int, default=200, help="genomes of 2.5 Mbp in the database")
     ap.add_argument("--autotune", type=int, default=-1,
-                    help="1: time the filter variants on a sample of the batch first and keep the fastest per "
+                    help="1: time the filter variants on the batch (up to 2M reads) first and keep the fastest per "
                          "bucket (default: on for the uneven workload); 0: built-in defaults")
     ap.add_argument("--serving", type=int, default=1,
                     help="1: also measure the served workload (batched workload only); 0: skip it")
@@ -364,8 +364,8 @@ def main() -> int:
         args.autotune = 1 if args.workload == "uneven" else 0
     if args.autotune:
         t = time.time()
-        sample = mt.to_device(reads.subset(np.arange(min(reads.n, 200_000))))
-        info = ix.autotune(sample, reps=2, **{k: v for k, v in q.items() if k != "mode"})
+        sample = mt.to_device(reads.subset(np.arange(min(reads.n, 2_000_000))))
+        info = ix.autotune(sample, reps=3, **{k: v for k, v in q.items() if k != "mode"})
         del sample
         tune = {b["name"]: b["current"] for b in info if b["pairs"]}
         log(f"[bench] autotuned in {time.time() - t:.1f}s: "
