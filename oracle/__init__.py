@@ -62,6 +62,10 @@ def _declare(lib):
     lib.or_filter_pairs.restype = C.c_int
     lib.or_filter_pairs.argtypes = [C.c_void_p, u8p, u64p, C.c_uint64, u32p, u32p, i64p, u16p, C.c_uint64,
                                     u16p, u8p]
+    lib.or_containment.restype = C.c_int
+    lib.or_containment.argtypes = [C.c_void_p, u8p, u64p, C.c_uint64, u64p]
+    lib.or_select_genomes.restype = C.c_int64
+    lib.or_select_genomes.argtypes = [u64p, C.c_uint64, C.c_uint64, C.c_uint64, u32p, u64p]
     return lib
 
 
@@ -187,3 +191,26 @@ class Index:
         if rc != 0:
             raise ValueError("oracle filter_pairs rejected its input")
         return ap, ac
+
+    def containment(self, reads) -> np.ndarray:
+        """Stage 1: seed hits of every genome over the read set (uint64 per genome)."""
+        seq = np.ascontiguousarray(reads.seq, dtype=np.uint8)
+        offs = np.ascontiguousarray(reads.offsets, dtype=np.uint64)
+        hits = np.zeros(max(self.n_genomes, 1), np.uint64)
+        rc = self.lib.or_containment(self.h, _p(seq, C.c_uint8), _p(offs, C.c_uint64), len(offs) - 1,
+                                     _p(hits, C.c_uint64))
+        if rc != 0:
+            raise ValueError("oracle containment rejected its input")
+        return hits[:self.n_genomes]
+
+
+def select_genomes(hits, num: int = 1, den: int = 10_000, lib=None):
+    """Subset database: (kept genome indices ascending, largest seed-hit count)."""
+    lib = lib or load()
+    h = np.ascontiguousarray(hits, dtype=np.uint64)
+    sel = np.zeros(max(len(h), 1), np.uint32)
+    mx = np.zeros(1, np.uint64)
+    c = lib.or_select_genomes(_p(h, C.c_uint64), len(h), num, den, _p(sel, C.c_uint32), _p(mx, C.c_uint64))
+    if c < 0:
+        raise ValueError("cutoff denominator must be nonzero")
+    return sel[:c].copy(), int(mx[0])

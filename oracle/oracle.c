@@ -47,6 +47,14 @@
  *       the taxa of accepted candidates whose approx equals the smallest
  *       accepted approx of the read; one taxon -> unique[t] += 1, several ->
  *       multi[t] += 1 for each; none -> unmapped += 1.
+ *   O9  stage 1 (containment search): the seed-hit count of genome g over a
+ *       read set is the number of (read minimizer, minimizer occurrence in g)
+ *       pairs with equal k-mer, summed over all reads, keys above max_occ
+ *       skipped -- the O4 matches of every read summed over its diagonals.
+ *   O10 subset database: with M the largest seed-hit count over the genomes,
+ *       genome g is kept iff hits[g] / M exceeds the cutoff num / den
+ *       (strictly: "above" / "surpasses"), decided exactly as
+ *       hits[g] * den > M * num; M = 0 keeps no genome.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -531,4 +539,55 @@ int or_filter_pairs(const or_index *ix, const uint8_t *seq, const uint64_t *offs
         free(q);
     }
     return OR_OK;
+}
+
+/* ----------------------------------------- stage 1 containment search ---- */
+
+/*
+ * Containment search (Fig. 1 steps 1a-1c, "Containment Search"): seeds
+ * every read (ASCII + offsets[n+1]) and adds to hits[g] one per seed match in
+ * genome g (reading O9).  hits: n_genomes entries, overwritten.  Returns
+ * OR_EINVAL on a bad byte or a read longer than 65535.
+ */
+int or_containment(const or_index *ix, const uint8_t *seq, const uint64_t *offsets, uint64_t n, uint64_t *hits)
+{
+    for (uint64_t g = 0; g < ix->n_genomes; g++) hits[g] = 0;
+    for (uint64_t r = 0; r < n; r++) {
+        int64_t m = (int64_t)(offsets[r + 1] - offsets[r]);
+        if (m > (int64_t)MAX_READ_LEN) return OR_EINVAL;
+        uint8_t *q = malloc((size_t)(m > 0 ? m : 1));
+        if (encode(seq + offsets[r], m, q) != OR_OK) { free(q); return OR_EINVAL; }
+        int64_t nk = m - ix->k + 1 > 0 ? m - ix->k + 1 : 0;
+        int64_t *mpos = malloc((size_t)(nk ? nk : 1) * sizeof *mpos);
+        uint64_t *mx = malloc((size_t)(nk ? nk : 1) * sizeof *mx);
+        int64_t nmin = minimizers_of_codes(q, m, ix->k, ix->w, mpos, mx);
+        for (int64_t i = 0; i < nmin; i++) {
+            int64_t lo = lower_bound(ix->occ, ix->n_occ, mx[i]);
+            int64_t hi = lo;
+            while (hi < ix->n_occ && ix->occ[hi].x == mx[i]) hi++;
+            if (ix->max_occ && (uint64_t)(hi - lo) > ix->max_occ) continue; /* O4 cap */
+            for (int64_t o = lo; o < hi; o++) hits[ix->occ[o].genome] += 1;
+        }
+        free(mpos); free(mx); free(q);
+    }
+    return OR_OK;
+}
+
+/*
+ * Subset database selection (Fig. 1 step 1d; the normalised seed-hit cutoff of
+ * the containment Evaluation Methodology): reading O10 with exact 128-bit
+ * products.  selected receives the kept genome indices in ascending order and
+ * *max_out the largest count.  Returns the number kept, or -1 when den is 0.
+ */
+int64_t or_select_genomes(const uint64_t *hits, uint64_t n, uint64_t num, uint64_t den, uint32_t *selected,
+                          uint64_t *max_out)
+{
+    if (den == 0) return -1;
+    uint64_t M = 0;
+    for (uint64_t g = 0; g < n; g++) if (hits[g] > M) M = hits[g];
+    *max_out = M;
+    int64_t c = 0;
+    for (uint64_t g = 0; g < n; g++)
+        if ((unsigned __int128)hits[g] * den > (unsigned __int128)M * num) selected[c++] = (uint32_t)g;
+    return c;
 }

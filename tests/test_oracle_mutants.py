@@ -12,6 +12,7 @@ import oracle
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "oracle.c")
+PIN_FILES = [os.path.join(ROOT, "tests", f) for f in ("test_oracle_pins.py", "test_oracle_containment.py")]
 
 # (name, original text, planted mistake); each original occurs exactly once.
 MUTANTS = [
@@ -49,6 +50,13 @@ MUTANTS = [
      "if (a <= E && (best < 0 || a > best)) best = a;"),
     ("multi counted once", "if (ntax > 1) res->multi_reads[t]++;", "if (ntax > 1 && t == only) res->multi_reads[t]++;"),
     ("unique ignores ties", "if (ntax == 1) res->unique_reads[only]++;", "if (ntax >= 1) res->unique_reads[only]++;"),
+    ("containment counts a key once", "for (int64_t o = lo; o < hi; o++) hits[ix->occ[o].genome] += 1;",
+     "if (hi > lo) hits[ix->occ[lo].genome] += 1;"),
+    ("containment cap inclusive", "if (ix->max_occ && (uint64_t)(hi - lo) > ix->max_occ) continue;",
+     "if (ix->max_occ && (uint64_t)(hi - lo) >= ix->max_occ) continue;"),
+    ("selection not strict", "> (unsigned __int128)M * num) selected", ">= (unsigned __int128)M * num) selected"),
+    ("selection in 64 bits", "if ((unsigned __int128)hits[g] * den > (unsigned __int128)M * num)",
+     "if (hits[g] * den > M * num)"),
 ]
 
 
@@ -61,9 +69,8 @@ def test_pins_catch_planted_mistake(name, orig, mut, tmp_path):
     lib = str(tmp_path / "liboracle_mutant.so")
     subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", lib, str(mutant_c)])
     env = dict(os.environ, ORACLE_LIB=lib)
-    r = subprocess.run([sys.executable, "-m", "pytest", os.path.join(ROOT, "tests", "test_oracle_pins.py"), "-x",
-                        "-q", "-p", "no:cacheprovider"], cwd=ROOT, env=env, capture_output=True, text=True,
-                       timeout=600)
+    r = subprocess.run([sys.executable, "-m", "pytest", *PIN_FILES, "-x", "-q", "-p", "no:cacheprovider"], cwd=ROOT,
+                       env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"no pin caught the planted mistake '{name}'"
 
 
@@ -71,6 +78,6 @@ def test_unmutated_copy_passes_the_pins(tmp_path):
     lib = str(tmp_path / "liboracle_copy.so")
     oracle.build(lib)
     env = dict(os.environ, ORACLE_LIB=lib)
-    r = subprocess.run([sys.executable, "-m", "pytest", os.path.join(ROOT, "tests", "test_oracle_pins.py"), "-q",
-                        "-p", "no:cacheprovider"], cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    r = subprocess.run([sys.executable, "-m", "pytest", *PIN_FILES, "-q", "-p", "no:cacheprovider"], cwd=ROOT,
+                       env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode == 0, r.stdout[-2000:]
