@@ -443,6 +443,24 @@ def main() -> int:
             roofline = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": None, "traffic": None, "avg_ms": round(stages[dom], 4)}
 
+    # Stage 1 (containment search) on the same resident index and batch.
+    containment = None
+    if args.workload == "batched" and hasattr(ix, "containment"):
+        hits = ix.containment(dreads)  # warm
+        torch.cuda.synchronize()
+        reps = 5
+        t = time.perf_counter()
+        for _ in range(reps):
+            hits = ix.containment(dreads)
+            sel, mx = mt.select_genomes(hits, 1, 10_000)
+        torch.cuda.synchronize()
+        c_ms = (time.perf_counter() - t) * 1000.0 / reps
+        total = int(hits.cpu().numpy().view(np.uint64).sum())
+        containment = {"ms": round(c_ms, 3), "reads_per_s": round(reads.n / (c_ms / 1000.0), 1),
+                       "seed_hits_per_s": round(total / (c_ms / 1000.0), 1), "seed_hits": total,
+                       "genomes": int(hits.numel()), "kept_at_1e-4": int(sel.numel()), "max_hits": mx}
+        log(f"[bench] containment: {json.dumps(containment)}")
+
     serving = None
     if pool is not None:
         serving = serving_bench(mt, ix, pool, seconds=args.serve_seconds, n_streams=args.serve_streams,
@@ -475,6 +493,7 @@ def main() -> int:
         "roofline": roofline,
         "filter_tuning": tune,
         "cpu_baseline": cpu,
+        "containment": containment,
         "serving": serving,
     }
     print(json.dumps(out), flush=True)

@@ -209,6 +209,37 @@ int mt_filter_pairs(const mt_index *index, const mt_seqs *reads, const uint32_t 
                     uint64_t n_pairs, uint16_t *approx_out, uint8_t *accept_out, void *stream);
 
 /*
+ * Containment search (Fig. 1 steps 1a-1c; section "Containment Search"): the
+ * seed-hit count of every genome of the index over the whole read set -- one
+ * hit per (read minimizer, occurrence of its k-mer among the genome's
+ * minimizers), k-mers above max_occ skipped, summed over all reads (the
+ * stage-2 seed matches of every read summed over its locations).
+ *   index  the resident index (the counts run on it, no other copy is made).
+ *   reads  host struct with device seq/offsets, as for mt_classify.
+ *   hits   device, n_genomes 64-bit counts, overwritten; owned by the caller.
+ * The call returns when the counts are written.  Errors: MT_EINVAL (null
+ * argument, byte outside ACGTN, read longer than 65535), MT_ENOMEM,
+ * MT_EDEVICE.
+ */
+int mt_containment(const mt_index *index, const mt_seqs *reads, uint64_t *hits, void *stream);
+
+/*
+ * Subset-database selection (Fig. 1 step 1d; the normalised seed-hit cutoff
+ * of the containment evaluation): with M the largest count, genome g is kept
+ * when hits[g] / M exceeds cutoff_num / cutoff_den (the paper: 1 / 10000),
+ * decided exactly as hits[g] * cutoff_den > M * cutoff_num in 128-bit
+ * arithmetic; M = 0 keeps none.  For an index split into shards, pass the
+ * per-genome maximum over the shards' counts (the paper's merge rule).
+ *   hits        device, n_genomes counts (e.g. from mt_containment).
+ *   selected    device, n_genomes capacity: the kept genome indices, ascending.
+ *   n_selected  host: how many were kept.   max_hits  host: M.
+ * The call waits for its stream.  Errors: MT_EINVAL (null argument,
+ * cutoff_den 0), MT_EDEVICE.
+ */
+int mt_select_genomes(const uint64_t *hits, uint64_t n_genomes, uint64_t cutoff_num, uint64_t cutoff_den,
+                      uint32_t *selected, uint64_t *n_selected, uint64_t *max_hits, void *stream);
+
+/*
  * Serving loop: continuous batching of classification requests on one GPU
  * with the index resident in HBM.  Requests that arrive while others run are
  * admitted as batch slots and device memory free up; reads of several

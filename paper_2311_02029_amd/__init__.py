@@ -17,7 +17,7 @@ from ._abi import (MT_E_CEIL_PERMILLE, MT_E_FIXED, MT_E_FLOOR_PERMILLE, MT_MODE_
                    MT_MODE_FUSED_GRAPH, MT_MODE_PER_STAGE, MT_OK)
 
 __all__ = ["MTError", "DeviceSeqs", "Index", "Result", "Server", "to_device", "mt_set_timing", "last_timings",
-           "tune_info", "tune_set", "tune_reset", "tune_save", "tune_load"]
+           "tune_info", "tune_set", "tune_reset", "tune_save", "tune_load", "select_genomes"]
 
 
 class MTError(RuntimeError):
@@ -131,6 +131,21 @@ def last_timings() -> list[tuple[str, float]]:
     n = C.c_uint32()
     _check(lib.mt_last_timings(names, ms, cap, C.byref(n)), lib)
     return [(names[i].decode(), float(ms[i])) for i in range(n.value)]
+
+
+def select_genomes(hits, cutoff_num: int = 1, cutoff_den: int = 10_000, stream=None):
+    """Subset database (mt_select_genomes): the genomes whose seed-hit count over
+    the largest exceeds cutoff_num / cutoff_den.  hits: device int64 tensor of
+    uint64 counts.  Returns (kept genome indices as a device int32 tensor,
+    ascending; the largest count)."""
+    torch = _torch()
+    lib = _abi.load()
+    n = int(hits.numel())
+    sel = torch.empty(max(n, 1), dtype=torch.int32, device=hits.device if n else "cuda")
+    ns, mx = C.c_uint64(), C.c_uint64()
+    _check(lib.mt_select_genomes(hits.data_ptr() if n else None, n, cutoff_num, cutoff_den, sel.data_ptr(),
+                                 C.byref(ns), C.byref(mx), _stream_ptr(stream)), lib)
+    return sel[:ns.value], int(mx.value)
 
 
 def tune_info() -> list[dict]:
@@ -254,6 +269,16 @@ class Index:
         inf = _abi.mt_index_info()
         _check(self.lib.mt_index_get_info(self.h, C.byref(inf)), self.lib)
         return {f: getattr(inf, f) for f, _ in inf._fields_}
+
+    def containment(self, reads: DeviceSeqs, stream=None):
+        """Stage 1: seed hits of every genome over the read set (mt_containment);
+        a device int64 tensor holding the uint64 counts."""
+        torch = _torch()
+        n = int(self.info()["n_genomes"])
+        hits = torch.empty(max(n, 1), dtype=torch.int64, device="cuda")
+        _check(self.lib.mt_containment(self.h, C.byref(reads.abi()), hits.data_ptr(), _stream_ptr(stream)),
+               self.lib)
+        return hits[:n]
 
     def classify(self, reads: DeviceSeqs, min_hits=3, top_n=3, e_mode=MT_E_FIXED, e_value=7,
                  mode=MT_MODE_PER_STAGE, stream=None) -> Result:

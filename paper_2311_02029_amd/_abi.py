@@ -21,7 +21,7 @@ ABI_FUNCTIONS = (
     "mt_filter_pairs", "mt_trim", "mt_last_error", "mt_abi_version", "mt_last_stats", "mt_server_create",
     "mt_server_submit", "mt_server_wait", "mt_server_destroy", "mt_result_on_host", "mt_result_times",
     "mt_tune_buckets", "mt_tune_info", "mt_tune_set", "mt_tune_reset", "mt_autotune", "mt_tune_save",
-    "mt_tune_load",
+    "mt_tune_load", "mt_containment", "mt_select_genomes",
 )
 
 
@@ -104,6 +104,8 @@ def load(path: str = LIB_PATH):
         "mt_autotune": (i32, [vp, C.POINTER(mt_query_params), C.POINTER(mt_seqs), u32, vp]),
         "mt_tune_save": (i32, [C.c_char_p]),
         "mt_tune_load": (i32, [C.c_char_p]),
+        "mt_containment": (i32, [vp, C.POINTER(mt_seqs), vp, vp]),
+        "mt_select_genomes": (i32, [vp, u64, u64, u64, vp, C.POINTER(u64), C.POINTER(u64), vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

@@ -231,7 +231,8 @@ __global__ __launch_bounds__(TPB) void k_min_tiles(const u64x2 *__restrict__ loh
 
 // One wavefront per tile: the marked starts are first listed in LDS, then
 // their k-mer values computed 64 at a time (one lane per start) and written in
-// start order at the tile's output offset with sequence and position.
+// start order at the tile's output offset with sequence and position (each
+// of those two outputs may be null).
 constexpr int EMIT_WPB = 4;
 
 template <int TILE>
@@ -272,8 +273,8 @@ __global__ __launch_bounds__(64 * EMIT_WPB) void k_min_emit(const u64x2 *__restr
             const i64 i = t0 + list[b + lane];
             const Bits64 bits = fetch_planes(ql, qn, i);
             out_x[o + b + lane] = kmer_value(bits.lo, bits.hi, k);
-            out_seq[o + b + lane] = s;
-            out_pos[o + b + lane] = (u32)i;
+            if (out_seq) out_seq[o + b + lane] = s;
+            if (out_pos) out_pos[o + b + lane] = (u32)i;
         }
     }
 }

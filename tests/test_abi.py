@@ -80,3 +80,11 @@ def test_null_arguments_are_errors_not_crashes():
     assert lib.mt_tune_set(6, 3) == _abi.MT_EINVAL  # 8 wavefronts x 768 blocks of LDS exceed a workgroup
     assert lib.mt_autotune(None, None, None, 1, None) == _abi.MT_EINVAL
     assert lib.mt_tune_load(None) == _abi.MT_EINVAL
+    assert lib.mt_containment(None, None, None, None) == _abi.MT_EINVAL
+    ns, mx = C.c_uint64(7), C.c_uint64(7)
+    assert lib.mt_select_genomes(None, 0, 1, 0, None, C.byref(ns), C.byref(mx), None) == _abi.MT_EINVAL
+    assert b"denominator" in lib.mt_last_error()
+    assert lib.mt_select_genomes(None, 5, 1, 10_000, None, C.byref(ns), C.byref(mx), None) == _abi.MT_EINVAL
+    # no genomes: nothing to launch, nothing kept
+    assert lib.mt_select_genomes(None, 0, 1, 10_000, None, C.byref(ns), C.byref(mx), None) == _abi.MT_OK
+    assert ns.value == 0 and mx.value == 0

@@ -56,7 +56,7 @@ def full(gpu):
             cache["ix"] = oracle.Index(ga, 21, 11)
         return cache["ix"]
 
-    return dict(ga=ga, reads=reads, fused=fused, stage=stage, graph=graph, oracle=oracle_index)
+    return dict(ga=ga, reads=reads, fused=fused, stage=stage, graph=graph, oracle=oracle_index, ix=ix, dr=dr)
 
 
 def _slice(res, idx):
@@ -72,6 +72,20 @@ def _slice(res, idx):
     out["read_accepted"] = res["read_accepted"][idx]
     out["read_E"] = res["read_E"][idx]
     return out
+
+
+def test_containment_full_size_against_oracle(full):
+    """Stage 1 over the whole batch on the resident index: every genome's seed-hit
+    count equals the oracle's, and so does the subset at the paper's cutoff."""
+    import paper_2311_02029_amd as mt
+    hits = full["ix"].containment(full["dr"])
+    got = hits.cpu().numpy().view(np.uint64)
+    want = full["oracle"]().containment(full["reads"])
+    assert np.array_equal(got, want), np.flatnonzero(got != want)[:10]
+    sel, mx = mt.select_genomes(hits, 1, 10_000)
+    osel, omx = oracle.select_genomes(want, 1, 10_000)
+    assert mx == omx and np.array_equal(sel.cpu().numpy().astype(np.uint32), osel)
+    assert want.min() > 0 and len(osel) == len(want)
 
 
 def test_fused_equals_per_stage_on_every_read(full):
