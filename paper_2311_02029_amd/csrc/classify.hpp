@@ -86,6 +86,12 @@ void classify_per_stage(const mt_index &ix, const mt_query_params &q, const mt_s
                         mt_result &res, Timer &tm, hipStream_t s);
 // Fused form.  Checks the call's flags and sets res.n_cands before it
 // returns; graph = launch the sequence as one captured HIP graph.
+// Containment search: adds every genome's seed hits over `reads` to hits
+// (device, n_genomes).  containment runs reads of up to 256 bases in one
+// fused kernel and the rest through containment_per_stage.
+void containment(const mt_index &ix, const mt_seqs &reads, u64 *hits, hipStream_t s);
+void containment_per_stage(const mt_index &ix, const mt_seqs &reads, u64 *hits, hipStream_t s);
+
 void classify_fused(const mt_index &ix, const mt_query_params &q, const mt_seqs &reads, ReadBatch &rb,
                     mt_result &res, Timer &tm, hipStream_t s, bool graph);
 void launch_max_u16(const u16 *v, u64 n, u32 *out, hipStream_t s);

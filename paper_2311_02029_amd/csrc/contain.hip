@@ -2,11 +2,11 @@
 // count of every reference genome over a whole read set, on the index that
 // stage 2 uses, and the subset-database selection by the normalised cutoff.
 //
-// Seeding and minimizer selection are the per-stage kernels' (bases packed to
-// bit planes, minimizer tiles); one kernel then probes the table for every
-// read minimizer and adds one hit to the genome of each occurrence.  Integer
-// atomics on per-block LDS counters take the place of the paper's
-// mutex-guarded per-thread seed maps.
+// Reads of up to 256 bases run in one fused kernel (fused.hip).  Longer reads
+// take the per-stage chain here: bases packed to bit planes, minimizer tiles,
+// then one kernel that probes the table for every read minimizer and adds one
+// hit to the genome of each occurrence.  Integer atomics on per-block LDS
+// counters take the place of the paper's mutex-guarded per-thread seed maps.
 #include "classify.hpp"
 #include "seq.hpp"
 
@@ -81,6 +81,26 @@ static unsigned contain_blocks(u64 n_min) {
     return (unsigned)std::max<u64>(1, std::min<u64>(grid_for(n_min, CT_TPB), (u64)std::max(cus, 1) * 8));
 }
 
+void containment_per_stage(const mt_index &ix, const mt_seqs &reads, u64 *hits, hipStream_t s) {
+    if (reads.n == 0 || ix.n_genomes == 0) return;
+    ReadBatch rb;
+    rb.prepare(reads, MT_E_FIXED, 0, s);  // validates lengths and bytes; E is unused here
+    MinimizerPlan mp;
+    const int tile = reads.total / reads.n > 512 ? 1024 : 256;
+    minimizer_plan(reads, rb.planes, ix.k, ix.w, tile, mp, s);
+    u32 f = 0;
+    u64 n_min = 0;
+    MT_HIP(hipMemcpyAsync(&f, rb.flags.p, sizeof f, hipMemcpyDeviceToHost, s));
+    read_back(s, mp.min_off.p + mp.tiles_cap, &n_min, sizeof n_min);
+    check_flags(f);
+    if (n_min == 0) return;
+    DBuf<u64> min_x(n_min);
+    minimizer_emit(reads, rb.planes, ix.k, ix.w, mp, min_x.p, nullptr, nullptr, s);
+    k_contain<<<contain_blocks(n_min), CT_TPB, 0, s>>>(min_x.p, n_min, ix.table.p, ix.nbuckets, ix.occ.p,
+                                                        ix.n_genomes, (unsigned long long *)hits);
+    MT_HIP(hipGetLastError());
+}
+
 }  // namespace mt
 
 using namespace mt;
@@ -94,26 +114,8 @@ extern "C" int mt_containment(const mt_index *index, const mt_seqs *reads, uint6
     return guarded("mt_containment", [&] {
         MT_REQUIRE(reads->n == 0 || (reads->seq && reads->offsets), "null read arrays");
         CallScope scope(s);
-        if (index->n_genomes)
-            MT_HIP(hipMemsetAsync(hits, 0, index->n_genomes * sizeof(uint64_t), s));
-        if (reads->n == 0) return;
-        ReadBatch rb;
-        rb.prepare(*reads, MT_E_FIXED, 0, s);  // validates lengths and bytes; E is unused here
-        MinimizerPlan mp;
-        const int tile = reads->total / reads->n > 512 ? 1024 : 256;
-        minimizer_plan(*reads, rb.planes, index->k, index->w, tile, mp, s);
-        u32 f = 0;
-        u64 n_min = 0;
-        MT_HIP(hipMemcpyAsync(&f, rb.flags.p, sizeof f, hipMemcpyDeviceToHost, s));
-        read_back(s, mp.min_off.p + mp.tiles_cap, &n_min, sizeof n_min);
-        check_flags(f);
-        if (n_min == 0 || index->n_genomes == 0) return;
-        DBuf<u64> min_x(n_min);
-        minimizer_emit(*reads, rb.planes, index->k, index->w, mp, min_x.p, nullptr, nullptr, s);
-        k_contain<<<contain_blocks(n_min), CT_TPB, 0, s>>>(min_x.p, n_min, index->table.p, index->nbuckets,
-                                                            index->occ.p, index->n_genomes,
-                                                            (unsigned long long *)hits);
-        MT_HIP(hipGetLastError());
+        if (index->n_genomes) MT_HIP(hipMemsetAsync(hits, 0, index->n_genomes * sizeof(uint64_t), s));
+        containment(*index, *reads, hits, s);
     });
 }
 

@@ -1070,4 +1070,177 @@ void classify_fused(const mt_index &ix, const mt_query_params &q, const mt_seqs 
     tm.mark("fallback");
 }
 
+// ------------------------------------------------------ containment search --
+
+// Containment search (Fig. 1 steps 1a-1c) for reads of up to F_MAX_M bases,
+// one wavefront per read: its N plane by ballot and its 2-bit stream in LDS,
+// k-mer hashes and window minima as in k_fused (steps 1-3), then one table
+// probe per minimizer lane adding one hit to the genome of every occurrence.
+// Up to CF_LDS_GENOMES genomes a block counts in LDS and adds its nonzero
+// counters to the global ones when it ends; with more genomes the hits go to
+// the global counters directly.  Longer reads are listed for the per-stage
+// chain.
+struct ContainArgs {
+    const u8 *seq;
+    const u64 *off;
+    u64 n;
+    u32 k, w;
+    const u64x2 *table;
+    u64 nbuckets;
+    const u64 *occ;
+    u64 n_genomes;
+    unsigned long long *hits;
+    u32 *fb_list;
+    u32 *fb_count;
+    u32 *flags;
+    const u32 *gate;  // offsets check result: nonzero skips the whole launch
+};
+
+constexpr u64 CF_LDS_GENOMES = 2048;  // 64-bit counters, 16 KB per block
+
+__global__ __launch_bounds__(64 * F_WPB) void k_contain_fused(ContainArgs a) {
+    __shared__ u64 sh_h[F_WPB][F_MAX_M];
+    __shared__ u16 sh_pos[F_WPB][F_MAX_M];
+    __shared__ u8 sh_pick[F_WPB][F_MAX_M];
+    __shared__ u32 sh_st[F_WPB][F_WORDS];
+    __shared__ u64 sh_nb[F_WPB][4];
+    __shared__ unsigned long long cnt[CF_LDS_GENOMES];
+    if (*a.gate) return;  // malformed offsets: the whole grid leaves
+    const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    u64 *hh = sh_h[wid];
+    u16 *mpos = sh_pos[wid];
+    u8 *pick = sh_pick[wid];
+    u32 *stream = sh_st[wid];
+    u64 *nbp = sh_nb[wid];
+    const bool in_lds = a.n_genomes <= CF_LDS_GENOMES;  // uniform over the grid
+    unsigned long long *dst = in_lds ? cnt : a.hits;
+    if (in_lds)
+        for (u64 g = threadIdx.x; g < a.n_genomes; g += blockDim.x) cnt[g] = 0;
+    __syncthreads();
+    const u32 k = a.k;
+    const u64 kmask = (1ull << k) - 1;
+    u32 wflags = 0;
+    for (u64 r = (u64)blockIdx.x * F_WPB + wid; r < a.n; r += (u64)gridDim.x * F_WPB) {
+        const u64 beg = a.off[r];
+        const int m = (int)(a.off[r + 1] - beg);
+        if (m > F_MAX_M) {
+            if (lane == 0) a.fb_list[atomicAdd(a.fb_count, 1u)] = (u32)r;
+            continue;
+        }
+        // 1. N plane and big-endian 2-bit stream
+        if (lane < F_WORDS) stream[lane] = 0;
+        wave_sync();
+        bool bad = false;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const int i = 64 * q + lane;
+            const u32 c = i < m ? base_code(a.seq[beg + i]) : 4u;
+            bad |= c == 5;
+            const u64 nb = ballot64(c >= 4);
+            if (lane == 0) nbp[q] = nb;
+            if (c < 4 && c > 0) atomicOr(&stream[i >> 4], c << (30 - 2 * (i & 15)));
+        }
+        if (ballot64(bad)) {
+            wflags |= ERR_BAD_BYTE;  // the call fails
+            wave_sync();
+            continue;
+        }
+        wave_sync();
+        // 2. k-mer hashes (~0 for k-mers with an N)
+        const int nk = m - (int)k + 1;
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const int i = 64 * q + lane;
+            if (i < nk) {
+                const u64 nb = funnel(nbp[q], q < 3 ? nbp[q + 1] : ~0ull, (u32)lane);
+                hh[i] = (nb & kmask) == 0 ? mix64(stream_kmer(stream, i, k)) : ~0ull;
+            }
+            pick[i] = 0;
+        }
+        wave_sync();
+        // 3. window minima (~0 marks an invalid k-mer, as in k_fused) and their
+        // positions in order
+        int nmin = 0;
+        if (nk > 0) {
+            const int win = nk < (int)a.w ? nk : (int)a.w;
+            const int nws = nk - win + 1;
+#pragma unroll 1
+            for (int q = 0; q < 4; q++) {
+                const int ws = 64 * q + lane;
+                if (ws < nws) {
+                    const int best = window_argmin_any(hh, ws, win);
+                    if (best >= 0) pick[best] = 1;
+                }
+            }
+            wave_sync();
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const int i = 64 * q + lane;
+                const bool chosen = i < nk && pick[i];
+                const u64 cm = ballot64(chosen);
+                if (chosen) mpos[nmin + lanes_below(cm, lane)] = (u16)i;
+                nmin += __popcll(cm);
+            }
+            wave_sync();
+        }
+        // 4. one probe per minimizer; one hit per occurrence to its genome
+        for (int t0 = 0; t0 < nmin; t0 += 64) {
+            const int j = t0 + lane;
+            if (j >= nmin) continue;
+            const u64 v = table_lookup(a.table, a.nbuckets, stream_kmer(stream, mpos[j], k));
+            if (v == SLOT_NONE) continue;
+            if (!(v & SLOT_MULTI)) {
+                atomicAdd(&dst[v >> 32], 1ull);
+                continue;
+            }
+            const u32 c = slot_count(v);  // 0 for a k-mer above max_occ
+            const u64 st = slot_start(v);
+            for (u32 u = 0; u < c; u++) atomicAdd(&dst[a.occ[st + u] >> 32], 1ull);
+        }
+        wave_sync();  // the next read reuses the wavefront's LDS
+    }
+    if (lane == 0 && wflags) atomicOr(a.flags, wflags);
+    if (in_lds) {
+        __syncthreads();
+        for (u64 g = threadIdx.x; g < a.n_genomes; g += blockDim.x)
+            if (cnt[g]) atomicAdd(&a.hits[g], cnt[g]);
+    }
+}
+
+void containment(const mt_index &ix, const mt_seqs &reads, u64 *hits, hipStream_t s) {
+    const u64 n = reads.n;
+    if (n == 0 || ix.n_genomes == 0) return;
+    DBuf<u32> ctl(CTL_WORDS), fb_list(n);
+    k_fused_init<<<1, 64, 0, s>>>(ctl.p);
+    MT_HIP(hipGetLastError());
+    k_check_reads<<<grid_for(n, 256), 256, 0, s>>>(reads.offsets, n, reads.total, ctl.p + CTL_GATE);
+    MT_HIP(hipGetLastError());
+    int dev = 0, cus = 0;
+    MT_HIP(hipGetDevice(&dev));
+    MT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const u64 blocks = std::min<u64>(grid_for(n, F_WPB), (u64)std::max(cus, 1) * 8);
+    ContainArgs a{(const u8 *)reads.seq, reads.offsets, n, ix.k, ix.w, ix.table.p, ix.nbuckets, ix.occ.p,
+                  ix.n_genomes, (unsigned long long *)hits, fb_list.p, ctl.p + CTL_FB, ctl.p + CTL_FLAGS,
+                  ctl.p + CTL_GATE};
+    k_contain_fused<<<(unsigned)blocks, 64 * F_WPB, 0, s>>>(a);
+    MT_HIP(hipGetLastError());
+    u32 h[CTL_WORDS];
+    read_back(s, ctl.p, h, sizeof h);
+    check_flags(h[CTL_GATE] | h[CTL_FLAGS]);
+    const u32 nfb = h[CTL_FB];
+    if (nfb == 0) return;
+    // longer reads: the per-stage chain on a gathered subset, adding to hits
+    DBuf<u64> sub_len(nfb), sub_off(nfb + 1);
+    k_subset_lengths<<<grid_for(nfb, 256), 256, 0, s>>>(reads.offsets, fb_list.p, nfb, sub_len.p);
+    MT_HIP(hipGetLastError());
+    scan_u64(sub_len.p, sub_off.p, nfb, s);
+    u64 sub_total = 0;
+    read_back(s, sub_off.p + nfb, &sub_total, sizeof sub_total);
+    DBuf<u8> sub_seq(sub_total);
+    k_subset_copy<<<nfb, 256, 0, s>>>((const u8 *)reads.seq, reads.offsets, fb_list.p, nfb, sub_off.p, sub_seq.p);
+    MT_HIP(hipGetLastError());
+    const mt_seqs sub{(const char *)sub_seq.p, sub_off.p, nfb, sub_total};
+    containment_per_stage(ix, sub, hits, s);
+}
+
 }  // namespace mt
