@@ -72,6 +72,9 @@ def load(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with __graft_entry__.build() "
                            "(the classifier has no CPU fallback)")
+    # torch first: the library must bind to the HIP runtime torch loads, or the
+    # process ends up with two runtimes and the second sees no device
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     vp, u64, u32, i32 = C.c_void_p, C.c_uint64, C.c_uint32, C.c_int
     pp = C.POINTER(C.c_void_p)
