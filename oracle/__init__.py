@@ -62,6 +62,9 @@ def _declare(lib):
     lib.or_filter_pairs.restype = C.c_int
     lib.or_filter_pairs.argtypes = [C.c_void_p, u8p, u64p, C.c_uint64, u32p, u32p, i64p, u16p, C.c_uint64,
                                     u16p, u8p]
+    lib.or_filter_pairs_kind.restype = C.c_int
+    lib.or_filter_pairs_kind.argtypes = [C.c_void_p, u8p, u64p, C.c_uint64, u32p, u32p, i64p, u16p, C.c_uint64,
+                                         C.c_uint32, u16p, u8p]
     lib.or_containment.restype = C.c_int
     lib.or_containment.argtypes = [C.c_void_p, u8p, u64p, C.c_uint64, u64p]
     lib.or_select_genomes.restype = C.c_int64
@@ -175,7 +178,8 @@ class Index:
         out["unmapped"] = int(unm[0])
         return out
 
-    def filter_pairs(self, reads, pair_read, pair_genome, pair_diag, pair_E):
+    def filter_pairs(self, reads, pair_read, pair_genome, pair_diag, pair_E, kind: int = 0):
+        """Filter of kind 0 (obstacle walk), 1 (Hamming) or 2 (base counting) over pairs."""
         seq = np.ascontiguousarray(reads.seq, dtype=np.uint8)
         offs = np.ascontiguousarray(reads.offsets, dtype=np.uint64)
         pr = np.ascontiguousarray(pair_read, dtype=np.uint32)
@@ -185,9 +189,9 @@ class Index:
         n = len(pr)
         ap = np.zeros(n, np.uint16)
         ac = np.zeros(n, np.uint8)
-        rc = self.lib.or_filter_pairs(self.h, _p(seq, C.c_uint8), _p(offs, C.c_uint64), len(offs) - 1,
-                                      _p(pr, C.c_uint32), _p(pg, C.c_uint32), _p(pd, C.c_int64),
-                                      _p(pe, C.c_uint16), n, _p(ap, C.c_uint16), _p(ac, C.c_uint8))
+        rc = self.lib.or_filter_pairs_kind(self.h, _p(seq, C.c_uint8), _p(offs, C.c_uint64), len(offs) - 1,
+                                           _p(pr, C.c_uint32), _p(pg, C.c_uint32), _p(pd, C.c_int64),
+                                           _p(pe, C.c_uint16), n, kind, _p(ap, C.c_uint16), _p(ac, C.c_uint8))
         if rc != 0:
             raise ValueError("oracle filter_pairs rejected its input")
         return ap, ac

@@ -55,6 +55,16 @@
  *       genome g is kept iff hits[g] / M exceeds the cutoff num / den
  *       (strictly: "above" / "surpasses"), decided exactly as
  *       hits[g] * den > M * num; M = 0 keeps no genome.
+ *   O11 Hamming-distance filter (Table 1; the simplest pigeonhole method): the
+ *       number of columns j in [0, m) where Q[j] and reference position
+ *       diag + j differ under O1 (row 0 of the O6 band alone), saturated at
+ *       E + 1; accept iff <= E.
+ *   O12 base-counting filter (the frequency comparison of the Table 1
+ *       discussion): with n_Q(c) and n_W(c) the counts of base c in {A, C,
+ *       G, T} in the read and in the reference window [diag, diag + m)
+ *       (N and positions outside the genome count as no base), the value is
+ *       ceil(sum_c |n_Q(c) - n_W(c)| / 2), saturated at E + 1; accept iff
+ *       <= E.  It never exceeds the Hamming distance of O11.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -517,15 +527,40 @@ void or_result_copy(const or_result *r, uint64_t *cand_offsets, uint8_t *read_ac
     *unmapped = r->unmapped;
 }
 
-/*
- * The filter alone over explicit pairs (pair_read indexes the reads).  Used to
- * check a filter kernel on pair lists.  Returns OR_EINVAL on a bad byte or an
- * out-of-range genome / read index.
- */
-int or_filter_pairs(const or_index *ix, const uint8_t *seq, const uint64_t *offsets, uint64_t n_reads,
-                    const uint32_t *pair_read, const uint32_t *pair_genome, const int64_t *pair_diag,
-                    const uint16_t *pair_E, uint64_t n_pairs, uint16_t *approx_out, uint8_t *accept_out)
+/* O11: mismatching columns of row 0, saturated at E + 1. */
+static int hamming_codes(const uint8_t *q, int64_t m, const uint8_t *gcode, int64_t glen, int64_t diag, int E)
 {
+    int64_t c = 0;
+    for (int64_t j = 0; j < m; j++) c += obstacle(q[j], gcode, glen, diag + j);
+    return c < E + 1 ? (int)c : E + 1;
+}
+
+/* O12: half the L1 distance of the base counts, rounded up, saturated at E + 1. */
+static int base_count_codes(const uint8_t *q, int64_t m, const uint8_t *gcode, int64_t glen, int64_t diag, int E)
+{
+    int64_t nq[4] = {0, 0, 0, 0}, nw[4] = {0, 0, 0, 0};
+    for (int64_t j = 0; j < m; j++) {
+        if (q[j] < 4) nq[q[j]]++;
+        int64_t p = diag + j;
+        if (p >= 0 && p < glen && gcode[p] < 4) nw[gcode[p]]++;
+    }
+    int64_t l1 = 0;
+    for (int c = 0; c < 4; c++) l1 += nq[c] > nw[c] ? nq[c] - nw[c] : nw[c] - nq[c];
+    int64_t v = (l1 + 1) / 2;
+    return v < E + 1 ? (int)v : E + 1;
+}
+
+/*
+ * One filter of kind 0 (O6 obstacle walk), 1 (O11 Hamming) or 2 (O12 base
+ * counting) over explicit pairs, as or_filter_pairs.  Returns OR_EINVAL on a
+ * bad byte, an out-of-range index or an unknown kind.
+ */
+int or_filter_pairs_kind(const or_index *ix, const uint8_t *seq, const uint64_t *offsets, uint64_t n_reads,
+                         const uint32_t *pair_read, const uint32_t *pair_genome, const int64_t *pair_diag,
+                         const uint16_t *pair_E, uint64_t n_pairs, uint32_t kind, uint16_t *approx_out,
+                         uint8_t *accept_out)
+{
+    if (kind > 2) return OR_EINVAL;
     for (uint64_t p = 0; p < n_pairs; p++) {
         if (pair_read[p] >= n_reads || pair_genome[p] >= ix->n_genomes) return OR_EINVAL;
         uint64_t r = pair_read[p];
@@ -533,12 +568,24 @@ int or_filter_pairs(const or_index *ix, const uint8_t *seq, const uint64_t *offs
         uint8_t *q = malloc((size_t)(m > 0 ? m : 1));
         if (encode(seq + offsets[r], m, q) != OR_OK) { free(q); return OR_EINVAL; }
         uint32_t g = pair_genome[p];
-        int a = approx_codes(q, m, ix->gcode[g], ix->glen[g], pair_diag[p], pair_E[p]);
+        int E = pair_E[p], a;
+        if (kind == 1) a = hamming_codes(q, m, ix->gcode[g], ix->glen[g], pair_diag[p], E);
+        else if (kind == 2) a = base_count_codes(q, m, ix->gcode[g], ix->glen[g], pair_diag[p], E);
+        else a = approx_codes(q, m, ix->gcode[g], ix->glen[g], pair_diag[p], E);
         approx_out[p] = (uint16_t)a;
-        accept_out[p] = (uint8_t)(a <= pair_E[p]);
+        accept_out[p] = (uint8_t)(a <= E);
         free(q);
     }
     return OR_OK;
+}
+
+/* The obstacle filter alone over explicit pairs (pair_read indexes the reads). */
+int or_filter_pairs(const or_index *ix, const uint8_t *seq, const uint64_t *offsets, uint64_t n_reads,
+                    const uint32_t *pair_read, const uint32_t *pair_genome, const int64_t *pair_diag,
+                    const uint16_t *pair_E, uint64_t n_pairs, uint16_t *approx_out, uint8_t *accept_out)
+{
+    return or_filter_pairs_kind(ix, seq, offsets, n_reads, pair_read, pair_genome, pair_diag, pair_E, n_pairs, 0,
+                                approx_out, accept_out);
 }
 
 /* ----------------------------------------- stage 1 containment search ---- */

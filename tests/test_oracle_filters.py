@@ -1,0 +1,106 @@
+"""Pins of the oracle's alternative filters on one pair stream (Table 1's
+Hamming-distance filter and the base-counting comparison).
+
+* brute force from the definitions, on strings, with N and windows that run
+  past either end of the genome;
+* order: obstacle count <= Hamming distance and base count <= Hamming distance
+  (each saturated at E + 1): the greedy walk may use any row of the band, the
+  Hamming distance only row 0, and one mismatching column changes the base
+  counts by at most two;
+* special cases: Hamming 0 iff the read occurs exactly at the diagonal; base
+  count 0 for a window that is a rearrangement of the read.
+"""
+import random
+from collections import Counter
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+
+def _ref_at(ref, p):
+    return ref[p] if 0 <= p < len(ref) else None
+
+
+def _hamming(q, ref, diag, E):
+    c = sum(1 for j, b in enumerate(q) if b == "N" or _ref_at(ref, diag + j) in (None, "N")
+            or _ref_at(ref, diag + j) != b)
+    return min(c, E + 1)
+
+
+def _base_count(q, ref, diag, E):
+    nq = Counter(b for b in q if b != "N")
+    nw = Counter(x for x in (_ref_at(ref, diag + j) for j in range(len(q))) if x not in (None, "N"))
+    l1 = sum(abs(nq[c] - nw[c]) for c in "ACGT")
+    return min((l1 + 1) // 2, E + 1)
+
+
+def _pairs(rnd, n):
+    genomes = ["".join(rnd.choice("ACGTN" if rnd.random() < 0.05 else "ACGT") for _ in range(rnd.randint(1, 300)))
+               for _ in range(3)]
+    reads, pr, pg, pd, pe = [], [], [], [], []
+    for i in range(n):
+        g = rnd.randrange(3)
+        m = rnd.randint(0, 120)
+        d = rnd.randint(-40, len(genomes[g]) + 10)
+        src = genomes[g][max(d, 0):max(d, 0) + m]
+        r = [c if rnd.random() > 0.08 else rnd.choice("ACGTN") for c in src] + \
+            [rnd.choice("ACGT") for _ in range(m - len(src))]
+        if rnd.random() < 0.3:
+            rnd.shuffle(r)
+        reads.append("".join(r))
+        pr.append(i)
+        pg.append(g)
+        pd.append(d)
+        pe.append(rnd.choice([0, 1, 3, 7, 20, 200]))
+    return genomes, reads, np.array(pr, np.uint32), np.array(pg, np.uint32), np.array(pd, np.int64), \
+        np.array(pe, np.uint16)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_hamming_and_base_count_match_brute_force(seed):
+    rnd = random.Random(seed)
+    genomes, reads, pr, pg, pd, pe = _pairs(rnd, 300)
+    ix = oracle.Index(synth.SeqSet.from_list(genomes), 5, 3)
+    rs = synth.SeqSet.from_list(reads)
+    hd, hacc = ix.filter_pairs(rs, pr, pg, pd, pe, kind=1)
+    bc, bacc = ix.filter_pairs(rs, pr, pg, pd, pe, kind=2)
+    for i in range(len(pr)):
+        q, ref, d, E = reads[i], genomes[pg[i]], int(pd[i]), int(pe[i])
+        assert hd[i] == _hamming(q, ref, d, E), i
+        assert bc[i] == _base_count(q, ref, d, E), i
+    assert np.array_equal(hacc, (hd <= pe).astype(np.uint8)) and np.array_equal(bacc, (bc <= pe).astype(np.uint8))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_filter_order_obstacles_below_hamming_base_count_below_hamming(seed):
+    rnd = random.Random(50 + seed)
+    genomes, reads, pr, pg, pd, pe = _pairs(rnd, 400)
+    ix = oracle.Index(synth.SeqSet.from_list(genomes), 5, 3)
+    rs = synth.SeqSet.from_list(reads)
+    ob, _ = ix.filter_pairs(rs, pr, pg, pd, pe, kind=0)
+    hd, _ = ix.filter_pairs(rs, pr, pg, pd, pe, kind=1)
+    bc, _ = ix.filter_pairs(rs, pr, pg, pd, pe, kind=2)
+    assert (ob <= hd).all() and (bc <= hd).all()
+    assert (ob < hd).any() and (bc < hd).any()  # the bounds are not all tight
+
+
+def test_special_cases():
+    g = "ACGTTGCAAGGCTTACCGATGCAGTAAC"
+    ix = oracle.Index(synth.SeqSet.from_list([g]), 5, 3)
+    exact, shuffled = g[4:20], "".join(sorted(g[4:20]))
+    rs = synth.SeqSet.from_list([exact, shuffled, "ACGNACGT"])
+    pr = np.array([0, 1, 2, 0], np.uint32)
+    pg = np.zeros(4, np.uint32)
+    pd = np.array([4, 4, 0, 5], np.int64)
+    pe = np.full(4, 30, np.uint16)
+    hd, _ = ix.filter_pairs(rs, pr, pg, pd, pe, kind=1)
+    bc, _ = ix.filter_pairs(rs, pr, pg, pd, pe, kind=2)
+    assert hd[0] == 0 and bc[0] == 0          # exact occurrence
+    assert hd[1] > 0 and bc[1] == 0           # a rearrangement of the window
+    assert hd[2] >= 1                         # N never matches
+    assert hd[3] > 0                          # shifted by one
+    with pytest.raises(ValueError):
+        ix.filter_pairs(rs, pr, pg, pd, pe, kind=3)

@@ -12,7 +12,8 @@ import oracle
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "oracle.c")
-PIN_FILES = [os.path.join(ROOT, "tests", f) for f in ("test_oracle_pins.py", "test_oracle_containment.py")]
+PIN_FILES = [os.path.join(ROOT, "tests", f)
+             for f in ("test_oracle_pins.py", "test_oracle_containment.py", "test_oracle_filters.py")]
 
 # (name, original text, planted mistake); each original occurs exactly once.
 MUTANTS = [
@@ -57,6 +58,12 @@ MUTANTS = [
     ("selection not strict", "> (unsigned __int128)M * num) selected", ">= (unsigned __int128)M * num) selected"),
     ("selection in 64 bits", "if ((unsigned __int128)hits[g] * den > (unsigned __int128)M * num)",
      "if (hits[g] * den > M * num)"),
+    ("hamming off row 0", "for (int64_t j = 0; j < m; j++) c += obstacle(q[j], gcode, glen, diag + j);",
+     "for (int64_t j = 0; j < m; j++) c += obstacle(q[j], gcode, glen, diag + j + 1);"),
+    ("base count rounds down", "int64_t v = (l1 + 1) / 2;", "int64_t v = l1 / 2;"),
+    ("base count counts outside", "if (p >= 0 && p < glen && gcode[p] < 4) nw[gcode[p]]++;",
+     "if (p >= 0 && p < glen && gcode[p] < 4) nw[gcode[p]]++; else nw[0]++;"),
+    ("filter kinds swapped", "if (kind == 1) a = hamming_codes(", "if (kind == 2) a = hamming_codes("),
 ]
 
 
