@@ -461,6 +461,32 @@ def main() -> int:
                        "genomes": int(hits.numel()), "kept_at_1e-4": int(sel.numel()), "max_hits": mx}
         log(f"[bench] containment: {json.dumps(containment)}")
 
+    # Table 1's filter choice on the batch's own pair stream (its candidates).
+    filters = None
+    if args.workload == "batched" and hasattr(mt, "MT_FILTER_HAMMING"):
+        r = ix.classify(dreads, **q)
+        h = r.to_host()
+        r.free()
+        co = np.asarray(h["cand_offsets"], dtype=np.int64)
+        pr = np.repeat(np.arange(len(co) - 1, dtype=np.int64), np.diff(co)).astype(np.int32)
+        pe = np.asarray(h["read_E"], dtype=np.uint16)[pr]
+        dev = [torch.from_numpy(x).cuda() for x in (pr, np.asarray(h["genome"]).view(np.int32),
+                                                    np.asarray(h["diag"], dtype=np.int64), pe.view(np.int16))]
+        filters = {}
+        for name, kind in (("obstacle", mt.MT_FILTER_OBSTACLE), ("hamming", mt.MT_FILTER_HAMMING),
+                           ("base_count", mt.MT_FILTER_BASE_COUNT)):
+            ix.filter_pairs(dreads, *dev, kind=kind)  # warm
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(5):
+                _, acc = ix.filter_pairs(dreads, *dev, kind=kind)
+            torch.cuda.synchronize()
+            f_ms = (time.perf_counter() - t) * 1000.0 / 5
+            filters[name] = {"ms": round(f_ms, 3), "pairs_per_s": round(len(pr) / (f_ms / 1000.0), 1),
+                             "accepted": round(float(acc.float().mean().item()), 4)}
+        filters["pairs"] = int(len(pr))
+        log(f"[bench] filters on the pair stream (mt_filter_pairs_kind, incl. read packing): {json.dumps(filters)}")
+
     serving = None
     if pool is not None:
         serving = serving_bench(mt, ix, pool, seconds=args.serve_seconds, n_streams=args.serve_streams,
@@ -494,6 +520,7 @@ def main() -> int:
         "filter_tuning": tune,
         "cpu_baseline": cpu,
         "containment": containment,
+        "filters": filters,
         "serving": serving,
     }
     print(json.dumps(out), flush=True)

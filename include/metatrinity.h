@@ -209,6 +209,25 @@ int mt_filter_pairs(const mt_index *index, const mt_seqs *reads, const uint32_t 
                     uint64_t n_pairs, uint16_t *approx_out, uint8_t *accept_out, void *stream);
 
 /*
+ * Other filters of Table 1 on the same pair stream, the runtime/accuracy knob
+ * of the filter choice (same arguments and errors as mt_filter_pairs, plus
+ * MT_EINVAL for an unknown kind):
+ *   MT_FILTER_OBSTACLE    the obstacle walk over the 2E+1 band rows (as
+ *                         mt_filter_pairs);
+ *   MT_FILTER_HAMMING     the Hamming distance: mismatching columns of the
+ *                         diagonal itself (row 0 alone), N and positions
+ *                         outside the genome mismatching;
+ *   MT_FILTER_BASE_COUNT  base counting: ceil(sum over A, C, G, T of |count in
+ *                         the read - count in reference [diag, diag + m)| / 2),
+ *                         a lower bound of the Hamming distance.
+ * Each value saturates at E + 1; accept is value <= E.
+ */
+enum { MT_FILTER_OBSTACLE = 0, MT_FILTER_HAMMING = 1, MT_FILTER_BASE_COUNT = 2 };
+int mt_filter_pairs_kind(const mt_index *index, const mt_seqs *reads, const uint32_t *pair_read,
+                         const uint32_t *pair_genome, const int64_t *pair_diag, const uint16_t *pair_E,
+                         uint64_t n_pairs, uint32_t kind, uint16_t *approx_out, uint8_t *accept_out, void *stream);
+
+/*
  * Containment search (Fig. 1 steps 1a-1c; section "Containment Search"): the
  * seed-hit count of every genome of the index over the whole read set -- one
  * hit per (read minimizer, occurrence of its k-mer among the genome's

@@ -13,8 +13,8 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import _abi
-from ._abi import (MT_E_CEIL_PERMILLE, MT_E_FIXED, MT_E_FLOOR_PERMILLE, MT_MODE_FUSED,  # noqa: F401
-                   MT_MODE_FUSED_GRAPH, MT_MODE_PER_STAGE, MT_OK)
+from ._abi import (MT_E_CEIL_PERMILLE, MT_E_FIXED, MT_E_FLOOR_PERMILLE, MT_FILTER_BASE_COUNT,  # noqa: F401
+                   MT_FILTER_HAMMING, MT_FILTER_OBSTACLE, MT_MODE_FUSED, MT_MODE_FUSED_GRAPH, MT_MODE_PER_STAGE, MT_OK)
 
 __all__ = ["MTError", "DeviceSeqs", "Index", "Result", "Server", "to_device", "mt_set_timing", "last_timings",
            "tune_info", "tune_set", "tune_reset", "tune_save", "tune_load", "select_genomes"]
@@ -305,16 +305,18 @@ class Index:
         _check(self.lib.mt_autotune(self.h, C.byref(q), C.byref(reads.abi()), reps, _stream_ptr(stream)), self.lib)
         return tune_info()
 
-    def filter_pairs(self, reads: DeviceSeqs, pair_read, pair_genome, pair_diag, pair_E, stream=None):
+    def filter_pairs(self, reads: DeviceSeqs, pair_read, pair_genome, pair_diag, pair_E, stream=None,
+                     kind: int = 0):
         """Device tensors in (uint32/int32 read and genome, int64 diag, int16/uint16 E); returns
-        device tensors (approx int16 holding uint16 bits, accept uint8)."""
+        device tensors (approx int16 holding uint16 bits, accept uint8).  kind: MT_FILTER_OBSTACLE
+        (the band walk), MT_FILTER_HAMMING or MT_FILTER_BASE_COUNT."""
         torch = _torch()
         n = int(pair_read.numel())
         approx = torch.empty(max(n, 1), dtype=torch.int16, device=pair_read.device)
         accept = torch.empty(max(n, 1), dtype=torch.uint8, device=pair_read.device)
-        rc = self.lib.mt_filter_pairs(self.h, C.byref(reads.abi()), pair_read.data_ptr(), pair_genome.data_ptr(),
-                                      pair_diag.data_ptr(), pair_E.data_ptr(), n, approx.data_ptr(),
-                                      accept.data_ptr(), _stream_ptr(stream))
+        rc = self.lib.mt_filter_pairs_kind(self.h, C.byref(reads.abi()), pair_read.data_ptr(),
+                                           pair_genome.data_ptr(), pair_diag.data_ptr(), pair_E.data_ptr(), n, kind,
+                                           approx.data_ptr(), accept.data_ptr(), _stream_ptr(stream))
         _check(rc, self.lib)
         return approx[:n], accept[:n]
 

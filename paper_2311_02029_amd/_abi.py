@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmetatrin
 MT_OK, MT_EINVAL, MT_ENOMEM, MT_EDEVICE, MT_EAGAIN, MT_ETIMEDOUT, MT_ECANCELED, MT_EINTERNAL = 0, -1, -2, -3, -4, -5, -6, -7
 MT_E_FIXED, MT_E_CEIL_PERMILLE, MT_E_FLOOR_PERMILLE = 0, 1, 2
 MT_MODE_PER_STAGE, MT_MODE_FUSED, MT_MODE_FUSED_GRAPH = 0, 1, 2
+MT_FILTER_OBSTACLE, MT_FILTER_HAMMING, MT_FILTER_BASE_COUNT = 0, 1, 2
 
 # Every function the header declares; a test checks the library exports them.
 ABI_FUNCTIONS = (
@@ -21,7 +22,7 @@ ABI_FUNCTIONS = (
     "mt_filter_pairs", "mt_trim", "mt_last_error", "mt_abi_version", "mt_last_stats", "mt_server_create",
     "mt_server_submit", "mt_server_wait", "mt_server_destroy", "mt_result_on_host", "mt_result_times",
     "mt_tune_buckets", "mt_tune_info", "mt_tune_set", "mt_tune_reset", "mt_autotune", "mt_tune_save",
-    "mt_tune_load", "mt_containment", "mt_select_genomes",
+    "mt_tune_load", "mt_containment", "mt_select_genomes", "mt_filter_pairs_kind",
 )
 
 
@@ -108,6 +109,7 @@ def load(path: str = LIB_PATH):
         "mt_tune_save": (i32, [C.c_char_p]),
         "mt_tune_load": (i32, [C.c_char_p]),
         "mt_containment": (i32, [vp, C.POINTER(mt_seqs), vp, vp]),
+        "mt_filter_pairs_kind": (i32, [vp, C.POINTER(mt_seqs), vp, vp, vp, vp, u64, u32, vp, vp, vp]),
         "mt_select_genomes": (i32, [vp, u64, u64, u64, vp, C.POINTER(u64), C.POINTER(u64), vp]),
     }
     for name, (res, args) in sig.items():

@@ -777,15 +777,20 @@ extern "C" int mt_result_free(mt_result *res) {
     return MT_OK;
 }
 
-extern "C" int mt_filter_pairs(const mt_index *index, const mt_seqs *reads, const uint32_t *pair_read,
-                               const uint32_t *pair_genome, const int64_t *pair_diag, const uint16_t *pair_E,
-                               uint64_t n_pairs, uint16_t *approx_out, uint8_t *accept_out, void *stream) {
+extern "C" int mt_filter_pairs_kind(const mt_index *index, const mt_seqs *reads, const uint32_t *pair_read,
+                                    const uint32_t *pair_genome, const int64_t *pair_diag, const uint16_t *pair_E,
+                                    uint64_t n_pairs, uint32_t kind, uint16_t *approx_out, uint8_t *accept_out,
+                                    void *stream) {
     if (!index || !reads) {
         mt::set_last_error("mt_filter_pairs: null argument");
         return MT_EINVAL;
     }
     if (n_pairs && (!pair_read || !pair_genome || !pair_diag || !pair_E || !approx_out || !accept_out)) {
         mt::set_last_error("mt_filter_pairs: null pair array");
+        return MT_EINVAL;
+    }
+    if (kind > MT_FILTER_BASE_COUNT) {
+        mt::set_last_error("mt_filter_pairs: unknown filter kind");
         return MT_EINVAL;
     }
     hipStream_t s = (hipStream_t)stream;
@@ -814,9 +819,19 @@ extern "C" int mt_filter_pairs(const mt_index *index, const mt_seqs *reads, cons
         fa.approx = approx_out;
         fa.accept = accept_out;
         fa.flags = rb.flags.p;
-        mt::launch_filter(fa, n_pairs, 0, s);
+        if (kind == MT_FILTER_OBSTACLE)
+            mt::launch_filter(fa, n_pairs, 0, s);
+        else
+            mt::launch_filter_simple(fa, n_pairs, kind, s);
         mt::u32 f = 0;
         mt::read_back(s, rb.flags.p, &f, sizeof f);
         mt::check_flags(f);
     });
+}
+
+extern "C" int mt_filter_pairs(const mt_index *index, const mt_seqs *reads, const uint32_t *pair_read,
+                               const uint32_t *pair_genome, const int64_t *pair_diag, const uint16_t *pair_E,
+                               uint64_t n_pairs, uint16_t *approx_out, uint8_t *accept_out, void *stream) {
+    return mt_filter_pairs_kind(index, reads, pair_read, pair_genome, pair_diag, pair_E, n_pairs, MT_FILTER_OBSTACLE,
+                                approx_out, accept_out, stream);
 }

@@ -399,6 +399,70 @@ static void bucket_pairs(const FilterArgs &a, u64 n_cap, DBuf<u32> &idx, u32 hc[
     MT_HIP(hipStreamSynchronize(s));  // hb lives on this host stack frame
 }
 
+// Table 1's single-row and base-frequency filters on explicit pairs, one
+// thread per pair over the read's 64-base words.  Kind 1 (Hamming distance)
+// counts the mismatch bits of row 0 of the band, the diagonal alone; kind 2
+// (base counting) compares the counts of A, C, G and T in the read and in the
+// reference window [diag, diag + m) (N and positions outside the genome are no
+// base) and reports ceil(L1 / 2).  Both saturate at E + 1.
+template <int KIND>
+__global__ void k_filter_simple(FilterArgs a, u64 n) {
+    const u64 p = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    u32 r, g, err;
+    int E;
+    bool ok;
+    pair_fields(a, p, r, g, E, ok, err);
+    if (!ok) {
+        atomicOr(a.flags, err);
+        a.approx[p] = 0xFFFF;
+        a.accept[p] = 0;
+        return;
+    }
+    const int m = read_len(a, r);
+    const u64 rb = a.read_blk[r];
+    const GenomeMeta gm = a.meta[g];
+    const u64x2 *rl = a.ref_lohi + gm.blk;
+    const u64 *rn = a.ref_nb + gm.blk;
+    const i64 L = (i64)gm.len;
+    const bool hn = meta_has_n(gm);
+    const i64 diag = a.pair_diag[p];
+    int c = 0;
+    int dA = 0, dC = 0, dG = 0, dT = 0;  // read count minus window count per base
+    for (int w0 = 0; w0 < m; w0 += 64) {
+        const u64x2 q = a.read_lohi[rb + (u64)(w0 >> 6)];
+        const u64 qn = a.read_nb[rb + (u64)(w0 >> 6)];
+        const int left = m - w0;
+        const u64 vm = left >= 64 ? ~0ull : (1ull << left) - 1;
+        const Bits64 wb = fetch_ref(rl, rn, L, hn, diag + w0);
+        if constexpr (KIND == 1) {
+            c += __popcll(((q.lo ^ wb.lo) | (q.hi ^ wb.hi) | qn | wb.nb) & vm);
+            if (c > E) break;
+        } else {
+            const u64 qv = ~qn & vm, wv = ~wb.nb & vm;
+            dA += __popcll(~q.lo & ~q.hi & qv) - __popcll(~wb.lo & ~wb.hi & wv);
+            dC += __popcll(q.lo & ~q.hi & qv) - __popcll(wb.lo & ~wb.hi & wv);
+            dG += __popcll(~q.lo & q.hi & qv) - __popcll(~wb.lo & wb.hi & wv);
+            dT += __popcll(q.lo & q.hi & qv) - __popcll(wb.lo & wb.hi & wv);
+        }
+    }
+    if constexpr (KIND == 2) c = (abs(dA) + abs(dC) + abs(dG) + abs(dT) + 1) / 2;
+    const int v = c < E + 1 ? c : E + 1;
+    a.approx[p] = (u16)v;
+    a.accept[p] = v <= E;
+}
+
+void launch_filter_simple(const FilterArgs &a, u64 n, u32 kind, hipStream_t s) {
+    if (n == 0) return;
+    if (kind == MT_FILTER_HAMMING)
+        k_filter_simple<1><<<grid_for(n, 256), 256, 0, s>>>(a, n);
+    else if (kind == MT_FILTER_BASE_COUNT)
+        k_filter_simple<2><<<grid_for(n, 256), 256, 0, s>>>(a, n);
+    else
+        throw Error(MT_EINVAL, "unknown filter kind");
+    MT_HIP(hipGetLastError());
+}
+
 void launch_filter(const FilterArgs &a, u64 n_cap, u32 /*max_E*/, hipStream_t s) {
     if (n_cap == 0) return;
     DBuf<u32> idx;

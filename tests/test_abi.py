@@ -88,3 +88,4 @@ def test_null_arguments_are_errors_not_crashes():
     # no genomes: nothing to launch, nothing kept
     assert lib.mt_select_genomes(None, 0, 1, 10_000, None, C.byref(ns), C.byref(mx), None) == _abi.MT_OK
     assert ns.value == 0 and mx.value == 0
+    assert lib.mt_filter_pairs_kind(None, None, None, None, None, None, 0, 0, None, None, None) == _abi.MT_EINVAL

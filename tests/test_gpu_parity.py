@@ -321,6 +321,38 @@ def test_filter_pairs_against_oracle(mt):
     assert (oap <= pe).mean() > 0.3 and (oap > pe).mean() > 0.05
 
 
+@pytest.mark.parametrize("kind", [1, 2])
+def test_filter_kinds_against_oracle(mt, kind):
+    """The Hamming and base-counting filters on one pair stream: reads of 0 to
+    3,000 bases with N, genomes with N, windows past either genome end."""
+    import torch
+    rnd = np.random.default_rng(31 + kind)
+    gen = synth.make_genomes(rnd, 4, 20_000, (0.3, 0.7))
+    lens = np.concatenate([rnd.integers(0, 300, 400), rnd.integers(300, 3000, 40), [64, 128, 192, 256, 65]])
+    reads, origin = synth.make_reads(rnd, gen, lens, 0.01, 0.005)
+    reads = synth.inject_n(rnd, reads, 0.003)
+    ga = gen.ascii()
+    seq = ga.seq.copy()
+    seq[rnd.random(len(seq)) < 0.0005] = ord("N")
+    ga = synth.SeqSet(seq=seq, offsets=ga.offsets)
+    n = 5000
+    pr = rnd.integers(0, reads.n, n).astype(np.uint32)
+    pg = np.where(rnd.random(n) < 0.8, origin[pr, 0], rnd.integers(0, 4, n)).astype(np.uint32)
+    pdg = (origin[pr, 1] + rnd.integers(-3, 4, n)).astype(np.int64)
+    pdg[:100] = rnd.integers(-400, 20, 100)
+    pdg[100:200] = 20_000 - lens[pr[100:200]] + rnd.integers(-20, 400, 100)
+    pe = rnd.choice([0, 1, 3, 7, 15, 40, 300], n).astype(np.uint16)
+    ix = mt.Index(ga, 15, 10)
+    ap, ac = ix.filter_pairs(mt.to_device(reads), torch.from_numpy(pr.view(np.int32)).cuda(),
+                             torch.from_numpy(pg.view(np.int32)).cuda(), torch.from_numpy(pdg).cuda(),
+                             torch.from_numpy(pe.view(np.int16)).cuda(), kind=kind)
+    ap = ap.cpu().numpy().view(np.uint16)
+    oap, oac = oracle.Index(ga, 15, 10).filter_pairs(reads, pr, pg, pdg, pe, kind=kind)
+    assert np.array_equal(ap, oap), np.flatnonzero(ap != oap)[:10]
+    assert np.array_equal(ac.cpu().numpy(), oac)
+    assert (oap <= pe).mean() > 0.2 and (oap > pe).mean() > 0.05
+
+
 def test_filter_long_pairs_at_edges_and_n(mt):
     """Long-read pairs (E > 31, LDS kernel) whose window runs past either end
     of the genome, lies in a genome with N bases, or lies inside a genome
