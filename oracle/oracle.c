@@ -65,6 +65,13 @@
  *       (N and positions outside the genome count as no base), the value is
  *       ceil(sum_c |n_Q(c) - n_W(c)| / 2), saturated at E + 1; accept iff
  *       <= E.  It never exceeds the Hamming distance of O11.
+ *   O13 q-gram filter (Table 1's q-gram family, q = 5): with the read's
+ *       m - 4 q-grams and the reference window [diag - E, diag + m + E) of
+ *       the band, shared = the size of the multiset intersection of the
+ *       q-grams free of N and of positions outside the genome, missing =
+ *       (m - 4) - shared, value = ceil(missing / 5) (0 for m < 5), saturated
+ *       at E + 1; accept iff <= E.  Each edit destroys at most q of the read's
+ *       q-grams, so the value never exceeds the banded edit distance.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -550,17 +557,48 @@ static int base_count_codes(const uint8_t *q, int64_t m, const uint8_t *gcode, i
     return v < E + 1 ? (int)v : E + 1;
 }
 
+#define QGRAM_Q 5
+
+/* O13: the q-gram lower bound over the band's window, saturated at E + 1. */
+static int qgram_codes(const uint8_t *q, int64_t m, const uint8_t *gcode, int64_t glen, int64_t diag, int E)
+{
+    if (m < QGRAM_Q) return 0;
+    uint32_t *cw = calloc(1u << (2 * QGRAM_Q), sizeof *cw);
+    for (int64_t p = diag - E; p + QGRAM_Q <= diag + m + E; p++) {
+        int v = 0, ok = 1;
+        for (int t = 0; t < QGRAM_Q && ok; t++) {
+            int64_t x = p + t;
+            if (x < 0 || x >= glen || gcode[x] == 4) ok = 0;
+            else v = v * 4 + gcode[x];
+        }
+        if (ok) cw[v]++;
+    }
+    int64_t shared = 0;
+    for (int64_t j = 0; j + QGRAM_Q <= m; j++) {
+        int v = 0, ok = 1;
+        for (int t = 0; t < QGRAM_Q && ok; t++) {
+            if (q[j + t] == 4) ok = 0;
+            else v = v * 4 + q[j + t];
+        }
+        if (ok && cw[v] > 0) { cw[v]--; shared++; }
+    }
+    free(cw);
+    int64_t missing = (m - QGRAM_Q + 1) - shared;
+    int64_t val = (missing + QGRAM_Q - 1) / QGRAM_Q;
+    return val < E + 1 ? (int)val : E + 1;
+}
+
 /*
- * One filter of kind 0 (O6 obstacle walk), 1 (O11 Hamming) or 2 (O12 base
- * counting) over explicit pairs, as or_filter_pairs.  Returns OR_EINVAL on a
- * bad byte, an out-of-range index or an unknown kind.
+ * One filter of kind 0 (O6 obstacle walk), 1 (O11 Hamming), 2 (O12 base
+ * counting) or 3 (O13 q-grams) over explicit pairs, as or_filter_pairs.
+ * Returns OR_EINVAL on a bad byte, an out-of-range index or an unknown kind.
  */
 int or_filter_pairs_kind(const or_index *ix, const uint8_t *seq, const uint64_t *offsets, uint64_t n_reads,
                          const uint32_t *pair_read, const uint32_t *pair_genome, const int64_t *pair_diag,
                          const uint16_t *pair_E, uint64_t n_pairs, uint32_t kind, uint16_t *approx_out,
                          uint8_t *accept_out)
 {
-    if (kind > 2) return OR_EINVAL;
+    if (kind > 3) return OR_EINVAL;
     for (uint64_t p = 0; p < n_pairs; p++) {
         if (pair_read[p] >= n_reads || pair_genome[p] >= ix->n_genomes) return OR_EINVAL;
         uint64_t r = pair_read[p];
@@ -571,6 +609,7 @@ int or_filter_pairs_kind(const or_index *ix, const uint8_t *seq, const uint64_t 
         int E = pair_E[p], a;
         if (kind == 1) a = hamming_codes(q, m, ix->gcode[g], ix->glen[g], pair_diag[p], E);
         else if (kind == 2) a = base_count_codes(q, m, ix->gcode[g], ix->glen[g], pair_diag[p], E);
+        else if (kind == 3) a = qgram_codes(q, m, ix->gcode[g], ix->glen[g], pair_diag[p], E);
         else a = approx_codes(q, m, ix->gcode[g], ix->glen[g], pair_diag[p], E);
         approx_out[p] = (uint16_t)a;
         accept_out[p] = (uint8_t)(a <= E);

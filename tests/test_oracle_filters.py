@@ -1,5 +1,5 @@
 """Pins of the oracle's alternative filters on one pair stream (Table 1's
-Hamming-distance filter and the base-counting comparison).
+Hamming-distance filter, the base-counting comparison and the q-gram filter).
 
 * brute force from the definitions, on strings, with N and windows that run
   past either end of the genome;
@@ -8,7 +8,9 @@ Hamming-distance filter and the base-counting comparison).
   Hamming distance only row 0, and one mismatching column changes the base
   counts by at most two;
 * special cases: Hamming 0 iff the read occurs exactly at the diagonal; base
-  count 0 for a window that is a rearrangement of the read.
+  count 0 for a window that is a rearrangement of the read;
+* the q-gram lemma: the q-gram value never exceeds the semi-global banded edit
+  distance (an independent DP) nor the Hamming distance.
 """
 import random
 from collections import Counter
@@ -18,6 +20,9 @@ import pytest
 
 import oracle
 import synth
+from test_oracle_pins import semi_global_banded
+
+Q = 5
 
 
 def _ref_at(ref, p):
@@ -35,6 +40,19 @@ def _base_count(q, ref, diag, E):
     nw = Counter(x for x in (_ref_at(ref, diag + j) for j in range(len(q))) if x not in (None, "N"))
     l1 = sum(abs(nq[c] - nw[c]) for c in "ACGT")
     return min((l1 + 1) // 2, E + 1)
+
+
+def _qgram(q, ref, diag, E):
+    m = len(q)
+    if m < Q:
+        return 0
+    win = [_ref_at(ref, p) for p in range(diag - E, diag + m + E)]
+    cw = Counter("".join(win[i:i + Q]) for i in range(len(win) - Q + 1)
+                 if all(x not in (None, "N") for x in win[i:i + Q]))
+    cq = Counter(q[j:j + Q] for j in range(m - Q + 1) if "N" not in q[j:j + Q])
+    shared = sum(min(c, cw[g]) for g, c in cq.items())
+    missing = (m - Q + 1) - shared
+    return min(-(-missing // Q), E + 1)
 
 
 def _pairs(rnd, n):
@@ -67,10 +85,12 @@ def test_hamming_and_base_count_match_brute_force(seed):
     rs = synth.SeqSet.from_list(reads)
     hd, hacc = ix.filter_pairs(rs, pr, pg, pd, pe, kind=1)
     bc, bacc = ix.filter_pairs(rs, pr, pg, pd, pe, kind=2)
+    qg, _ = ix.filter_pairs(rs, pr, pg, pd, pe, kind=3)
     for i in range(len(pr)):
         q, ref, d, E = reads[i], genomes[pg[i]], int(pd[i]), int(pe[i])
         assert hd[i] == _hamming(q, ref, d, E), i
         assert bc[i] == _base_count(q, ref, d, E), i
+        assert qg[i] == _qgram(q, ref, d, E), i
     assert np.array_equal(hacc, (hd <= pe).astype(np.uint8)) and np.array_equal(bacc, (bc <= pe).astype(np.uint8))
 
 
@@ -85,6 +105,24 @@ def test_filter_order_obstacles_below_hamming_base_count_below_hamming(seed):
     bc, _ = ix.filter_pairs(rs, pr, pg, pd, pe, kind=2)
     assert (ob <= hd).all() and (bc <= hd).all()
     assert (ob < hd).any() and (bc < hd).any()  # the bounds are not all tight
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_qgram_lemma(seed):
+    rnd = random.Random(80 + seed)
+    genomes, reads, pr, pg, pd, pe = _pairs(rnd, 250)
+    pe = np.array([rnd.choice([1, 2, 4, 8]) for _ in pe], np.uint16)  # small bands keep the DP fast
+    ix = oracle.Index(synth.SeqSet.from_list(genomes), 5, 3)
+    rs = synth.SeqSet.from_list(reads)
+    qg, _ = ix.filter_pairs(rs, pr, pg, pd, pe, kind=3)
+    hd, _ = ix.filter_pairs(rs, pr, pg, pd, pe, kind=1)
+    tight = 0
+    for i in range(len(pr)):
+        E = int(pe[i])
+        sg = semi_global_banded(reads[i], genomes[pg[i]], int(pd[i]), E)
+        assert qg[i] <= min(sg, E + 1), i
+        tight += qg[i] == min(sg, E + 1) and sg > 0
+    assert (qg <= hd).all() and tight > 5
 
 
 def test_special_cases():
@@ -102,5 +140,9 @@ def test_special_cases():
     assert hd[1] > 0 and bc[1] == 0           # a rearrangement of the window
     assert hd[2] >= 1                         # N never matches
     assert hd[3] > 0                          # shifted by one
+    qg, _ = ix.filter_pairs(rs, pr, pg, pd, pe, kind=3)
+    assert qg[0] == 0 and qg[3] == 0          # shifted by one: inside the band, every q-gram is shared
+    short = synth.SeqSet.from_list(["ACG"])
+    assert ix.filter_pairs(short, [0], [0], [0], [0], kind=3)[0][0] == 0  # fewer than q bases
     with pytest.raises(ValueError):
-        ix.filter_pairs(rs, pr, pg, pd, pe, kind=3)
+        ix.filter_pairs(rs, pr, pg, pd, pe, kind=4)

@@ -64,6 +64,10 @@ MUTANTS = [
     ("base count counts outside", "if (p >= 0 && p < glen && gcode[p] < 4) nw[gcode[p]]++;",
      "if (p >= 0 && p < glen && gcode[p] < 4) nw[gcode[p]]++; else nw[0]++;"),
     ("filter kinds swapped", "if (kind == 1) a = hamming_codes(", "if (kind == 2) a = hamming_codes("),
+    ("q-gram window without the band", "for (int64_t p = diag - E; p + QGRAM_Q <= diag + m + E; p++) {",
+     "for (int64_t p = diag; p + QGRAM_Q <= diag + m; p++) {"),
+    ("q-gram rounds down", "int64_t val = (missing + QGRAM_Q - 1) / QGRAM_Q;", "int64_t val = missing / QGRAM_Q;"),
+    ("q-gram window N shared", "if (x < 0 || x >= glen || gcode[x] == 4) ok = 0;", "if (x < 0 || x >= glen) ok = 0;"),
 ]
 
 
