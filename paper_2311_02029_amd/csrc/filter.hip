@@ -452,12 +452,86 @@ __global__ void k_filter_simple(FilterArgs a, u64 n) {
     a.accept[p] = v <= E;
 }
 
+// Table 1's q-gram filter (q = QG_Q), one wavefront per pair: the q-grams of
+// the reference window [diag - E, diag + m + E) free of N and of positions
+// outside the genome are counted in a per-wavefront LDS table of 4^q
+// counters; each of the read's q-grams then takes one count (an atomic
+// decrement that found it positive), so the number taken is the size of the
+// multiset intersection.  Value: ceil((m - q + 1 - shared) / q), 0 for m < q,
+// saturated at E + 1.
+constexpr int QG_Q = 5;
+constexpr int QG_WPB = 4;
+
+__global__ __launch_bounds__(64 * QG_WPB) void k_filter_qgram(FilterArgs a, u64 n) {
+    __shared__ int cnt_all[QG_WPB][1 << (2 * QG_Q)];
+    const int lane = threadIdx.x & 63;
+    const u32 wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    int *cnt = cnt_all[wid];
+    constexpr u64 QMASK = (1ull << QG_Q) - 1;
+    for (u64 p = (u64)blockIdx.x * QG_WPB + wid; p < n; p += (u64)gridDim.x * QG_WPB) {
+        u32 r, g, err;
+        int E;
+        bool ok;
+        pair_fields(a, p, r, g, E, ok, err);
+        if (!ok) {
+            if (lane == 0) {
+                atomicOr(a.flags, err);
+                a.approx[p] = 0xFFFF;
+                a.accept[p] = 0;
+            }
+            continue;
+        }
+        const int m = read_len(a, r);
+        if (m < QG_Q) {
+            if (lane == 0) {
+                a.approx[p] = 0;
+                a.accept[p] = 1;
+            }
+            continue;
+        }
+        for (int i = lane; i < (1 << (2 * QG_Q)); i += 64) cnt[i] = 0;
+        lds_wave_sync();
+        const GenomeMeta gm = a.meta[g];
+        const u64x2 *rl = a.ref_lohi + gm.blk;
+        const u64 *rn = a.ref_nb + gm.blk;
+        const i64 L = (i64)gm.len;
+        const bool hn = meta_has_n(gm);
+        const i64 w0 = a.pair_diag[p] - E;
+        const i64 nwq = (i64)m + 2 * (i64)E - QG_Q + 1;
+        for (i64 t = lane; t < nwq; t += 64) {
+            const Bits64 b = fetch_ref(rl, rn, L, hn, w0 + t);
+            if ((b.nb & QMASK) == 0) atomicAdd(&cnt[kmer_value(b.lo, b.hi, QG_Q)], 1);
+        }
+        lds_wave_sync();
+        const u64 rb = a.read_blk[r];
+        int shared = 0;
+        for (int j0 = 0; j0 <= m - QG_Q; j0 += 64) {
+            const int j = j0 + lane;
+            bool took = false;
+            if (j <= m - QG_Q) {
+                const Bits64 b = fetch_planes(a.read_lohi + rb, a.read_nb + rb, j);
+                if ((b.nb & QMASK) == 0) took = atomicSub(&cnt[kmer_value(b.lo, b.hi, QG_Q)], 1) > 0;
+            }
+            shared += __popcll(__ballot(took));
+        }
+        const int missing = m - QG_Q + 1 - shared;
+        const int v = min((missing + QG_Q - 1) / QG_Q, E + 1);
+        if (lane == 0) {
+            a.approx[p] = (u16)v;
+            a.accept[p] = v <= E;
+        }
+        lds_wave_sync();  // the next pair clears the counters
+    }
+}
+
 void launch_filter_simple(const FilterArgs &a, u64 n, u32 kind, hipStream_t s) {
     if (n == 0) return;
     if (kind == MT_FILTER_HAMMING)
         k_filter_simple<1><<<grid_for(n, 256), 256, 0, s>>>(a, n);
     else if (kind == MT_FILTER_BASE_COUNT)
         k_filter_simple<2><<<grid_for(n, 256), 256, 0, s>>>(a, n);
+    else if (kind == MT_FILTER_QGRAM)
+        k_filter_qgram<<<(unsigned)std::min<u64>(grid_for(n, QG_WPB), 65536), 64 * QG_WPB, 0, s>>>(a, n);
     else
         throw Error(MT_EINVAL, "unknown filter kind");
     MT_HIP(hipGetLastError());

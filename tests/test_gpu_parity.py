@@ -172,7 +172,8 @@ def _hits_per_read(genomes, reads, k, w):
 def test_hit_count_tiers(mt, mode, top_n):
     """Reads whose seed-hit totals fall in every counting tier of the
     per-stage kernels (one wavefront holding one or four hits per lane, one
-    block sorting in LDS, the global-memory sort), many with tied counts."""
+    block counting in an LDS hash table, the global-memory sort), many with
+    tied counts."""
     rnd = random.Random(91)
     unit = "".join(rnd.choice("ACGT") for _ in range(40))
     rand = "".join(rnd.choice("ACGT") for _ in range(12_000))
@@ -321,10 +322,10 @@ def test_filter_pairs_against_oracle(mt):
     assert (oap <= pe).mean() > 0.3 and (oap > pe).mean() > 0.05
 
 
-@pytest.mark.parametrize("kind", [1, 2])
+@pytest.mark.parametrize("kind", [1, 2, 3])
 def test_filter_kinds_against_oracle(mt, kind):
-    """The Hamming and base-counting filters on one pair stream: reads of 0 to
-    3,000 bases with N, genomes with N, windows past either genome end."""
+    """The Hamming, base-counting and q-gram filters on one pair stream: reads
+    of 0 to 3,000 bases with N, genomes with N, windows past either genome end."""
     import torch
     rnd = np.random.default_rng(31 + kind)
     gen = synth.make_genomes(rnd, 4, 20_000, (0.3, 0.7))
