@@ -72,6 +72,11 @@
  *       (m - 4) - shared, value = ceil(missing / 5) (0 for m < 5), saturated
  *       at E + 1; accept iff <= E.  Each edit destroys at most q of the read's
  *       q-grams, so the value never exceeds the banded edit distance.
+ *   O14 shifted Hamming distance (SHD, Table 1): for each row d in [-E, E] the
+ *       mismatch mask H_d[j] = O6 obstacle at column j; in each mask a run of
+ *       one or two zeros with a one on both sides (inside [0, m)) becomes
+ *       ones; the value is the number of columns where every amended mask is
+ *       one, saturated at E + 1; accept iff <= E.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -588,17 +593,41 @@ static int qgram_codes(const uint8_t *q, int64_t m, const uint8_t *gcode, int64_
     return val < E + 1 ? (int)val : E + 1;
 }
 
+/* O14: ones of the AND over the band of the amended mismatch masks. */
+static int shd_codes(const uint8_t *q, int64_t m, const uint8_t *gcode, int64_t glen, int64_t diag, int E)
+{
+    if (m == 0) return 0;
+    uint8_t *F = malloc((size_t)m), *H = malloc((size_t)m);
+    memset(F, 1, (size_t)m);
+    for (int64_t d = -(int64_t)E; d <= E; d++) {
+        for (int64_t j = 0; j < m; j++) H[j] = (uint8_t)obstacle(q[j], gcode, glen, diag + j + d);
+        for (int64_t j = 0; j < m;) {
+            if (H[j]) { F[j] &= 1; j++; continue; }
+            int64_t k = j;
+            while (k < m && !H[k]) k++;              /* zeros [j, k) */
+            int amend = j > 0 && k < m && k - j <= 2;  /* a short match between two mismatches */
+            for (int64_t t = j; t < k; t++) F[t] &= (uint8_t)amend;
+            j = k;
+        }
+    }
+    int64_t c = 0;
+    for (int64_t j = 0; j < m; j++) c += F[j];
+    free(F); free(H);
+    return c < E + 1 ? (int)c : E + 1;
+}
+
 /*
  * One filter of kind 0 (O6 obstacle walk), 1 (O11 Hamming), 2 (O12 base
- * counting) or 3 (O13 q-grams) over explicit pairs, as or_filter_pairs.
- * Returns OR_EINVAL on a bad byte, an out-of-range index or an unknown kind.
+ * counting), 3 (O13 q-grams) or 4 (O14 SHD) over explicit pairs, as
+ * or_filter_pairs.  Returns OR_EINVAL on a bad byte, an out-of-range index or
+ * an unknown kind.
  */
 int or_filter_pairs_kind(const or_index *ix, const uint8_t *seq, const uint64_t *offsets, uint64_t n_reads,
                          const uint32_t *pair_read, const uint32_t *pair_genome, const int64_t *pair_diag,
                          const uint16_t *pair_E, uint64_t n_pairs, uint32_t kind, uint16_t *approx_out,
                          uint8_t *accept_out)
 {
-    if (kind > 3) return OR_EINVAL;
+    if (kind > 4) return OR_EINVAL;
     for (uint64_t p = 0; p < n_pairs; p++) {
         if (pair_read[p] >= n_reads || pair_genome[p] >= ix->n_genomes) return OR_EINVAL;
         uint64_t r = pair_read[p];
@@ -610,6 +639,7 @@ int or_filter_pairs_kind(const or_index *ix, const uint8_t *seq, const uint64_t 
         if (kind == 1) a = hamming_codes(q, m, ix->gcode[g], ix->glen[g], pair_diag[p], E);
         else if (kind == 2) a = base_count_codes(q, m, ix->gcode[g], ix->glen[g], pair_diag[p], E);
         else if (kind == 3) a = qgram_codes(q, m, ix->gcode[g], ix->glen[g], pair_diag[p], E);
+        else if (kind == 4) a = shd_codes(q, m, ix->gcode[g], ix->glen[g], pair_diag[p], E);
         else a = approx_codes(q, m, ix->gcode[g], ix->glen[g], pair_diag[p], E);
         approx_out[p] = (uint16_t)a;
         accept_out[p] = (uint8_t)(a <= E);

@@ -1,5 +1,6 @@
 """Pins of the oracle's alternative filters on one pair stream (Table 1's
-Hamming-distance filter, the base-counting comparison and the q-gram filter).
+Hamming-distance filter, the base-counting comparison, the q-gram filter and
+the shifted Hamming distance).
 
 * brute force from the definitions, on strings, with N and windows that run
   past either end of the genome;
@@ -10,9 +11,13 @@ Hamming-distance filter, the base-counting comparison and the q-gram filter).
 * special cases: Hamming 0 iff the read occurs exactly at the diagonal; base
   count 0 for a window that is a rearrangement of the read;
 * the q-gram lemma: the q-gram value never exceeds the semi-global banded edit
-  distance (an independent DP) nor the Hamming distance.
+  distance (an independent DP) nor the Hamming distance;
+* shifted Hamming distance: brute force with the masks written as strings and
+  the short-match amendment as a regular expression; 0 whenever the read
+  occurs exactly on any diagonal of the band.
 """
 import random
+import re
 from collections import Counter
 
 import numpy as np
@@ -55,6 +60,20 @@ def _qgram(q, ref, diag, E):
     return min(-(-missing // Q), E + 1)
 
 
+def _shd(q, ref, diag, E):
+    m = len(q)
+    if m == 0:
+        return 0
+    final = [1] * m
+    for d in range(-E, E + 1):
+        mask = "".join("1" if (b == "N" or _ref_at(ref, diag + d + j) in (None, "N")
+                               or _ref_at(ref, diag + d + j) != b) else "0" for j, b in enumerate(q))
+        # one or two zeros between two ones become ones (lookarounds keep the flanking ones)
+        amended = re.sub(r"(?<=1)0{1,2}(?=1)", lambda mo: "1" * len(mo.group(0)), mask)
+        final = [f & int(c) for f, c in zip(final, amended)]
+    return min(sum(final), E + 1)
+
+
 def _pairs(rnd, n):
     genomes = ["".join(rnd.choice("ACGTN" if rnd.random() < 0.05 else "ACGT") for _ in range(rnd.randint(1, 300)))
                for _ in range(3)]
@@ -86,11 +105,15 @@ def test_hamming_and_base_count_match_brute_force(seed):
     hd, hacc = ix.filter_pairs(rs, pr, pg, pd, pe, kind=1)
     bc, bacc = ix.filter_pairs(rs, pr, pg, pd, pe, kind=2)
     qg, _ = ix.filter_pairs(rs, pr, pg, pd, pe, kind=3)
+    small = pe <= 20  # the brute-force SHD is quadratic in E
+    sh, _ = ix.filter_pairs(rs, pr[small], pg[small], pd[small], pe[small], kind=4)
     for i in range(len(pr)):
         q, ref, d, E = reads[i], genomes[pg[i]], int(pd[i]), int(pe[i])
         assert hd[i] == _hamming(q, ref, d, E), i
         assert bc[i] == _base_count(q, ref, d, E), i
         assert qg[i] == _qgram(q, ref, d, E), i
+    for s_i, i in enumerate(np.flatnonzero(small)):
+        assert sh[s_i] == _shd(reads[i], genomes[pg[i]], int(pd[i]), int(pe[i])), i
     assert np.array_equal(hacc, (hd <= pe).astype(np.uint8)) and np.array_equal(bacc, (bc <= pe).astype(np.uint8))
 
 
@@ -142,7 +165,10 @@ def test_special_cases():
     assert hd[3] > 0                          # shifted by one
     qg, _ = ix.filter_pairs(rs, pr, pg, pd, pe, kind=3)
     assert qg[0] == 0 and qg[3] == 0          # shifted by one: inside the band, every q-gram is shared
+    sh, _ = ix.filter_pairs(rs, pr, pg, pd, np.full(4, 3, np.uint16), kind=4)
+    assert sh[0] == 0 and sh[3] == 0          # exact on the diagonal, and one row off it
+    assert sh[2] >= 1                         # the N column is a one in every mask
     short = synth.SeqSet.from_list(["ACG"])
     assert ix.filter_pairs(short, [0], [0], [0], [0], kind=3)[0][0] == 0  # fewer than q bases
     with pytest.raises(ValueError):
-        ix.filter_pairs(rs, pr, pg, pd, pe, kind=4)
+        ix.filter_pairs(rs, pr, pg, pd, pe, kind=5)

@@ -68,6 +68,9 @@ MUTANTS = [
      "for (int64_t p = diag; p + QGRAM_Q <= diag + m; p++) {"),
     ("q-gram rounds down", "int64_t val = (missing + QGRAM_Q - 1) / QGRAM_Q;", "int64_t val = missing / QGRAM_Q;"),
     ("q-gram window N shared", "if (x < 0 || x >= glen || gcode[x] == 4) ok = 0;", "if (x < 0 || x >= glen) ok = 0;"),
+    ("SHD amends runs of three", "int amend = j > 0 && k < m && k - j <= 2;", "int amend = j > 0 && k < m && k - j <= 3;"),
+    ("SHD amends at the read ends", "int amend = j > 0 && k < m && k - j <= 2;", "int amend = k - j <= 2;"),
+    ("SHD band one row short", "for (int64_t d = -(int64_t)E; d <= E; d++) {", "for (int64_t d = -(int64_t)E; d < E; d++) {"),
 ]
 
 
