@@ -474,7 +474,8 @@ def main() -> int:
                                                     np.asarray(h["diag"], dtype=np.int64), pe.view(np.int16))]
         filters = {}
         for name, kind in (("obstacle", mt.MT_FILTER_OBSTACLE), ("hamming", mt.MT_FILTER_HAMMING),
-                           ("base_count", mt.MT_FILTER_BASE_COUNT), ("qgram", mt.MT_FILTER_QGRAM)):
+                           ("base_count", mt.MT_FILTER_BASE_COUNT), ("qgram", mt.MT_FILTER_QGRAM),
+                           ("shd", mt.MT_FILTER_SHD)):
             ix.filter_pairs(dreads, *dev, kind=kind)  # warm
             torch.cuda.synchronize()
             t = time.perf_counter()

@@ -224,10 +224,14 @@ int mt_filter_pairs(const mt_index *index, const mt_seqs *reads, const uint32_t 
  *                         the multiset intersection of the read's q-grams and
  *                         those of reference [diag - E, diag + m + E) (q-grams
  *                         with N or outside positions excluded); 0 for m < 5;
- *                         a lower bound of the banded edit distance.
+ *                         a lower bound of the banded edit distance;
+ *   MT_FILTER_SHD         shifted Hamming distance: the band rows' mismatch
+ *                         masks, each with runs of one or two zeros between
+ *                         ones set, ANDed; the value counts the ones.
  * Each value saturates at E + 1; accept is value <= E.
  */
-enum { MT_FILTER_OBSTACLE = 0, MT_FILTER_HAMMING = 1, MT_FILTER_BASE_COUNT = 2, MT_FILTER_QGRAM = 3 };
+enum { MT_FILTER_OBSTACLE = 0, MT_FILTER_HAMMING = 1, MT_FILTER_BASE_COUNT = 2, MT_FILTER_QGRAM = 3,
+       MT_FILTER_SHD = 4 };
 int mt_filter_pairs_kind(const mt_index *index, const mt_seqs *reads, const uint32_t *pair_read,
                          const uint32_t *pair_genome, const int64_t *pair_diag, const uint16_t *pair_E,
                          uint64_t n_pairs, uint32_t kind, uint16_t *approx_out, uint8_t *accept_out, void *stream);

@@ -14,7 +14,7 @@ import numpy as np
 
 from . import _abi
 from ._abi import (MT_E_CEIL_PERMILLE, MT_E_FIXED, MT_E_FLOOR_PERMILLE, MT_FILTER_BASE_COUNT,  # noqa: F401
-                   MT_FILTER_HAMMING, MT_FILTER_OBSTACLE, MT_FILTER_QGRAM, MT_MODE_FUSED, MT_MODE_FUSED_GRAPH,
+                   MT_FILTER_HAMMING, MT_FILTER_OBSTACLE, MT_FILTER_QGRAM, MT_FILTER_SHD, MT_MODE_FUSED, MT_MODE_FUSED_GRAPH,
                    MT_MODE_PER_STAGE, MT_OK)
 
 __all__ = ["MTError", "DeviceSeqs", "Index", "Result", "Server", "to_device", "mt_set_timing", "last_timings",
@@ -310,7 +310,7 @@ class Index:
                      kind: int = 0):
         """Device tensors in (uint32/int32 read and genome, int64 diag, int16/uint16 E); returns
         device tensors (approx int16 holding uint16 bits, accept uint8).  kind: MT_FILTER_OBSTACLE
-        (the band walk), MT_FILTER_HAMMING, MT_FILTER_BASE_COUNT or MT_FILTER_QGRAM."""
+        (the band walk), MT_FILTER_HAMMING, MT_FILTER_BASE_COUNT, MT_FILTER_QGRAM or MT_FILTER_SHD."""
         torch = _torch()
         n = int(pair_read.numel())
         approx = torch.empty(max(n, 1), dtype=torch.int16, device=pair_read.device)

@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmetatrin
 MT_OK, MT_EINVAL, MT_ENOMEM, MT_EDEVICE, MT_EAGAIN, MT_ETIMEDOUT, MT_ECANCELED, MT_EINTERNAL = 0, -1, -2, -3, -4, -5, -6, -7
 MT_E_FIXED, MT_E_CEIL_PERMILLE, MT_E_FLOOR_PERMILLE = 0, 1, 2
 MT_MODE_PER_STAGE, MT_MODE_FUSED, MT_MODE_FUSED_GRAPH = 0, 1, 2
-MT_FILTER_OBSTACLE, MT_FILTER_HAMMING, MT_FILTER_BASE_COUNT, MT_FILTER_QGRAM = 0, 1, 2, 3
+MT_FILTER_OBSTACLE, MT_FILTER_HAMMING, MT_FILTER_BASE_COUNT, MT_FILTER_QGRAM, MT_FILTER_SHD = 0, 1, 2, 3, 4
 
 # Every function the header declares; a test checks the library exports them.
 ABI_FUNCTIONS = (

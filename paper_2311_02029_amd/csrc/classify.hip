@@ -789,7 +789,7 @@ extern "C" int mt_filter_pairs_kind(const mt_index *index, const mt_seqs *reads,
         mt::set_last_error("mt_filter_pairs: null pair array");
         return MT_EINVAL;
     }
-    if (kind > MT_FILTER_QGRAM) {
+    if (kind > MT_FILTER_SHD) {
         mt::set_last_error("mt_filter_pairs: unknown filter kind");
         return MT_EINVAL;
     }

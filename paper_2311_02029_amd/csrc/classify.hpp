@@ -73,7 +73,7 @@ struct FilterArgs {
 // then each bucket runs the kernel shaped for it.
 void launch_filter(const FilterArgs &a, u64 n_cap, u32 max_E, hipStream_t s);
 // Pairs [0, n) (n_host) through the Hamming (MT_FILTER_HAMMING), base-counting
-// (MT_FILTER_BASE_COUNT) or q-gram (MT_FILTER_QGRAM) filter.
+// (MT_FILTER_BASE_COUNT), q-gram (MT_FILTER_QGRAM) or shifted Hamming (MT_FILTER_SHD) filter.
 void launch_filter_simple(const FilterArgs &a, u64 n, u32 kind, hipStream_t s);
 
 // Filter variants per bucket (see filter.hip) and their autotuner.

@@ -524,12 +524,95 @@ __global__ __launch_bounds__(64 * QG_WPB) void k_filter_qgram(FilterArgs a, u64 
     }
 }
 
+// Shifted Hamming distance (Table 1's SHD), one thread per pair.  Row d's
+// mismatch word w covers columns 64w .. 64w+63 (zero at columns >= m); in
+// each row, a run of one or two zeros with a one on both sides (inside the
+// read) becomes ones; the value is the number of columns where every amended
+// row is one, saturated at E + 1.
+__device__ inline u64 shd_word(const FilterArgs &a, u64 rb, int m, const u64x2 *rl, const u64 *rn, i64 L, bool hn,
+                               i64 diag, int d, int w) {
+    if (w < 0 || 64 * w >= m) return 0;
+    const u64x2 q = a.read_lohi[rb + (u64)w];
+    const u64 qn = a.read_nb[rb + (u64)w];
+    const Bits64 r = fetch_ref(rl, rn, L, hn, diag + d + 64 * (i64)w);
+    const int left = m - 64 * w;
+    const u64 vm = left >= 64 ? ~0ull : (1ull << left) - 1;
+    return ((q.lo ^ r.lo) | (q.hi ^ r.hi) | qn | r.nb) & vm;
+}
+
+// Word x of a row with its neighbours xp (columns before) and xn (after),
+// short zero runs between ones set.
+__device__ inline u64 shd_amend(u64 xp, u64 x, u64 xn) {
+    const u64 l1 = (x << 1) | (xp >> 63), l2 = (x << 2) | (xp >> 62);  // bit i: x[i - 1], x[i - 2]
+    const u64 r1 = (x >> 1) | (xn << 63), r2 = (x >> 2) | (xn << 62);  // bit i: x[i + 1], x[i + 2]
+    const u64 one = ~x & l1 & r1;            // 1 0 1
+    const u64 first = ~x & ~r1 & l1 & r2;    // 1 [0] 0 1
+    const u64 second = ~x & ~l1 & l2 & r1;   // 1 0 [0] 1
+    return x | one | first | second;
+}
+
+__global__ void k_filter_shd(FilterArgs a, u64 n) {
+    const u64 p = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    u32 r, g, err;
+    int E;
+    bool ok;
+    pair_fields(a, p, r, g, E, ok, err);
+    if (!ok) {
+        atomicOr(a.flags, err);
+        a.approx[p] = 0xFFFF;
+        a.accept[p] = 0;
+        return;
+    }
+    const int m = read_len(a, r);
+    const u64 rb = a.read_blk[r];
+    const GenomeMeta gm = a.meta[g];
+    const u64x2 *rl = a.ref_lohi + gm.blk;
+    const u64 *rn = a.ref_nb + gm.blk;
+    const i64 L = (i64)gm.len;
+    const bool hn = meta_has_n(gm);
+    const i64 diag = a.pair_diag[p];
+    int c = 0;
+    if (m <= 256) {  // the whole read in four words: rows outer, four accumulators
+        u64 acc[4];
+#pragma unroll
+        for (int w = 0; w < 4; w++) {
+            const int left = m - 64 * w;
+            acc[w] = left >= 64 ? ~0ull : left > 0 ? (1ull << left) - 1 : 0ull;
+        }
+        for (int d = -E; d <= E && (acc[0] | acc[1] | acc[2] | acc[3]); d++) {
+            u64 x[4];
+#pragma unroll
+            for (int w = 0; w < 4; w++) x[w] = shd_word(a, rb, m, rl, rn, L, hn, diag, d, w);
+#pragma unroll
+            for (int w = 0; w < 4; w++) acc[w] &= shd_amend(w ? x[w - 1] : 0ull, x[w], w < 3 ? x[w + 1] : 0ull);
+        }
+        c = __popcll(acc[0]) + __popcll(acc[1]) + __popcll(acc[2]) + __popcll(acc[3]);
+    } else {  // longer reads: words outer, each row word with its neighbours
+        const int nw = (m + 63) / 64;
+        for (int w = 0; w < nw && c <= E; w++) {
+            const int left = m - 64 * w;
+            u64 acc = left >= 64 ? ~0ull : (1ull << left) - 1;
+            for (int d = -E; d <= E && acc; d++)
+                acc &= shd_amend(shd_word(a, rb, m, rl, rn, L, hn, diag, d, w - 1),
+                                 shd_word(a, rb, m, rl, rn, L, hn, diag, d, w),
+                                 shd_word(a, rb, m, rl, rn, L, hn, diag, d, w + 1));
+            c += __popcll(acc);
+        }
+    }
+    const int v = c < E + 1 ? c : E + 1;
+    a.approx[p] = (u16)v;
+    a.accept[p] = v <= E;
+}
+
 void launch_filter_simple(const FilterArgs &a, u64 n, u32 kind, hipStream_t s) {
     if (n == 0) return;
     if (kind == MT_FILTER_HAMMING)
         k_filter_simple<1><<<grid_for(n, 256), 256, 0, s>>>(a, n);
     else if (kind == MT_FILTER_BASE_COUNT)
         k_filter_simple<2><<<grid_for(n, 256), 256, 0, s>>>(a, n);
+    else if (kind == MT_FILTER_SHD)
+        k_filter_shd<<<grid_for(n, 256), 256, 0, s>>>(a, n);
     else if (kind == MT_FILTER_QGRAM)
         k_filter_qgram<<<(unsigned)std::min<u64>(grid_for(n, QG_WPB), 65536), 64 * QG_WPB, 0, s>>>(a, n);
     else

@@ -322,10 +322,11 @@ def test_filter_pairs_against_oracle(mt):
     assert (oap <= pe).mean() > 0.3 and (oap > pe).mean() > 0.05
 
 
-@pytest.mark.parametrize("kind", [1, 2, 3])
+@pytest.mark.parametrize("kind", [1, 2, 3, 4])
 def test_filter_kinds_against_oracle(mt, kind):
-    """The Hamming, base-counting and q-gram filters on one pair stream: reads
-    of 0 to 3,000 bases with N, genomes with N, windows past either genome end."""
+    """The Hamming, base-counting, q-gram and shifted-Hamming filters on one
+    pair stream: reads of 0 to 3,000 bases with N, genomes with N, windows past
+    either genome end."""
     import torch
     rnd = np.random.default_rng(31 + kind)
     gen = synth.make_genomes(rnd, 4, 20_000, (0.3, 0.7))
