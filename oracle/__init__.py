@@ -50,6 +50,9 @@ def _declare(lib):
     lib.or_approx.argtypes = [u8p, C.c_int64, u8p, C.c_int64, C.c_int64, C.c_int]
     lib.or_read_E.restype = C.c_int
     lib.or_read_E.argtypes = [C.c_int64, C.c_uint32, C.c_uint32]
+    lib.or_classify_kind.restype = C.c_void_p
+    lib.or_classify_kind.argtypes = [C.c_void_p, u8p, u64p, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
+                                     C.c_uint32, C.c_uint32]
     lib.or_classify.restype = C.c_void_p
     lib.or_classify.argtypes = [C.c_void_p, u8p, u64p, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
                                 C.c_uint32]
@@ -154,12 +157,14 @@ class Index:
     def n_occ(self) -> int:
         return int(self.lib.or_index_n_occ(self.h))
 
-    def classify(self, reads, min_hits=3, top_n=3, e_mode=0, e_value=7) -> dict:
+    def classify(self, reads, min_hits=3, top_n=3, e_mode=0, e_value=7, filter_kind=0) -> dict:
+        """Stage 2 and the step-3a counts; filter_kind 0 is the obstacle walk, 1-4 the
+        Hamming, base-counting, q-gram and shifted-Hamming filters."""
         seq = np.ascontiguousarray(reads.seq, dtype=np.uint8)
         offs = np.ascontiguousarray(reads.offsets, dtype=np.uint64)
         n = len(offs) - 1
-        r = self.lib.or_classify(self.h, _p(seq, C.c_uint8), _p(offs, C.c_uint64), n, min_hits, top_n,
-                                 e_mode, e_value)
+        r = self.lib.or_classify_kind(self.h, _p(seq, C.c_uint8), _p(offs, C.c_uint64), n, min_hits, top_n,
+                                      e_mode, e_value, filter_kind)
         if not r:
             raise ValueError("oracle classify rejected its input")
         nc = int(self.lib.or_result_n_cands(r))

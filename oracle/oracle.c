@@ -409,13 +409,33 @@ static void push_cand(or_result *r, const cand_t *c)
     r->n_cands++;
 }
 
+static int hamming_codes(const uint8_t *q, int64_t m, const uint8_t *gcode, int64_t glen, int64_t diag, int E);
+static int base_count_codes(const uint8_t *q, int64_t m, const uint8_t *gcode, int64_t glen, int64_t diag, int E);
+static int qgram_codes(const uint8_t *q, int64_t m, const uint8_t *gcode, int64_t glen, int64_t diag, int E);
+static int shd_codes(const uint8_t *q, int64_t m, const uint8_t *gcode, int64_t glen, int64_t diag, int E);
+
+/* The filter of kind 0 (O6 obstacle walk), 1 (O11 Hamming), 2 (O12 base
+ * counting), 3 (O13 q-grams) or 4 (O14 SHD) on one pair. */
+static int filter_codes(uint32_t kind, const uint8_t *q, int64_t m, const uint8_t *gcode, int64_t glen,
+                        int64_t diag, int E)
+{
+    switch (kind) {
+    case 1: return hamming_codes(q, m, gcode, glen, diag, E);
+    case 2: return base_count_codes(q, m, gcode, glen, diag, E);
+    case 3: return qgram_codes(q, m, gcode, glen, diag, E);
+    case 4: return shd_codes(q, m, gcode, glen, diag, E);
+    default: return approx_codes(q, m, gcode, glen, diag, E);
+    }
+}
+
 /*
  * Classifies reads (ASCII + offsets[n+1]).  Returns NULL on an invalid input
  * (bad byte, read longer than 65535, E above 65534).
  */
-or_result *or_classify(const or_index *ix, const uint8_t *seq, const uint64_t *offsets, uint64_t n,
-                       uint32_t min_hits, uint32_t top_n, uint32_t e_mode, uint32_t e_value)
+or_result *or_classify_kind(const or_index *ix, const uint8_t *seq, const uint64_t *offsets, uint64_t n,
+                            uint32_t min_hits, uint32_t top_n, uint32_t e_mode, uint32_t e_value, uint32_t kind)
 {
+    if (kind > 4) return NULL;
     or_result *res = calloc(1, sizeof *res);
     res->n_reads = n;
     res->cand_offsets = calloc(n + 1, sizeof *res->cand_offsets);
@@ -482,7 +502,7 @@ or_result *or_classify(const or_index *ix, const uint8_t *seq, const uint64_t *o
         for (int64_t c = 0; c < nc; c++) {
             push_cand(res, &cand[c]);
             uint32_t g = cand[c].genome;
-            int a = approx_codes(q, m, ix->gcode[g], ix->glen[g], cand[c].diag, E);
+            int a = filter_codes(kind, q, m, ix->gcode[g], ix->glen[g], cand[c].diag, E);
             res->approx[res->n_cands - 1] = (uint16_t)a;
             res->accept[res->n_cands - 1] = (uint8_t)(a <= E);
             if (a <= E && (best < 0 || a < best)) best = a;
@@ -515,6 +535,13 @@ or_result *or_classify(const or_index *ix, const uint8_t *seq, const uint64_t *o
     }
     free(taxon_seen);
     return res;
+}
+
+/* Classification with the obstacle filter (kind 0). */
+or_result *or_classify(const or_index *ix, const uint8_t *seq, const uint64_t *offsets, uint64_t n,
+                       uint32_t min_hits, uint32_t top_n, uint32_t e_mode, uint32_t e_value)
+{
+    return or_classify_kind(ix, seq, offsets, n, min_hits, top_n, e_mode, e_value, 0);
 }
 
 uint64_t or_result_n_cands(const or_result *r) { return r->n_cands; }
@@ -635,12 +662,8 @@ int or_filter_pairs_kind(const or_index *ix, const uint8_t *seq, const uint64_t 
         uint8_t *q = malloc((size_t)(m > 0 ? m : 1));
         if (encode(seq + offsets[r], m, q) != OR_OK) { free(q); return OR_EINVAL; }
         uint32_t g = pair_genome[p];
-        int E = pair_E[p], a;
-        if (kind == 1) a = hamming_codes(q, m, ix->gcode[g], ix->glen[g], pair_diag[p], E);
-        else if (kind == 2) a = base_count_codes(q, m, ix->gcode[g], ix->glen[g], pair_diag[p], E);
-        else if (kind == 3) a = qgram_codes(q, m, ix->gcode[g], ix->glen[g], pair_diag[p], E);
-        else if (kind == 4) a = shd_codes(q, m, ix->gcode[g], ix->glen[g], pair_diag[p], E);
-        else a = approx_codes(q, m, ix->gcode[g], ix->glen[g], pair_diag[p], E);
+        int E = pair_E[p];
+        int a = filter_codes(kind, q, m, ix->gcode[g], ix->glen[g], pair_diag[p], E);
         approx_out[p] = (uint16_t)a;
         accept_out[p] = (uint8_t)(a <= E);
         free(q);

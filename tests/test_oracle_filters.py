@@ -172,3 +172,22 @@ def test_special_cases():
     assert ix.filter_pairs(short, [0], [0], [0], [0], kind=3)[0][0] == 0  # fewer than q bases
     with pytest.raises(ValueError):
         ix.filter_pairs(rs, pr, pg, pd, pe, kind=5)
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2, 3, 4])
+def test_classification_uses_the_chosen_filter(kind):
+    """Classification with a filter kind: the candidates are those of the
+    obstacle run, and each one's value is that filter's value on the pair."""
+    rnd = np.random.default_rng(kind)
+    gen = synth.make_genomes(rnd, 4, 20_000, 0.5)
+    reads, _ = synth.make_reads(rnd, gen, rnd.integers(60, 250, 300), 0.02, 0.01)
+    ix = oracle.Index(gen.ascii(), 13, 7)
+    base = ix.classify(reads, 2, 3, 0, 6, filter_kind=0)
+    res = ix.classify(reads, 2, 3, 0, 6, filter_kind=kind)
+    for f in ("cand_offsets", "genome", "diag", "hits", "read_E"):
+        assert np.array_equal(res[f], base[f]), f
+    co = res["cand_offsets"].astype(np.int64)
+    pr = np.repeat(np.arange(reads.n), np.diff(co)).astype(np.uint32)
+    ap, ac = ix.filter_pairs(reads, pr, res["genome"], res["diag"], res["read_E"][pr], kind=kind)
+    assert np.array_equal(ap, res["approx"]) and np.array_equal(ac, res["accept"])
+    assert len(ap) > 200

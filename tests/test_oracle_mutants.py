@@ -63,7 +63,7 @@ MUTANTS = [
     ("base count rounds down", "int64_t v = (l1 + 1) / 2;", "int64_t v = l1 / 2;"),
     ("base count counts outside", "if (p >= 0 && p < glen && gcode[p] < 4) nw[gcode[p]]++;",
      "if (p >= 0 && p < glen && gcode[p] < 4) nw[gcode[p]]++; else nw[0]++;"),
-    ("filter kinds swapped", "if (kind == 1) a = hamming_codes(", "if (kind == 2) a = hamming_codes("),
+    ("filter kinds swapped", "case 1: return hamming_codes(", "case 1: return base_count_codes("),
     ("q-gram window without the band", "for (int64_t p = diag - E; p + QGRAM_Q <= diag + m + E; p++) {",
      "for (int64_t p = diag; p + QGRAM_Q <= diag + m; p++) {"),
     ("q-gram rounds down", "int64_t val = (missing + QGRAM_Q - 1) / QGRAM_Q;", "int64_t val = missing / QGRAM_Q;"),
