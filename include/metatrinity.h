@@ -102,7 +102,9 @@ typedef struct mt_query_params {
     uint32_t e_mode;     /* MT_E_* */
     uint32_t e_value;    /* E, or permille of the read length */
     uint32_t mode;       /* MT_MODE_* */
-    uint32_t reserved[3];/* must be 0 */
+    uint32_t filter;     /* MT_FILTER_* (0: the obstacle walk).  The other filters
+                            run in the per-stage form whatever the mode. */
+    uint32_t reserved[2];/* must be 0 */
 } mt_query_params;
 
 typedef struct mt_index_info {

@@ -282,8 +282,8 @@ class Index:
         return hits[:n]
 
     def classify(self, reads: DeviceSeqs, min_hits=3, top_n=3, e_mode=MT_E_FIXED, e_value=7,
-                 mode=MT_MODE_PER_STAGE, stream=None) -> Result:
-        q = _abi.mt_query_params(min_hits, top_n, e_mode, e_value, mode)
+                 mode=MT_MODE_PER_STAGE, stream=None, filter_kind=MT_FILTER_OBSTACLE) -> Result:
+        q = _abi.mt_query_params(min_hits, top_n, e_mode, e_value, mode, filter_kind)
         h = C.c_void_p()
         sp = _stream_ptr(stream)
         if mode == MT_MODE_FUSED_GRAPH and sp == 0:
@@ -352,10 +352,11 @@ class Server:
         _check(self.lib.mt_server_create(index.h, C.byref(p), C.byref(h)), self.lib)
         self.h = h.value
 
-    def submit(self, seqset, min_hits=3, top_n=3, e_mode=MT_E_FIXED, e_value=7) -> int:
+    def submit(self, seqset, min_hits=3, top_n=3, e_mode=MT_E_FIXED, e_value=7,
+               filter_kind=MT_FILTER_OBSTACLE) -> int:
         seq = np.ascontiguousarray(seqset.seq, dtype=np.uint8)
         offs = np.ascontiguousarray(seqset.offsets, dtype=np.uint64)
-        q = _abi.mt_query_params(min_hits, top_n, e_mode, e_value, MT_MODE_FUSED)
+        q = _abi.mt_query_params(min_hits, top_n, e_mode, e_value, MT_MODE_FUSED, filter_kind)
         rid = C.c_uint64()
         rc = self.lib.mt_server_submit(self.h, C.byref(q), seq.ctypes.data if len(seq) else None,
                                        offs.ctypes.data, len(offs) - 1, C.byref(rid))

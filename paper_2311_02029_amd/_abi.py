@@ -36,7 +36,7 @@ class mt_index_params(C.Structure):
 
 class mt_query_params(C.Structure):
     _fields_ = [("min_hits", C.c_uint32), ("top_n", C.c_uint32), ("e_mode", C.c_uint32), ("e_value", C.c_uint32),
-                ("mode", C.c_uint32), ("reserved", C.c_uint32 * 3)]
+                ("mode", C.c_uint32), ("filter", C.c_uint32), ("reserved", C.c_uint32 * 2)]
 
 
 class mt_index_info(C.Structure):

@@ -522,7 +522,8 @@ void validate_query(const mt_query_params &q) {
     MT_REQUIRE(q.e_mode <= MT_E_FLOOR_PERMILLE, "unknown e_mode");
     MT_REQUIRE(q.e_mode != MT_E_FIXED || q.e_value <= 65534, "E must be at most 65534");
     MT_REQUIRE(q.mode <= MT_MODE_FUSED_GRAPH, "unknown mode");
-    MT_REQUIRE(q.reserved[0] == 0 && q.reserved[1] == 0 && q.reserved[2] == 0, "reserved fields must be 0");
+    MT_REQUIRE(q.filter <= MT_FILTER_SHD, "unknown filter");
+    MT_REQUIRE(q.reserved[0] == 0 && q.reserved[1] == 0, "reserved fields must be 0");
 }
 
 void classify_per_stage(const mt_index &ix, const mt_query_params &q, const mt_seqs &reads, ReadBatch &rb,
@@ -618,7 +619,10 @@ void classify_per_stage(const mt_index &ix, const mt_query_params &q, const mt_s
     fa.approx = res.approx.p;
     fa.accept = res.accept.p;
     fa.flags = rb.flags.p;
-    launch_filter(fa, cap, max_E, s);
+    if (q.filter == MT_FILTER_OBSTACLE)
+        launch_filter(fa, cap, max_E, s);
+    else
+        launch_filter_simple(fa, cap, q.filter, s);
     tm.mark("filter");
     // reduce
     if (n) {
@@ -664,6 +668,23 @@ using mt::Error;
 
 using mt::guarded;
 
+namespace mt {
+
+void classify_staged(const mt_index &ix, const mt_query_params &q, const mt_seqs &reads, ReadBatch &rb,
+                     mt_result &res, Timer &tm, hipStream_t s) {
+    rb.prepare(reads, q.e_mode, q.e_value, s);
+    MT_HIP(hipMemcpyAsync(res.read_E.p, rb.read_E.p, (reads.n ? reads.n : 1) * sizeof(u16), hipMemcpyDeviceToDevice,
+                          s));
+    tm.mark("pack");
+    classify_per_stage(ix, q, reads, rb, res, tm, s);
+    u32 f = 0;
+    read_back(s, rb.flags.p, &f, sizeof f);
+    check_flags(f);
+    read_back(s, res.cand_off.p + reads.n, &res.n_cands, sizeof(u64));
+}
+
+}  // namespace mt
+
 extern "C" int mt_classify(const mt_index *index, const mt_query_params *params, const mt_seqs *reads,
                            void *stream, mt_result **out) {
     if (!index || !params || !reads || !out) {
@@ -685,19 +706,10 @@ extern "C" int mt_classify(const mt_index *index, const mt_query_params *params,
             tm.begin(s);
             mt::mt_result_init(*res, reads->n, index->n_taxa, s);
             mt::ReadBatch rb;
-            if (params->mode != MT_MODE_PER_STAGE) {
+            if (params->mode != MT_MODE_PER_STAGE)
                 mt::classify_fused(*index, *params, *reads, rb, *res, tm, s, params->mode == MT_MODE_FUSED_GRAPH);
-            } else {
-                rb.prepare(*reads, params->e_mode, params->e_value, s);
-                MT_HIP(hipMemcpyAsync(res->read_E.p, rb.read_E.p, (reads->n ? reads->n : 1) * sizeof(mt::u16),
-                                      hipMemcpyDeviceToDevice, s));
-                tm.mark("pack");
-                mt::classify_per_stage(*index, *params, *reads, rb, *res, tm, s);
-                mt::u32 f = 0;
-                mt::read_back(s, rb.flags.p, &f, sizeof f);
-                mt::check_flags(f);
-                mt::read_back(s, res->cand_off.p + reads->n, &res->n_cands, sizeof(mt::u64));
-            }
+            else
+                mt::classify_staged(*index, *params, *reads, rb, *res, tm, s);
             mt::last_stats().n_cands = res->n_cands;
         }
         tm.finish();

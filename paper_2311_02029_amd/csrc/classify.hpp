@@ -72,8 +72,9 @@ struct FilterArgs {
 // pairs are bucketed by their E (one synchronization to size the buckets),
 // then each bucket runs the kernel shaped for it.
 void launch_filter(const FilterArgs &a, u64 n_cap, u32 max_E, hipStream_t s);
-// Pairs [0, n) (n_host) through the Hamming (MT_FILTER_HAMMING), base-counting
-// (MT_FILTER_BASE_COUNT), q-gram (MT_FILTER_QGRAM) or shifted Hamming (MT_FILTER_SHD) filter.
+// Pairs [0, count) through the Hamming (MT_FILTER_HAMMING), base-counting
+// (MT_FILTER_BASE_COUNT), q-gram (MT_FILTER_QGRAM) or shifted Hamming (MT_FILTER_SHD)
+// filter; count = *n_dev if set, else n_host, at most n.
 void launch_filter_simple(const FilterArgs &a, u64 n, u32 kind, hipStream_t s);
 
 // Filter variants per bucket (see filter.hip) and their autotuner.
@@ -95,6 +96,10 @@ void classify_per_stage(const mt_index &ix, const mt_query_params &q, const mt_s
 void containment(const mt_index &ix, const mt_seqs &reads, u64 *hits, hipStream_t s);
 void containment_per_stage(const mt_index &ix, const mt_seqs &reads, u64 *hits, hipStream_t s);
 
+// The per-stage form end to end: packing and validation, classify_per_stage,
+// flags, candidate count.
+void classify_staged(const mt_index &ix, const mt_query_params &q, const mt_seqs &reads, ReadBatch &rb,
+                     mt_result &res, Timer &tm, hipStream_t s);
 void classify_fused(const mt_index &ix, const mt_query_params &q, const mt_seqs &reads, ReadBatch &rb,
                     mt_result &res, Timer &tm, hipStream_t s, bool graph);
 void launch_max_u16(const u16 *v, u64 n, u32 *out, hipStream_t s);

@@ -399,6 +399,13 @@ static void bucket_pairs(const FilterArgs &a, u64 n_cap, DBuf<u32> &idx, u32 hc[
     MT_HIP(hipStreamSynchronize(s));  // hb lives on this host stack frame
 }
 
+// Pairs to filter: the device count when there is one (bounded by the
+// launch's capacity), else the host count.
+__device__ inline u64 pair_count(const FilterArgs &a, u64 n_cap) {
+    const u64 n = a.n_dev ? *a.n_dev : a.n_host;
+    return n < n_cap ? n : n_cap;
+}
+
 // Table 1's single-row and base-frequency filters on explicit pairs, one
 // thread per pair over the read's 64-base words.  Kind 1 (Hamming distance)
 // counts the mismatch bits of row 0 of the band, the diagonal alone; kind 2
@@ -406,9 +413,9 @@ static void bucket_pairs(const FilterArgs &a, u64 n_cap, DBuf<u32> &idx, u32 hc[
 // reference window [diag, diag + m) (N and positions outside the genome are no
 // base) and reports ceil(L1 / 2).  Both saturate at E + 1.
 template <int KIND>
-__global__ void k_filter_simple(FilterArgs a, u64 n) {
+__global__ void k_filter_simple(FilterArgs a, u64 n_cap) {
     const u64 p = (u64)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
+    if (p >= pair_count(a, n_cap)) return;
     u32 r, g, err;
     int E;
     bool ok;
@@ -462,7 +469,8 @@ __global__ void k_filter_simple(FilterArgs a, u64 n) {
 constexpr int QG_Q = 5;
 constexpr int QG_WPB = 4;
 
-__global__ __launch_bounds__(64 * QG_WPB) void k_filter_qgram(FilterArgs a, u64 n) {
+__global__ __launch_bounds__(64 * QG_WPB) void k_filter_qgram(FilterArgs a, u64 n_cap) {
+    const u64 n = pair_count(a, n_cap);
     __shared__ int cnt_all[QG_WPB][1 << (2 * QG_Q)];
     const int lane = threadIdx.x & 63;
     const u32 wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -551,9 +559,9 @@ __device__ inline u64 shd_amend(u64 xp, u64 x, u64 xn) {
     return x | one | first | second;
 }
 
-__global__ void k_filter_shd(FilterArgs a, u64 n) {
+__global__ void k_filter_shd(FilterArgs a, u64 n_cap) {
     const u64 p = (u64)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
+    if (p >= pair_count(a, n_cap)) return;
     u32 r, g, err;
     int E;
     bool ok;
@@ -606,7 +614,7 @@ __global__ void k_filter_shd(FilterArgs a, u64 n) {
 }
 
 void launch_filter_simple(const FilterArgs &a, u64 n, u32 kind, hipStream_t s) {
-    if (n == 0) return;
+    if (n == 0) return;  // n: the capacity; the kernels read the count itself
     if (kind == MT_FILTER_HAMMING)
         k_filter_simple<1><<<grid_for(n, 256), 256, 0, s>>>(a, n);
     else if (kind == MT_FILTER_BASE_COUNT)

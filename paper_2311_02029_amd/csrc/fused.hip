@@ -918,6 +918,10 @@ static void launch_fused_graph(const FusedLaunch &L, hipStream_t s) {
 
 void classify_fused(const mt_index &ix, const mt_query_params &q, const mt_seqs &reads, ReadBatch &rb,
                     mt_result &res, Timer &tm, hipStream_t s, bool graph) {
+    if (q.filter != MT_FILTER_OBSTACLE) {  // the fused kernel runs the obstacle walk only
+        classify_staged(ix, q, reads, rb, res, tm, s);
+        return;
+    }
     const u64 n = reads.n;
     // staging slots per read: top_n, or F_MAX_TOPN for keep-all (top_n = 0;
     // reads with more candidates are finished per stage)

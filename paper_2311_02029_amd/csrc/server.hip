@@ -150,7 +150,8 @@ struct Batch {
 };
 
 inline bool same_query(const mt_query_params &a, const mt_query_params &b) {
-    return a.min_hits == b.min_hits && a.top_n == b.top_n && a.e_mode == b.e_mode && a.e_value == b.e_value;
+    return a.min_hits == b.min_hits && a.top_n == b.top_n && a.e_mode == b.e_mode && a.e_value == b.e_value &&
+           a.filter == b.filter;
 }
 
 // Device bytes a batch holds while it runs: bases and offsets, the read planes

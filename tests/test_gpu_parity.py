@@ -322,6 +322,26 @@ def test_filter_pairs_against_oracle(mt):
     assert (oap <= pe).mean() > 0.3 and (oap > pe).mean() > 0.05
 
 
+@pytest.mark.parametrize("mode", MODES)
+@pytest.mark.parametrize("kind", [1, 2, 3, 4])
+def test_classify_with_each_filter(mt, mode, kind):
+    """Classification with another filter of Table 1 (it runs per stage in
+    every mode): candidates as with the obstacle walk, values of that filter."""
+    rnd = np.random.default_rng(60 + kind)
+    gen = synth.make_genomes(rnd, 5, 30_000, (0.3, 0.7))
+    lens = np.concatenate([rnd.integers(60, 300, 600), rnd.integers(800, 3000, 10)])
+    reads, _ = synth.make_reads(rnd, gen, lens, 0.02, 0.01)
+    reads = synth.inject_n(rnd, reads, 0.002)
+    ga = gen.ascii()
+    ix = mt.Index(ga, 13, 7)
+    res = ix.classify(mt.to_device(reads), min_hits=2, top_n=3, e_mode=1, e_value=40, mode=mode, filter_kind=kind)
+    got = res.to_host()
+    res.free()
+    ref = oracle.Index(ga, 13, 7).classify(reads, 2, 3, 1, 40, filter_kind=kind)
+    assert_same(got, ref, f"filter {kind} mode {mode}")
+    assert 0 < ref["accept"].mean() < 1 or kind in (2, 3)
+
+
 @pytest.mark.parametrize("kind", [1, 2, 3, 4])
 def test_filter_kinds_against_oracle(mt, kind):
     """The Hamming, base-counting, q-gram and shifted-Hamming filters on one

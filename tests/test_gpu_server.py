@@ -110,6 +110,20 @@ def test_served_equals_alone_in_a_mix(env):
     assert got[0]["cand_offsets"].tolist() == [0] and got[0]["unmapped"] == 0
 
 
+def test_served_filter_kinds(env):
+    """Requests with different filters of Table 1 are batched apart and each
+    result equals the same request classified alone, and the oracle."""
+    sizes = [200, 35, 900, 4, 300, 1500, 60, 700, 10, 250]
+    reqs = _requests(env["gen"], 13, sizes)
+    queries = [dict(QUERIES[0], filter_kind=i % 5) for i in range(len(reqs))]
+    got = _serve(env, reqs, queries, threads=3, max_batch_reads=1200, n_streams=2)
+    oix = oracle.Index(env["ga"], env["k"], env["w"], taxon=env["taxon"], n_taxa=5)
+    for i, (r, q) in enumerate(zip(reqs, queries)):
+        _same(got[i], _alone(env, r, q), f"request {i}")
+        ref = oix.classify(r, q["min_hits"], q["top_n"], q["e_mode"], q["e_value"], filter_kind=q["filter_kind"])
+        _same(got[i], ref, f"request {i} vs oracle")
+
+
 def test_served_query_mix_and_oracle(env):
     sizes = [300, 50, 1200, 7, 600, 90, 2000, 15]
     reqs = _requests(env["gen"], 12, sizes)
