@@ -53,6 +53,11 @@ def _declare(lib):
     lib.or_classify_kind.restype = C.c_void_p
     lib.or_classify_kind.argtypes = [C.c_void_p, u8p, u64p, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
                                      C.c_uint32, C.c_uint32]
+    lib.or_classify_strands.restype = C.c_void_p
+    lib.or_classify_strands.argtypes = [C.c_void_p, u8p, u64p, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
+                                        C.c_uint32, C.c_uint32, C.c_uint32]
+    lib.or_result_strand.restype = None
+    lib.or_result_strand.argtypes = [C.c_void_p, u8p]
     lib.or_classify.restype = C.c_void_p
     lib.or_classify.argtypes = [C.c_void_p, u8p, u64p, C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32,
                                 C.c_uint32]
@@ -157,14 +162,19 @@ class Index:
     def n_occ(self) -> int:
         return int(self.lib.or_index_n_occ(self.h))
 
-    def classify(self, reads, min_hits=3, top_n=3, e_mode=0, e_value=7, filter_kind=0) -> dict:
+    def classify(self, reads, min_hits=3, top_n=3, e_mode=0, e_value=7, filter_kind=0, strands=1) -> dict:
         """Stage 2 and the step-3a counts; filter_kind 0 is the obstacle walk, 1-4 the
-        Hamming, base-counting, q-gram and shifted-Hamming filters."""
+        Hamming, base-counting, q-gram and shifted-Hamming filters; strands 2 adds the
+        reverse strand (the result's "strand" holds each candidate's)."""
         seq = np.ascontiguousarray(reads.seq, dtype=np.uint8)
         offs = np.ascontiguousarray(reads.offsets, dtype=np.uint64)
         n = len(offs) - 1
-        r = self.lib.or_classify_kind(self.h, _p(seq, C.c_uint8), _p(offs, C.c_uint64), n, min_hits, top_n,
-                                      e_mode, e_value, filter_kind)
+        if strands == 1:
+            r = self.lib.or_classify_kind(self.h, _p(seq, C.c_uint8), _p(offs, C.c_uint64), n, min_hits, top_n,
+                                          e_mode, e_value, filter_kind)
+        else:
+            r = self.lib.or_classify_strands(self.h, _p(seq, C.c_uint8), _p(offs, C.c_uint64), n, min_hits,
+                                             top_n, e_mode, e_value, filter_kind, strands)
         if not r:
             raise ValueError("oracle classify rejected its input")
         nc = int(self.lib.or_result_n_cands(r))
@@ -179,6 +189,8 @@ class Index:
                                 _p(out["diag"], C.c_int64), _p(out["hits"], C.c_uint32),
                                 _p(out["approx"], C.c_uint16), _p(out["accept"], C.c_uint8),
                                 _p(out["unique"], C.c_uint64), _p(out["multi"], C.c_uint64), _p(unm, C.c_uint64))
+        out["strand"] = np.zeros(nc, np.uint8)
+        self.lib.or_result_strand(r, _p(out["strand"], C.c_uint8))
         self.lib.or_result_free(r)
         out["unmapped"] = int(unm[0])
         return out

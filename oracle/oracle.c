@@ -77,6 +77,15 @@
  *       one or two zeros with a one on both sides (inside [0, m)) becomes
  *       ones; the value is the number of columns where every amended mask is
  *       one, saturated at E + 1; accept iff <= E.
+ *   O15 both strands (reads come from either strand; minimap2 maps both): the
+ *       reverse strand of a genome is met by the reverse complement R of the
+ *       read (Q reversed, A<->T and C<->G swapped, N kept) against the forward
+ *       genome.  Strand-1 seeds are the O3 minimizers of R looked up in the
+ *       same forward index; a location is (genome, strand, diag) with diag =
+ *       q - p for the position p in R.  O5 counts both strands together:
+ *       (hits desc, genome asc, diag asc, strand asc), one top_n over the
+ *       union.  The filter of a strand-1 location runs on R.  With one strand
+ *       (the default) only strand 0 exists.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -345,25 +354,37 @@ int or_read_E(int64_t m, uint32_t e_mode, uint32_t e_value)
     return (int)(num / 1000);
 }
 
-typedef struct { uint32_t genome; int64_t diag; } hit_t;
-typedef struct { uint32_t genome; int64_t diag; uint32_t hits; } cand_t;
+typedef struct { uint32_t genome; int64_t diag; uint8_t strand; } hit_t;
+typedef struct { uint32_t genome; int64_t diag; uint32_t hits; uint8_t strand; } cand_t;
 
 static int cmp_hit(const void *a, const void *b)
 {
     const hit_t *p = a, *q = b;
     if (p->genome != q->genome) return p->genome < q->genome ? -1 : 1;
     if (p->diag != q->diag) return p->diag < q->diag ? -1 : 1;
+    if (p->strand != q->strand) return p->strand < q->strand ? -1 : 1;
     return 0;
 }
 
-/* O5 order: hits descending, then genome ascending, then diagonal ascending. */
+/* O5 order: hits descending, then genome ascending, then diagonal ascending,
+ * then strand ascending (O15). */
 static int cmp_cand(const void *a, const void *b)
 {
     const cand_t *p = a, *q = b;
     if (p->hits != q->hits) return p->hits > q->hits ? -1 : 1;
     if (p->genome != q->genome) return p->genome < q->genome ? -1 : 1;
     if (p->diag != q->diag) return p->diag < q->diag ? -1 : 1;
+    if (p->strand != q->strand) return p->strand < q->strand ? -1 : 1;
     return 0;
+}
+
+/* O15: codes of the reverse complement of q[0, m) (A0<->T3, C1<->G2, N4 kept). */
+static void reverse_complement_codes(const uint8_t *q, int64_t m, uint8_t *out)
+{
+    for (int64_t j = 0; j < m; j++) {
+        uint8_t c = q[m - 1 - j];
+        out[j] = c == 4 ? 4 : (uint8_t)(3 - c);
+    }
 }
 
 typedef struct or_result {
@@ -377,6 +398,7 @@ typedef struct or_result {
     uint32_t *hits;
     uint16_t *approx;
     uint8_t *accept;
+    uint8_t *strand;
     uint32_t n_taxa;
     uint64_t *unique_reads;
     uint64_t *multi_reads;
@@ -388,7 +410,7 @@ void or_result_free(or_result *r)
 {
     if (!r) return;
     free(r->cand_offsets); free(r->read_accepted); free(r->read_E);
-    free(r->genome); free(r->diag); free(r->hits); free(r->approx); free(r->accept);
+    free(r->genome); free(r->diag); free(r->hits); free(r->approx); free(r->accept); free(r->strand);
     free(r->unique_reads); free(r->multi_reads);
     free(r);
 }
@@ -402,8 +424,10 @@ static void push_cand(or_result *r, const cand_t *c)
         r->hits = realloc(r->hits, r->cap * sizeof *r->hits);
         r->approx = realloc(r->approx, r->cap * sizeof *r->approx);
         r->accept = realloc(r->accept, r->cap * sizeof *r->accept);
+        r->strand = realloc(r->strand, r->cap * sizeof *r->strand);
     }
     r->genome[r->n_cands] = c->genome;
+    r->strand[r->n_cands] = c->strand;
     r->diag[r->n_cands] = c->diag;
     r->hits[r->n_cands] = c->hits;
     r->n_cands++;
@@ -429,13 +453,15 @@ static int filter_codes(uint32_t kind, const uint8_t *q, int64_t m, const uint8_
 }
 
 /*
- * Classifies reads (ASCII + offsets[n+1]).  Returns NULL on an invalid input
- * (bad byte, read longer than 65535, E above 65534).
+ * Classifies reads (ASCII + offsets[n+1]) on one strand or both (O15).
+ * Returns NULL on an invalid input (bad byte, read longer than 65535, E above
+ * 65534, unknown filter kind, strands other than 1 or 2).
  */
-or_result *or_classify_kind(const or_index *ix, const uint8_t *seq, const uint64_t *offsets, uint64_t n,
-                            uint32_t min_hits, uint32_t top_n, uint32_t e_mode, uint32_t e_value, uint32_t kind)
+or_result *or_classify_strands(const or_index *ix, const uint8_t *seq, const uint64_t *offsets, uint64_t n,
+                               uint32_t min_hits, uint32_t top_n, uint32_t e_mode, uint32_t e_value,
+                               uint32_t kind, uint32_t strands)
 {
-    if (kind > 4) return NULL;
+    if (kind > 4 || strands < 1 || strands > 2) return NULL;
     or_result *res = calloc(1, sizeof *res);
     res->n_reads = n;
     res->cand_offsets = calloc(n + 1, sizeof *res->cand_offsets);
@@ -451,28 +477,35 @@ or_result *or_classify_kind(const or_index *ix, const uint8_t *seq, const uint64
         int E = or_read_E(m, e_mode, e_value);
         if (m > (int64_t)MAX_READ_LEN || E > 65534) { free(taxon_seen); or_result_free(res); return NULL; }
         res->read_E[r] = (uint16_t)E;
-        uint8_t *q = malloc((size_t)(m > 0 ? m : 1));
-        if (encode(seq + offsets[r], m, q) != OR_OK) {
-            free(q); free(taxon_seen); or_result_free(res); return NULL;
+        /* the read (strand 0) and its reverse complement (strand 1, O15) */
+        uint8_t *oriented[2];
+        oriented[0] = malloc((size_t)(m > 0 ? m : 1));
+        oriented[1] = malloc((size_t)(m > 0 ? m : 1));
+        if (encode(seq + offsets[r], m, oriented[0]) != OR_OK) {
+            free(oriented[0]); free(oriented[1]); free(taxon_seen); or_result_free(res); return NULL;
         }
+        reverse_complement_codes(oriented[0], m, oriented[1]);
 
-        /* stage 2b: read minimizers and their seed matches -> (genome, diag) hits */
+        /* stage 2b: read minimizers and their seed matches -> (genome, diag, strand) hits */
         int64_t nk = m - ix->k + 1 > 0 ? m - ix->k + 1 : 0;
         int64_t *mpos = malloc((size_t)(nk ? nk : 1) * sizeof *mpos);
         uint64_t *mx = malloc((size_t)(nk ? nk : 1) * sizeof *mx);
-        int64_t nmin = minimizers_of_codes(q, m, ix->k, ix->w, mpos, mx);
         int64_t nh = 0, hcap = 64;
         hit_t *hit = malloc((size_t)hcap * sizeof *hit);
-        for (int64_t i = 0; i < nmin; i++) {
-            int64_t lo = lower_bound(ix->occ, ix->n_occ, mx[i]);
-            int64_t hi = lo;
-            while (hi < ix->n_occ && ix->occ[hi].x == mx[i]) hi++;
-            if (ix->max_occ > 0 && hi - lo > (int64_t)ix->max_occ) continue;
-            for (int64_t o = lo; o < hi; o++) {
-                if (nh == hcap) { hcap *= 2; hit = realloc(hit, (size_t)hcap * sizeof *hit); }
-                hit[nh].genome = ix->occ[o].genome;
-                hit[nh].diag = (int64_t)ix->occ[o].pos - mpos[i];
-                nh++;
+        for (uint32_t st = 0; st < strands; st++) {
+            int64_t nmin = minimizers_of_codes(oriented[st], m, ix->k, ix->w, mpos, mx);
+            for (int64_t i = 0; i < nmin; i++) {
+                int64_t lo = lower_bound(ix->occ, ix->n_occ, mx[i]);
+                int64_t hi = lo;
+                while (hi < ix->n_occ && ix->occ[hi].x == mx[i]) hi++;
+                if (ix->max_occ > 0 && hi - lo > (int64_t)ix->max_occ) continue;
+                for (int64_t o = lo; o < hi; o++) {
+                    if (nh == hcap) { hcap *= 2; hit = realloc(hit, (size_t)hcap * sizeof *hit); }
+                    hit[nh].genome = ix->occ[o].genome;
+                    hit[nh].diag = (int64_t)ix->occ[o].pos - mpos[i];
+                    hit[nh].strand = (uint8_t)st;
+                    nh++;
+                }
             }
         }
         free(mpos); free(mx);
@@ -483,10 +516,13 @@ or_result *or_classify_kind(const or_index *ix, const uint8_t *seq, const uint64
         int64_t nc = 0;
         for (int64_t i = 0; i < nh;) {
             int64_t j = i;
-            while (j < nh && hit[j].genome == hit[i].genome && hit[j].diag == hit[i].diag) j++;
+            while (j < nh && hit[j].genome == hit[i].genome && hit[j].diag == hit[i].diag &&
+                   hit[j].strand == hit[i].strand)
+                j++;
             if ((uint64_t)(j - i) >= min_hits) {
                 cand[nc].genome = hit[i].genome;
                 cand[nc].diag = hit[i].diag;
+                cand[nc].strand = hit[i].strand;
                 cand[nc].hits = (uint32_t)(j - i);
                 nc++;
             }
@@ -502,14 +538,14 @@ or_result *or_classify_kind(const or_index *ix, const uint8_t *seq, const uint64
         for (int64_t c = 0; c < nc; c++) {
             push_cand(res, &cand[c]);
             uint32_t g = cand[c].genome;
-            int a = filter_codes(kind, q, m, ix->gcode[g], ix->glen[g], cand[c].diag, E);
+            int a = filter_codes(kind, oriented[cand[c].strand], m, ix->gcode[g], ix->glen[g], cand[c].diag, E);
             res->approx[res->n_cands - 1] = (uint16_t)a;
             res->accept[res->n_cands - 1] = (uint8_t)(a <= E);
             if (a <= E && (best < 0 || a < best)) best = a;
         }
         res->cand_offsets[r + 1] = res->n_cands;
         free(cand);
-        free(q);
+        free(oriented[0]); free(oriented[1]);
 
         /* stage 3a: per-taxon unique / multi-mapped counts */
         if (best < 0) {
@@ -535,6 +571,13 @@ or_result *or_classify_kind(const or_index *ix, const uint8_t *seq, const uint64
     }
     free(taxon_seen);
     return res;
+}
+
+/* Classification on the forward strand with the filter of the given kind. */
+or_result *or_classify_kind(const or_index *ix, const uint8_t *seq, const uint64_t *offsets, uint64_t n,
+                            uint32_t min_hits, uint32_t top_n, uint32_t e_mode, uint32_t e_value, uint32_t kind)
+{
+    return or_classify_strands(ix, seq, offsets, n, min_hits, top_n, e_mode, e_value, kind, 1);
 }
 
 /* Classification with the obstacle filter (kind 0). */
@@ -564,6 +607,12 @@ void or_result_copy(const or_result *r, uint64_t *cand_offsets, uint8_t *read_ac
     memcpy(unique_reads, r->unique_reads, r->n_taxa * sizeof *unique_reads);
     memcpy(multi_reads, r->multi_reads, r->n_taxa * sizeof *multi_reads);
     *unmapped = r->unmapped;
+}
+
+/* The strand of every candidate (O15). */
+void or_result_strand(const or_result *r, uint8_t *strand)
+{
+    if (r->n_cands) memcpy(strand, r->strand, r->n_cands);
 }
 
 /* O11: mismatching columns of row 0, saturated at E + 1. */

@@ -13,7 +13,8 @@ import oracle
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "oracle.c")
 PIN_FILES = [os.path.join(ROOT, "tests", f)
-             for f in ("test_oracle_pins.py", "test_oracle_containment.py", "test_oracle_filters.py")]
+             for f in ("test_oracle_pins.py", "test_oracle_containment.py", "test_oracle_filters.py",
+                       "test_oracle_strands.py")]
 
 # (name, original text, planted mistake); each original occurs exactly once.
 MUTANTS = [
@@ -32,8 +33,15 @@ MUTANTS = [
     ("strict min_hits", "if ((uint64_t)(j - i) >= min_hits) {", "if ((uint64_t)(j - i) > min_hits) {"),
     ("hits ascending", "if (p->hits != q->hits) return p->hits > q->hits ? -1 : 1;",
      "if (p->hits != q->hits) return p->hits < q->hits ? -1 : 1;"),
-    ("genome tie descending", "if (p->genome != q->genome) return p->genome < q->genome ? -1 : 1;\n    if (p->diag != q->diag) return p->diag < q->diag ? -1 : 1;\n    return 0;\n}\n\ntypedef struct or_result",
-     "if (p->genome != q->genome) return p->genome > q->genome ? -1 : 1;\n    if (p->diag != q->diag) return p->diag < q->diag ? -1 : 1;\n    return 0;\n}\n\ntypedef struct or_result"),
+    ("genome tie descending",
+     "if (p->genome != q->genome) return p->genome < q->genome ? -1 : 1;\n    if (p->diag != q->diag) return p->diag < q->diag ? -1 : 1;\n    if (p->strand != q->strand) return p->strand < q->strand ? -1 : 1;\n    return 0;\n}\n\n/* O15",
+     "if (p->genome != q->genome) return p->genome > q->genome ? -1 : 1;\n    if (p->diag != q->diag) return p->diag < q->diag ? -1 : 1;\n    if (p->strand != q->strand) return p->strand < q->strand ? -1 : 1;\n    return 0;\n}\n\n/* O15"),
+    ("strand tie reverse first", "if (p->strand != q->strand) return p->strand < q->strand ? -1 : 1;\n    return 0;\n}\n\n/* O15",
+     "if (p->strand != q->strand) return p->strand > q->strand ? -1 : 1;\n    return 0;\n}\n\n/* O15"),
+    ("reverse without complement", "out[j] = c == 4 ? 4 : (uint8_t)(3 - c);", "out[j] = c;"),
+    ("complement without reverse", "uint8_t c = q[m - 1 - j];", "uint8_t c = q[j];"),
+    ("strands merged in counting", "hit[j].strand == hit[i].strand)", "1)"),
+    ("strand-1 filter on the read", "filter_codes(kind, oriented[cand[c].strand], m,", "filter_codes(kind, oriented[0], m,"),
     ("top_n off by one", "if (top_n > 0 && nc > (int64_t)top_n) nc = top_n;",
      "if (top_n > 0 && nc > (int64_t)top_n + 1) nc = top_n + 1;"),
     ("N is a fifth letter", "    if (qc == 4) return 1;\n    if (p < 0 || p >= glen) return 1;\n    uint8_t rc = gcode[p];\n    if (rc == 4) return 1;",
