@@ -271,6 +271,8 @@ def main() -> int:
                          "bucket (default: on for the uneven workload); 0: built-in defaults")
     ap.add_argument("--serving", type=int, default=1,
                     help="1: also measure the served workload (batched workload only); 0: skip it")
+    ap.add_argument("--strands-bench", type=int, default=1,
+                    help="also time both-strand classification of the batch with half its reads reversed")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="length of each served trace")
     ap.add_argument("--serve-streams", type=int, default=0, help="server worker streams (0: library default, 4)")
     ap.add_argument("--serve-threads", type=int, default=8, help="client threads submitting served requests")
@@ -488,6 +490,33 @@ def main() -> int:
         filters["pairs"] = int(len(pr))
         log(f"[bench] filters on the pair stream (mt_filter_pairs_kind, incl. read packing): {json.dumps(filters)}")
 
+    # Both strands: the batch with half its reads taken from the reverse strand.
+    strands = None
+    if args.workload == "batched" and args.strands_bench:
+        flipped = synth.from_reverse_strand(np.random.default_rng(77), reads, 0.5)
+        dflip = mt.to_device(flipped)
+        one = ix.classify(dflip, **q).to_host()
+        r = ix.classify(dflip, **dict(q, mode=mt.MT_MODE_PER_STAGE), strands=2)  # warm
+        r.free()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(3):
+            r = ix.classify(dflip, **dict(q, mode=mt.MT_MODE_PER_STAGE), strands=2)
+            torch.cuda.synchronize()
+            nc2 = r.n_cands
+            r.free()
+        s_ms = (time.perf_counter() - t) * 1000.0 / 3
+        r = ix.classify(dflip, **dict(q, mode=mt.MT_MODE_PER_STAGE), strands=2)
+        two = r.to_host()
+        r.free()
+        strands = {"ms": round(s_ms, 3), "reads_per_s": round(flipped.n / (s_ms / 1000.0), 1),
+                   "pairs_per_s": round(nc2 / (s_ms / 1000.0), 1), "pairs": int(nc2),
+                   "accepted_both": round(float(two["read_accepted"].mean()), 4),
+                   "accepted_forward_only": round(float(one["read_accepted"].mean()), 4),
+                   "reverse_cands": round(float(two["strand"].mean()), 4)}
+        del dflip
+        log(f"[bench] both strands (per-stage over the two-strand read set): {json.dumps(strands)}")
+
     serving = None
     if pool is not None:
         serving = serving_bench(mt, ix, pool, seconds=args.serve_seconds, n_streams=args.serve_streams,
@@ -522,6 +551,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "containment": containment,
         "filters": filters,
+        "strands": strands,
         "serving": serving,
     }
     print(json.dumps(out), flush=True)

@@ -104,7 +104,10 @@ typedef struct mt_query_params {
     uint32_t mode;       /* MT_MODE_* */
     uint32_t filter;     /* MT_FILTER_* (0: the obstacle walk).  The other filters
                             run in the per-stage form whatever the mode. */
-    uint32_t reserved[2];/* must be 0 */
+    uint32_t strands;    /* 0 or 1: the forward strand of each genome; 2: both
+                            strands (see mt_result_strands).  Two strands run in
+                            the per-stage form whatever the mode. */
+    uint32_t reserved;   /* must be 0 */
 } mt_query_params;
 
 typedef struct mt_index_info {
@@ -172,6 +175,20 @@ int mt_result_cands(const mt_result *res, uint64_t *n_cands, const uint32_t **ge
  * for each; a read with no accepted candidate is unmapped. */
 int mt_result_taxa(const mt_result *res, uint32_t *n_taxa, const uint64_t **unique_reads,
                    const uint64_t **multi_reads, const uint64_t **unmapped);
+
+/* Strand of every candidate (device array of n_cands entries, or host for a
+ * served result): 0 forward, 1 reverse.  *strand is NULL for a result of a
+ * one-strand query (every candidate is forward).
+ *
+ * Both strands (Fig. 1 step 2b: reads come from either strand of a genome,
+ * and the mapper the paper builds on maps both): the reverse strand is met by
+ * the reverse complement R of the read (reversed, A<->T and C<->G swapped, N
+ * kept) against the forward genome.  A reverse candidate's seeds are the
+ * minimizers of R in the same forward index, its diag is the reference
+ * position of R's first base, and its filter value is computed on R.  The
+ * candidates of both strands are ordered together by (hits descending, genome,
+ * diag, strand ascending) and one top_n cut applies to the union. */
+int mt_result_strands(const mt_result *res, const uint8_t **strand);
 int mt_result_free(mt_result *res);
 
 /* Per-launch kernel timings of the last mt_classify on this thread (ms,

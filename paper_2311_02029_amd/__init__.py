@@ -224,15 +224,23 @@ class Result:
         _check(self.lib.mt_result_times(self.h, C.byref(a), C.byref(b)), self.lib)
         return a.value, b.value
 
+    def _strands(self):
+        p = C.c_void_p()
+        _check(self.lib.mt_result_strands(self.h, C.byref(p)), self.lib)
+        return p.value
+
     def to_host(self) -> dict:
+        """Host copies of every output; "strand" is all zeros for a one-strand query."""
         nr, co, ra, re = self._reads()
         nc, (g, d, h, a, ac) = self._cands()
         nt, (u, mu, un) = self._taxa()
+        st = self._strands()
         cp = _host_array if self.on_host else _copy_to_host
         return dict(
             cand_offsets=cp(co, nr + 1, np.uint64), read_accepted=cp(ra, nr, np.uint8),
             read_E=cp(re, nr, np.uint16), genome=cp(g, nc, np.uint32), diag=cp(d, nc, np.int64),
             hits=cp(h, nc, np.uint32), approx=cp(a, nc, np.uint16), accept=cp(ac, nc, np.uint8),
+            strand=cp(st, nc, np.uint8) if st else np.zeros(nc, np.uint8),
             unique=cp(u, nt, np.uint64), multi=cp(mu, nt, np.uint64), unmapped=int(cp(un, 1, np.uint64)[0]))
 
     def free(self) -> None:
@@ -282,8 +290,9 @@ class Index:
         return hits[:n]
 
     def classify(self, reads: DeviceSeqs, min_hits=3, top_n=3, e_mode=MT_E_FIXED, e_value=7,
-                 mode=MT_MODE_PER_STAGE, stream=None, filter_kind=MT_FILTER_OBSTACLE) -> Result:
-        q = _abi.mt_query_params(min_hits, top_n, e_mode, e_value, mode, filter_kind)
+                 mode=MT_MODE_PER_STAGE, stream=None, filter_kind=MT_FILTER_OBSTACLE, strands=1) -> Result:
+        """mt_classify; strands=2 adds the reverse strand of every genome."""
+        q = _abi.mt_query_params(min_hits, top_n, e_mode, e_value, mode, filter_kind, strands)
         h = C.c_void_p()
         sp = _stream_ptr(stream)
         if mode == MT_MODE_FUSED_GRAPH and sp == 0:
@@ -353,10 +362,10 @@ class Server:
         self.h = h.value
 
     def submit(self, seqset, min_hits=3, top_n=3, e_mode=MT_E_FIXED, e_value=7,
-               filter_kind=MT_FILTER_OBSTACLE) -> int:
+               filter_kind=MT_FILTER_OBSTACLE, strands=1) -> int:
         seq = np.ascontiguousarray(seqset.seq, dtype=np.uint8)
         offs = np.ascontiguousarray(seqset.offsets, dtype=np.uint64)
-        q = _abi.mt_query_params(min_hits, top_n, e_mode, e_value, MT_MODE_FUSED, filter_kind)
+        q = _abi.mt_query_params(min_hits, top_n, e_mode, e_value, MT_MODE_FUSED, filter_kind, strands)
         rid = C.c_uint64()
         rc = self.lib.mt_server_submit(self.h, C.byref(q), seq.ctypes.data if len(seq) else None,
                                        offs.ctypes.data, len(offs) - 1, C.byref(rid))

@@ -18,7 +18,7 @@ MT_FILTER_OBSTACLE, MT_FILTER_HAMMING, MT_FILTER_BASE_COUNT, MT_FILTER_QGRAM, MT
 # Every function the header declares; a test checks the library exports them.
 ABI_FUNCTIONS = (
     "mt_index_build", "mt_index_free", "mt_index_get_info", "mt_classify", "mt_result_reads",
-    "mt_result_cands", "mt_result_taxa", "mt_result_free", "mt_last_timings", "mt_set_timing",
+    "mt_result_cands", "mt_result_taxa", "mt_result_strands", "mt_result_free", "mt_last_timings", "mt_set_timing",
     "mt_filter_pairs", "mt_trim", "mt_last_error", "mt_abi_version", "mt_last_stats", "mt_server_create",
     "mt_server_submit", "mt_server_wait", "mt_server_destroy", "mt_result_on_host", "mt_result_times",
     "mt_tune_buckets", "mt_tune_info", "mt_tune_set", "mt_tune_reset", "mt_autotune", "mt_tune_save",
@@ -36,7 +36,7 @@ class mt_index_params(C.Structure):
 
 class mt_query_params(C.Structure):
     _fields_ = [("min_hits", C.c_uint32), ("top_n", C.c_uint32), ("e_mode", C.c_uint32), ("e_value", C.c_uint32),
-                ("mode", C.c_uint32), ("filter", C.c_uint32), ("reserved", C.c_uint32 * 2)]
+                ("mode", C.c_uint32), ("filter", C.c_uint32), ("strands", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class mt_index_info(C.Structure):
@@ -86,6 +86,7 @@ def load(path: str = LIB_PATH):
         "mt_classify": (i32, [vp, C.POINTER(mt_query_params), C.POINTER(mt_seqs), vp, pp]),
         "mt_result_reads": (i32, [vp, C.POINTER(u64), pp, pp, pp]),
         "mt_result_cands": (i32, [vp, C.POINTER(u64), pp, pp, pp, pp, pp]),
+        "mt_result_strands": (i32, [vp, pp]),
         "mt_result_taxa": (i32, [vp, C.POINTER(u32), pp, pp, pp]),
         "mt_result_free": (i32, [vp]),
         "mt_last_timings": (i32, [C.POINTER(C.c_char_p), C.POINTER(C.c_float), u32, C.POINTER(u32)]),

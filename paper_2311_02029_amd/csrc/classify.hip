@@ -523,11 +523,22 @@ void validate_query(const mt_query_params &q) {
     MT_REQUIRE(q.e_mode != MT_E_FIXED || q.e_value <= 65534, "E must be at most 65534");
     MT_REQUIRE(q.mode <= MT_MODE_FUSED_GRAPH, "unknown mode");
     MT_REQUIRE(q.filter <= MT_FILTER_SHD, "unknown filter");
-    MT_REQUIRE(q.reserved[0] == 0 && q.reserved[1] == 0, "reserved fields must be 0");
+    MT_REQUIRE(q.strands <= 2, "strands must be 0, 1 or 2");
+    MT_REQUIRE(q.reserved == 0, "reserved fields must be 0");
 }
 
-void classify_per_stage(const mt_index &ix, const mt_query_params &q, const mt_seqs &reads, ReadBatch &rb,
-                        mt_result &res, Timer &tm, hipStream_t s) {
+// Seeds, lookup, gather, count and select of the per-stage form: for every
+// read its ncand[r] candidates at stage_key / stage_hits[read_hs[r] ...], in
+// the canonical order with min_hits and top_n applied.
+struct StagedCands {
+    DBuf<u64> stage_key, read_hs;
+    DBuf<u32> stage_hits, ncand;
+    u64 H = 0;      // seed hits (bounds every candidate count)
+    u32 max_E = 0;  // largest E of the reads
+};
+
+static void stage_seed_count(const mt_index &ix, const mt_query_params &q, const mt_seqs &reads, ReadBatch &rb,
+                             StagedCands &sc, Timer &tm, hipStream_t s) {
     u64 n = reads.n;
     // seeds
     MinimizerPlan mp;
@@ -542,7 +553,7 @@ void classify_per_stage(const mt_index &ix, const mt_query_params &q, const mt_s
     MT_HIP(hipMemcpyAsync(&hf[1], rb.maxE.p, sizeof(u32), hipMemcpyDeviceToHost, s));
     read_back(s, mp.min_off.p + mp.tiles_cap, &n_min, sizeof(u64));
     check_flags(hf[0]);
-    u32 max_E = hf[1];
+    sc.max_E = hf[1];
     DBuf<u64> min_x(n_min), min_val(n_min);
     DBuf<u32> min_seq(n_min), min_pos(n_min), min_nocc(n_min);
     minimizer_emit(reads, rb.planes, ix.k, ix.w, mp, min_x.p, min_seq.p, min_pos.p, s);
@@ -558,56 +569,56 @@ void classify_per_stage(const mt_index &ix, const mt_query_params &q, const mt_s
     scan_u32(min_nocc.p, hit_off.p, n_min, s);
     u64 H = 0;
     read_back(s, hit_off.p + n_min, &H, sizeof(u64));
-    DBuf<u64> hit_key(H), read_hs(n + 1);
+    sc.H = H;
+    DBuf<u64> hit_key(H);
+    sc.read_hs.alloc(n + 1);
     if (n_min) {
         k_gather<<<grid_for(n_min, 256), 256, 0, s>>>(min_pos.p, min_val.p, hit_off.p, n_min, ix.occ.p, hit_key.p);
         MT_HIP(hipGetLastError());
     }
-    k_read_hits<<<grid_for(n + 1, 256), 256, 0, s>>>(mp.tile_off.p, mp.min_off.p, hit_off.p, n, read_hs.p);
+    k_read_hits<<<grid_for(n + 1, 256), 256, 0, s>>>(mp.tile_off.p, mp.min_off.p, hit_off.p, n, sc.read_hs.p);
     MT_HIP(hipGetLastError());
     tm.mark("gather");
     // count + select
-    DBuf<u64> stage_key(H);
-    DBuf<u32> stage_hits(H), ncand(n), mid_list(n), large_list(n), lists(2);
+    sc.stage_key.alloc(H);
+    sc.stage_hits.alloc(H);
+    sc.ncand.alloc(n);
+    DBuf<u32> mid_list(n), large_list(n), lists(2);
     u32 *n_mid = lists.p, *n_large = lists.p + 1;
     MT_HIP(hipMemsetAsync(lists.p, 0, 2 * sizeof(u32), s));
     last_stats().n_minimizers += n_min;
     last_stats().n_hits += H;
     if (n) {
-        k_count_wave<<<grid_for(n, CW_WPB), 64 * CW_WPB, 0, s>>>(hit_key.p, read_hs.p, n, q.min_hits, q.top_n,
-                                                                  stage_key.p, stage_hits.p, ncand.p, mid_list.p,
-                                                                  n_mid);
+        k_count_wave<<<grid_for(n, CW_WPB), 64 * CW_WPB, 0, s>>>(hit_key.p, sc.read_hs.p, n, q.min_hits, q.top_n,
+                                                                  sc.stage_key.p, sc.stage_hits.p, sc.ncand.p,
+                                                                  mid_list.p, n_mid);
         MT_HIP(hipGetLastError());
-        k_count_block<<<count_blocks(), COUNT_TPB, 0, s>>>(hit_key.p, read_hs.p, q.min_hits, q.top_n, stage_key.p,
-                                                           stage_hits.p, ncand.p, mid_list.p, n_mid, large_list.p,
-                                                           n_large);
+        k_count_block<<<count_blocks(), COUNT_TPB, 0, s>>>(hit_key.p, sc.read_hs.p, q.min_hits, q.top_n,
+                                                           sc.stage_key.p, sc.stage_hits.p, sc.ncand.p, mid_list.p,
+                                                           n_mid, large_list.p, n_large);
         MT_HIP(hipGetLastError());
-        k_count_large<<<256, COUNT_TPB, 0, s>>>(hit_key.p, read_hs.p, q.min_hits, q.top_n, stage_key.p,
-                                                stage_hits.p, ncand.p, large_list.p, n_large);
+        k_count_large<<<256, COUNT_TPB, 0, s>>>(hit_key.p, sc.read_hs.p, q.min_hits, q.top_n, sc.stage_key.p,
+                                                sc.stage_hits.p, sc.ncand.p, large_list.p, n_large);
         MT_HIP(hipGetLastError());
     }
     tm.mark("count_select");
-    // candidates
-    u64 cap = q.top_n ? std::min<u64>(H, n * (u64)q.top_n) : H;
-    res.alloc_cands(cap);
-    scan_u32(ncand.p, res.cand_off.p, n, s);
-    DBuf<u32> pair_read(cap);
-    if (n) {
-        k_compact<<<grid_for(n, 256), 256, 0, s>>>(read_hs.p, ncand.p, res.cand_off.p, n, stage_key.p,
-                                                   stage_hits.p, res.genome.p, res.diag.p, res.hits.p, pair_read.p);
-        MT_HIP(hipGetLastError());
-    }
-    tm.mark("compact");
-    // filter
+}
+
+// Filter the candidates of res (pair_read indexes `reads`, whose planes are
+// in rb) and reduce them per result read with read_E.
+static void stage_filter_reduce(const mt_index &ix, const mt_query_params &q, const mt_seqs &reads,
+                                const ReadBatch &rb, const u32 *pair_read, u64 cap, u32 max_E, const u16 *read_E,
+                                mt_result &res, Timer &tm, hipStream_t s) {
+    const u64 n = res.n_reads;
     FilterArgs fa{};
-    fa.pair_read = pair_read.p;
+    fa.pair_read = pair_read;
     fa.pair_genome = res.genome.p;
     fa.pair_diag = res.diag.p;
     fa.pair_E = nullptr;
     fa.read_E = rb.read_E.p;
     fa.n_dev = res.cand_off.p + n;
     fa.n_host = cap;
-    fa.n_reads = n;
+    fa.n_reads = reads.n;
     fa.read_off = reads.offsets;
     fa.read_blk = rb.planes.blk_off.p;
     fa.read_lohi = rb.planes.lohi.p;
@@ -627,13 +638,186 @@ void classify_per_stage(const mt_index &ix, const mt_query_params &q, const mt_s
     // reduce
     if (n) {
         const unsigned blocks = std::min<u64>(grid_for(n, RED_TPB), (u64)count_blocks() / 2);
-        k_reduce<<<blocks, RED_TPB, 0, s>>>(res.cand_off.p, n, res.genome.p, res.approx.p, rb.read_E.p, ix.taxon.p,
+        k_reduce<<<blocks, RED_TPB, 0, s>>>(res.cand_off.p, n, res.genome.p, res.approx.p, read_E, ix.taxon.p,
                                             ix.n_taxa, res.read_accepted.p, (unsigned long long *)res.uniq.p,
                                             (unsigned long long *)res.multi.p,
                                             (unsigned long long *)res.unmapped.p);
         MT_HIP(hipGetLastError());
     }
     tm.mark("reduce");
+}
+
+void classify_per_stage(const mt_index &ix, const mt_query_params &q, const mt_seqs &reads, ReadBatch &rb,
+                        mt_result &res, Timer &tm, hipStream_t s) {
+    const u64 n = reads.n;
+    StagedCands sc;
+    stage_seed_count(ix, q, reads, rb, sc, tm, s);
+    // candidates
+    u64 cap = q.top_n ? std::min<u64>(sc.H, n * (u64)q.top_n) : sc.H;
+    res.alloc_cands(cap);
+    scan_u32(sc.ncand.p, res.cand_off.p, n, s);
+    DBuf<u32> pair_read(cap);
+    if (n) {
+        k_compact<<<grid_for(n, 256), 256, 0, s>>>(sc.read_hs.p, sc.ncand.p, res.cand_off.p, n, sc.stage_key.p,
+                                                   sc.stage_hits.p, res.genome.p, res.diag.p, res.hits.p,
+                                                   pair_read.p);
+        MT_HIP(hipGetLastError());
+    }
+    tm.mark("compact");
+    stage_filter_reduce(ix, q, reads, rb, pair_read.p, cap, sc.max_E, rb.read_E.p, res, tm, s);
+}
+
+// ------------------------------------------------------------ both strands --
+
+// Complement of an ASCII base (either case); N and any other byte unchanged,
+// so that invalid bytes are still refused by the packing step.
+__device__ inline u8 complement_base(u8 c) {
+    switch (c) {
+    case 'A': return 'T';
+    case 'C': return 'G';
+    case 'G': return 'C';
+    case 'T': return 'A';
+    case 'a': return 't';
+    case 'c': return 'g';
+    case 'g': return 'c';
+    case 't': return 'a';
+    default: return c;
+    }
+}
+
+// Offsets of the two-strand read set: read r becomes sequences 2r (the read)
+// and 2r + 1 (its reverse complement), stored back to back at 2 * off[r].
+// Checks the caller's offsets as the packing step does.
+__global__ void k_strand_offsets(const u64 *__restrict__ off, u64 n, u64 total, u64 *__restrict__ off2,
+                                 u32 *__restrict__ flags) {
+    const u64 r = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r > n) return;
+    if (r == n) {
+        off2[2 * n] = 2 * total;
+        return;
+    }
+    const u64 a = off[r], b = off[r + 1];
+    if (b < a || b > total || (r == 0 && a != 0) || (r == n - 1 && b != total)) atomicOr(flags, ERR_OFFSETS);
+    off2[2 * r] = 2 * a;
+    off2[2 * r + 1] = a + b;
+}
+
+constexpr int SR_WPB = 4;  // reads (one wavefront each) per block
+
+// One wavefront per read: the read's bytes, then its reverse complement.
+// Runs only after the offsets passed k_strand_offsets.
+__global__ __launch_bounds__(64 * SR_WPB) void k_strand_reads(const u8 *__restrict__ seq,
+                                                              const u64 *__restrict__ off, u64 n,
+                                                              u8 *__restrict__ seq2) {
+    const u64 lane = threadIdx.x & 63;
+    const u64 stride = (u64)gridDim.x * SR_WPB;
+    for (u64 r = (u64)blockIdx.x * SR_WPB + (threadIdx.x >> 6); r < n; r += stride) {
+        const u64 a = off[r], m = off[r + 1] - a;
+        const u8 *src = seq + a;
+        u8 *fwd = seq2 + 2 * a, *rev = fwd + m;
+        for (u64 j = lane; j < m; j += 64) {
+            const u8 c = src[j];
+            fwd[j] = c;
+            rev[m - 1 - j] = complement_base(c);
+        }
+    }
+}
+
+// Candidates kept per read over both strands: the union, cut at top_n.
+__global__ void k_strand_count(const u32 *__restrict__ ncand, u64 n, u32 top_n, u32 *__restrict__ nmerged) {
+    const u64 r = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const u32 c = ncand[2 * r] + ncand[2 * r + 1];
+    nmerged[r] = top_n && c > top_n ? top_n : c;
+}
+
+// Merges the two sorted candidate lists of read r (forward: sequence 2r,
+// reverse: 2r + 1) in the order (hits desc, genome, diag, strand), keeping the
+// first nmerged; pair_read names the oriented sequence the filter reads.
+__global__ void k_strand_merge(const u64 *__restrict__ read_hs, const u32 *__restrict__ ncand,
+                               const u64 *__restrict__ cand_off, u64 n, const u64 *__restrict__ stage_key,
+                               const u32 *__restrict__ stage_hits, const u16 *__restrict__ read_E2,
+                               u32 *__restrict__ genome, i64 *__restrict__ diag, u32 *__restrict__ hits,
+                               u8 *__restrict__ strand, u32 *__restrict__ pair_read, u16 *__restrict__ read_E) {
+    const u64 r = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const u64 h0 = read_hs[2 * r], h1 = read_hs[2 * r + 1];
+    const u32 n0 = ncand[2 * r], n1 = ncand[2 * r + 1];
+    const u64 o = cand_off[r], cnt = cand_off[r + 1] - o;
+    u32 i = 0, j = 0;
+    for (u64 t = 0; t < cnt; t++) {
+        bool take_fwd;
+        if (i == n0) take_fwd = false;
+        else if (j == n1) take_fwd = true;
+        else {
+            const u32 a = stage_hits[h0 + i], b = stage_hits[h1 + j];
+            // the key orders (genome, diag); the forward strand wins a full tie
+            take_fwd = a > b || (a == b && stage_key[h0 + i] <= stage_key[h1 + j]);
+        }
+        const u64 src = take_fwd ? h0 + i : h1 + j;
+        const u64 key = stage_key[src];
+        genome[o + t] = key_genome(key);
+        diag[o + t] = key_diag(key);
+        hits[o + t] = stage_hits[src];
+        strand[o + t] = take_fwd ? 0 : 1;
+        pair_read[o + t] = (u32)(2 * r + (take_fwd ? 0 : 1));
+        if (take_fwd) i++;
+        else j++;
+    }
+    read_E[r] = read_E2[2 * r];
+}
+
+// Both strands in the per-stage form: the per-stage seeding and counting over
+// the two-strand read set, one merge per read, then the filter on the
+// oriented sequences and the reduce per read.
+static void classify_both_strands(const mt_index &ix, const mt_query_params &q, const mt_seqs &reads,
+                                  ReadBatch &rb, mt_result &res, Timer &tm, hipStream_t s) {
+    const u64 n = reads.n;
+    MT_REQUIRE(n < (1ull << 31), "at most 2^31 - 1 reads per call on both strands");
+    DBuf<u64> off2(2 * n + 1);
+    DBuf<u8> seq2(2 * reads.total);
+    {
+        DBuf<u32> f(1);
+        MT_HIP(hipMemsetAsync(f.p, 0, sizeof(u32), s));
+        k_strand_offsets<<<grid_for(n + 1, 256), 256, 0, s>>>(reads.offsets, n, reads.total, off2.p, f.p);
+        MT_HIP(hipGetLastError());
+        u32 fh = 0;
+        read_back(s, f.p, &fh, sizeof fh);  // the offsets decide every address below
+        check_flags(fh);
+    }
+    if (n) {
+        const unsigned blocks = (unsigned)std::min<u64>(grid_for(n, SR_WPB), 1u << 20);
+        k_strand_reads<<<blocks, 64 * SR_WPB, 0, s>>>((const u8 *)reads.seq, reads.offsets, n, seq2.p);
+        MT_HIP(hipGetLastError());
+    }
+    const mt_seqs two{(const char *)seq2.p, off2.p, 2 * n, 2 * reads.total};
+    rb.prepare(two, q.e_mode, q.e_value, s);
+    tm.mark("pack");
+    StagedCands sc;
+    stage_seed_count(ix, q, two, rb, sc, tm, s);
+    // merge the strands of each read
+    DBuf<u32> nmerged(n);
+    if (n) {
+        k_strand_count<<<grid_for(n, 256), 256, 0, s>>>(sc.ncand.p, n, q.top_n, nmerged.p);
+        MT_HIP(hipGetLastError());
+    }
+    const u64 cap = q.top_n ? std::min<u64>(sc.H, n * (u64)q.top_n) : sc.H;
+    res.alloc_cands(cap);
+    res.strand.alloc(cap);
+    scan_u32(nmerged.p, res.cand_off.p, n, s);
+    DBuf<u32> pair_read(cap);
+    if (n) {
+        k_strand_merge<<<grid_for(n, 256), 256, 0, s>>>(sc.read_hs.p, sc.ncand.p, res.cand_off.p, n, sc.stage_key.p,
+                                                        sc.stage_hits.p, rb.read_E.p, res.genome.p, res.diag.p,
+                                                        res.hits.p, res.strand.p, pair_read.p, res.read_E.p);
+        MT_HIP(hipGetLastError());
+    }
+    tm.mark("compact");
+    stage_filter_reduce(ix, q, two, rb, pair_read.p, cap, sc.max_E, res.read_E.p, res, tm, s);
+    u32 f = 0;
+    read_back(s, rb.flags.p, &f, sizeof f);
+    check_flags(f);
+    read_back(s, res.cand_off.p + n, &res.n_cands, sizeof(u64));
 }
 
 void mt_result_init(mt_result &res, u64 n, u32 n_taxa, hipStream_t s) {
@@ -672,6 +856,10 @@ namespace mt {
 
 void classify_staged(const mt_index &ix, const mt_query_params &q, const mt_seqs &reads, ReadBatch &rb,
                      mt_result &res, Timer &tm, hipStream_t s) {
+    if (q.strands == 2) {
+        classify_both_strands(ix, q, reads, rb, res, tm, s);
+        return;
+    }
     rb.prepare(reads, q.e_mode, q.e_value, s);
     MT_HIP(hipMemcpyAsync(res.read_E.p, rb.read_E.p, (reads.n ? reads.n : 1) * sizeof(u16), hipMemcpyDeviceToDevice,
                           s));
@@ -769,6 +957,18 @@ extern "C" int mt_result_taxa(const mt_result *res, uint32_t *n_taxa, const uint
     if (unique_reads) *unique_reads = res->uniq.p;
     if (multi_reads) *multi_reads = res->multi.p;
     if (unmapped) *unmapped = res->unmapped.p;
+    return MT_OK;
+}
+
+extern "C" int mt_result_strands(const mt_result *res, const uint8_t **strand) {
+    if (!res || !strand) {
+        mt::set_last_error("mt_result_strands: null argument");
+        return MT_EINVAL;
+    }
+    if (res->on_host)
+        *strand = res->h.strand.empty() ? nullptr : res->h.strand.data();
+    else
+        *strand = res->strand.p;
     return MT_OK;
 }
 

@@ -14,6 +14,7 @@ struct mt_result {
     mt::DBuf<mt::u32> hits;
     mt::DBuf<mt::u16> approx;
     mt::DBuf<mt::u8> accept;
+    mt::DBuf<mt::u8> strand;          // both-strand results only (else empty)
     mt::DBuf<mt::u64> uniq, multi;    // n_taxa
     mt::DBuf<mt::u64> unmapped;       // 1
     void alloc_cands(mt::u64 c);
@@ -28,6 +29,7 @@ struct mt_result {
         std::vector<mt::u32> hits;
         std::vector<mt::u16> approx;
         std::vector<mt::u8> accept;
+        std::vector<mt::u8> strand;   // both-strand results only (else empty)
         std::vector<mt::u64> counts;  // unique[n_taxa], multi[n_taxa], unmapped
     } h;
     mt::u64 submit_ns = 0, done_ns = 0;

@@ -918,7 +918,7 @@ static void launch_fused_graph(const FusedLaunch &L, hipStream_t s) {
 
 void classify_fused(const mt_index &ix, const mt_query_params &q, const mt_seqs &reads, ReadBatch &rb,
                     mt_result &res, Timer &tm, hipStream_t s, bool graph) {
-    if (q.filter != MT_FILTER_OBSTACLE) {  // the fused kernel runs the obstacle walk only
+    if (q.filter != MT_FILTER_OBSTACLE || q.strands == 2) {  // the fused kernel: obstacle walk, forward strand
         classify_staged(ix, q, reads, rb, res, tm, s);
         return;
     }

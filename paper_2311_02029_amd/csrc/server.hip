@@ -116,6 +116,7 @@ struct Piece {
     std::vector<u32> hits;
     std::vector<u16> approx;
     std::vector<u8> accept;
+    std::vector<u8> strand;  // both-strand queries only
 };
 
 struct Request {
@@ -151,7 +152,7 @@ struct Batch {
 
 inline bool same_query(const mt_query_params &a, const mt_query_params &b) {
     return a.min_hits == b.min_hits && a.top_n == b.top_n && a.e_mode == b.e_mode && a.e_value == b.e_value &&
-           a.filter == b.filter;
+           a.filter == b.filter && (a.strands == 2) == (b.strands == 2);
 }
 
 // Device bytes a batch holds while it runs: bases and offsets, the read planes
@@ -164,6 +165,8 @@ inline u64 batch_bytes(u64 reads, u64 bases, const mt_query_params &q) {
     const u64 cands = bounded ? q.top_n : 32;
     u64 b = 2 * bases + reads * (64 + 2 * per_cand * cands) + (1ull << 20);
     if (!bounded) b += 24 * bases;
+    // both strands: the two-strand read set and its per-stage arrays
+    if (q.strands == 2) b = 2 * b + 2 * bases + 24 * 2 * bases;
     return b;
 }
 
@@ -314,7 +317,8 @@ void mt_server::run_batch(Batch &b, hipStream_t s, Pinned &h_in, Pinned &h_out, 
     launch_reduce_slots(res, *ix, d_slot, ns, d_cnt, s);
 
     // Outputs back to the host in one pinned block.
-    const u64 out_bytes = (n + 1) * 8 + nc * (8 + 4 + 4 + 2 + 1) + n * (2 + 1) + 64;
+    const bool with_strand = res.strand.p != nullptr;
+    const u64 out_bytes = (n + 1) * 8 + nc * (8 + 4 + 4 + 2 + 1 + 1) + n * (2 + 1) + 64;
     h_out.ensure(out_bytes);
     u8 *o = h_out.p;
     u64 *co = (u64 *)o;
@@ -325,6 +329,7 @@ void mt_server::run_batch(Batch &b, hipStream_t s, Pinned &h_in, Pinned &h_out, 
     u16 *re = ap + nc;
     u8 *ac = (u8 *)(re + n);
     u8 *ra = ac + nc;
+    u8 *sd = ra + n;
     MT_HIP(hipMemcpyAsync(co, res.cand_off.p, (n + 1) * 8, hipMemcpyDeviceToHost, s));
     if (nc) {
         MT_HIP(hipMemcpyAsync(dg, res.diag.p, nc * 8, hipMemcpyDeviceToHost, s));
@@ -332,6 +337,7 @@ void mt_server::run_batch(Batch &b, hipStream_t s, Pinned &h_in, Pinned &h_out, 
         MT_HIP(hipMemcpyAsync(ht, res.hits.p, nc * 4, hipMemcpyDeviceToHost, s));
         MT_HIP(hipMemcpyAsync(ap, res.approx.p, nc * 2, hipMemcpyDeviceToHost, s));
         MT_HIP(hipMemcpyAsync(ac, res.accept.p, nc, hipMemcpyDeviceToHost, s));
+        if (with_strand) MT_HIP(hipMemcpyAsync(sd, res.strand.p, nc, hipMemcpyDeviceToHost, s));
     }
     MT_HIP(hipMemcpyAsync(re, res.read_E.p, n * 2, hipMemcpyDeviceToHost, s));
     MT_HIP(hipMemcpyAsync(ra, res.read_accepted.p, n, hipMemcpyDeviceToHost, s));
@@ -352,6 +358,7 @@ void mt_server::run_batch(Batch &b, hipStream_t s, Pinned &h_in, Pinned &h_out, 
         pc.hits.assign(ht + c0, ht + c1);
         pc.approx.assign(ap + c0, ap + c1);
         pc.accept.assign(ac + c0, ac + c1);
+        if (with_strand) pc.strand.assign(sd + c0, sd + c1);
     }
 }
 
@@ -382,6 +389,7 @@ void mt_server::finish(Request *r, const u64 *counts) {
                 h.hits = std::move(pc.hits);
                 h.approx = std::move(pc.approx);
                 h.accept = std::move(pc.accept);
+                h.strand = std::move(pc.strand);
             } else {
                 h.cand_off.reserve(r->n + 1);
                 h.cand_off.push_back(0);
@@ -396,6 +404,7 @@ void mt_server::finish(Request *r, const u64 *counts) {
                     h.hits.insert(h.hits.end(), pc.hits.begin(), pc.hits.end());
                     h.approx.insert(h.approx.end(), pc.approx.begin(), pc.approx.end());
                     h.accept.insert(h.accept.end(), pc.accept.begin(), pc.accept.end());
+                    h.strand.insert(h.strand.end(), pc.strand.begin(), pc.strand.end());
                 }
             }
             if (h.cand_off.size() != r->n + 1) throw Error(MT_EINTERNAL, "served pieces do not cover the request");

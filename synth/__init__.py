@@ -215,6 +215,27 @@ def inject_n(rng, s: SeqSet, p: float) -> SeqSet:
     return SeqSet(seq=seq, offsets=s.offsets.copy())
 
 
+def from_reverse_strand(rng, s: SeqSet, frac: float = 0.5) -> SeqSet:
+    """Copy of s in which a random `frac` of the reads are replaced by their
+    reverse complement, as if sequenced from the other strand of the genome
+    (vectorised over the whole set: one gather of the reversed positions and a
+    byte lookup for the complement)."""
+    flip = rng.random(s.n) < frac
+    lens = np.diff(s.offsets.astype(np.int64))
+    start = s.offsets[:-1].astype(np.int64)
+    idx = np.arange(len(s.seq), dtype=np.int64)
+    read_of = np.repeat(np.arange(s.n), lens)
+    flipped = flip[read_of] if s.n else np.zeros(0, bool)
+    src = idx.copy()
+    src[flipped] = (2 * start[read_of[flipped]] + lens[read_of[flipped]] - 1) - idx[flipped]
+    table = np.arange(256, dtype=np.uint8)
+    for a, b in (b"AT", b"TA", b"CG", b"GC", b"at", b"ta", b"cg", b"gc"):
+        table[a] = b
+    seq = s.seq[src].copy()
+    seq[flipped] = table[seq[flipped]]
+    return SeqSet(seq=seq, offsets=s.offsets.copy())
+
+
 # ---------------------------------------------------------------------------
 # The paper-shaped workloads.  Each returns (genomes, reads, params dict).
 # ---------------------------------------------------------------------------

@@ -105,6 +105,38 @@ def test_sampled_reads_match_oracle(full):
         assert a.shape == b.shape and np.array_equal(a.astype(b.dtype), b), f
 
 
+def test_both_strands_full_size(full):
+    """Both strands at full size (half the reads taken from the reverse strand),
+    per-stage over the two-strand read set: a seeded sample against the oracle,
+    and on every read the canonical order with the strand as the last key and
+    accept == (approx <= E)."""
+    import paper_2311_02029_amd as mt
+    reads = synth.from_reverse_strand(np.random.default_rng(77), full["reads"], 0.5)
+    res = full["ix"].classify(mt.to_device(reads), min_hits=3, top_n=3, e_value=7, strands=2)
+    got = res.to_host()
+    res.free()
+    idx = np.sort(np.random.default_rng(2025).choice(reads.n, 2000, replace=False))
+    ref = full["oracle"]().classify(reads.subset(idx), 3, 3, 0, 7, strands=2)
+    co = got["cand_offsets"].astype(np.int64)
+    sl = np.concatenate([np.arange(co[r], co[r + 1]) for r in idx])
+    for f in ("genome", "diag", "hits", "approx", "accept", "strand"):
+        assert np.array_equal(got[f][sl], ref[f]), f
+    assert np.array_equal(np.diff(co)[idx], np.diff(ref["cand_offsets"].astype(np.int64)))
+    assert np.array_equal(got["read_accepted"][idx], ref["read_accepted"])
+    nc = np.diff(co)
+    same = np.repeat(np.arange(len(nc)), nc)
+    nxt = np.flatnonzero(same[1:] == same[:-1])
+    key = np.stack([-got["hits"].astype(np.int64), got["genome"].astype(np.int64), got["diag"],
+                    got["strand"].astype(np.int64)], 1)
+    a, b = key[nxt], key[nxt + 1]
+    diff = a != b
+    first = np.argmax(diff, 1)
+    assert diff.any(1).all() and (a[np.arange(len(a)), first] < b[np.arange(len(b)), first]).all()
+    E = np.repeat(got["read_E"], nc)
+    assert np.array_equal(got["accept"], (got["approx"] <= E).astype(np.uint8))
+    assert got["read_accepted"].mean() > 0.97 and 0.4 < got["strand"].mean() < 0.6
+
+
 def test_properties_at_full_size(full):
     res = full["fused"]
     co = res["cand_offsets"].astype(np.int64)
