@@ -75,6 +75,9 @@ def _declare(lib):
                                          C.c_uint32, u16p, u8p]
     lib.or_containment.restype = C.c_int
     lib.or_containment.argtypes = [C.c_void_p, u8p, u64p, C.c_uint64, u64p]
+    lib.or_abundance.restype = C.c_int64
+    lib.or_abundance.argtypes = [C.c_uint64, u64p, u32p, u16p, u8p, u32p, C.c_uint32, C.c_uint64, C.c_uint64,
+                                 u64p, C.POINTER(C.c_double)]
     lib.or_select_genomes.restype = C.c_int64
     lib.or_select_genomes.argtypes = [u64p, C.c_uint64, C.c_uint64, C.c_uint64, u32p, u64p]
     return lib
@@ -235,3 +238,23 @@ def select_genomes(hits, num: int = 1, den: int = 10_000, lib=None):
     if c < 0:
         raise ValueError("cutoff denominator must be nonzero")
     return sel[:c].copy(), int(mx[0])
+
+
+def abundance(res: dict, taxon, n_taxa: int, num: int = 1, den: int = 10_000, lib=None):
+    """Stage 3b (reading O16, parity unpinned): per-taxon counts in units of
+    2^-32 read, relative abundances and the number of taxa kept at the cutoff,
+    from a classification result dict (cand_offsets, genome, approx, accept)."""
+    lib = lib or load()
+    co = np.ascontiguousarray(res["cand_offsets"], dtype=np.uint64)
+    g = np.ascontiguousarray(res["genome"], dtype=np.uint32)
+    ap = np.ascontiguousarray(res["approx"], dtype=np.uint16)
+    ac = np.ascontiguousarray(res["accept"], dtype=np.uint8)
+    tx = np.ascontiguousarray(taxon, dtype=np.uint32)
+    counts = np.zeros(max(n_taxa, 1), np.uint64)
+    ab = np.zeros(max(n_taxa, 1), np.float64)
+    kept = lib.or_abundance(len(co) - 1, _p(co, C.c_uint64), _p(g, C.c_uint32), _p(ap, C.c_uint16),
+                            _p(ac, C.c_uint8), _p(tx, C.c_uint32), n_taxa, num, den, _p(counts, C.c_uint64),
+                            ab.ctypes.data_as(C.POINTER(C.c_double)))
+    if kept < 0:
+        raise ValueError("cutoff denominator must be nonzero")
+    return counts[:n_taxa], ab[:n_taxa], int(kept)

@@ -86,6 +86,17 @@
  *       (hits desc, genome asc, diag asc, strand asc), one top_n over the
  *       union.  The filter of a strand-1 location runs on R.  With one strand
  *       (the default) only strand 0 exists.
+ *   O16 relative abundance (Fig. 1 step 3b; PARITY UNPINNED: the paper takes
+ *       the apportionment from Metalign and does not state it): with T(r) the
+ *       mapped taxa of read r (O8) and u_t the unique-read count of taxon t,
+ *       the count of t in units of 2^-32 read is 2^32 * u_t plus, for every
+ *       multi-mapped read r with t in T(r), floor(2^32 * u_t / U_r) where U_r
+ *       is the sum of u over T(r), or floor(2^32 / |T(r)|) when U_r = 0 (one
+ *       proportional step from the unique evidence).  With C the sum of the
+ *       counts, taxon t is kept iff count_t * den >= C * num (the paper drops
+ *       taxa below 0.01%: num/den = 1/10^4), and its abundance is count_t / K
+ *       in double precision with K the sum over kept taxa; dropped taxa (and
+ *       every taxon when C = 0) get 0.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -778,4 +789,65 @@ int64_t or_select_genomes(const uint64_t *hits, uint64_t n, uint64_t num, uint64
     for (uint64_t g = 0; g < n; g++)
         if ((unsigned __int128)hits[g] * den > (unsigned __int128)M * num) selected[c++] = (uint32_t)g;
     return c;
+}
+
+/* ------------------------------------------------ stage 3b abundance ---- */
+
+/*
+ * Relative abundance from a classification's candidates (reading O16):
+ * cand_offsets[n_reads + 1], genome / approx / accept per candidate,
+ * taxon_of_genome.  counts (n_taxa, units of 2^-32 read) and abund (n_taxa)
+ * receive the results.  Returns the number of kept taxa, -1 when den is 0.
+ */
+int64_t or_abundance(uint64_t n_reads, const uint64_t *cand_offsets, const uint32_t *genome, const uint16_t *approx,
+                     const uint8_t *accept, const uint32_t *taxon_of_genome, uint32_t n_taxa, uint64_t num,
+                     uint64_t den, uint64_t *counts, double *abund)
+{
+    if (den == 0) return -1;
+    uint64_t *unique = calloc(n_taxa ? n_taxa : 1, sizeof *unique);
+    uint32_t *set = malloc(sizeof *set * (n_taxa ? n_taxa : 1));
+    memset(counts, 0, sizeof *counts * n_taxa);
+    for (int pass = 0; pass < 2; pass++) {
+        for (uint64_t r = 0; r < n_reads; r++) {
+            /* the read's mapped taxa (O8): distinct taxa of accepted candidates at the best value */
+            int best = -1;
+            for (uint64_t c = cand_offsets[r]; c < cand_offsets[r + 1]; c++)
+                if (accept[c] && (best < 0 || approx[c] < best)) best = approx[c];
+            if (best < 0) continue;
+            uint32_t nt = 0;
+            for (uint64_t c = cand_offsets[r]; c < cand_offsets[r + 1]; c++) {
+                if (!accept[c] || approx[c] != best) continue;
+                uint32_t t = taxon_of_genome[genome[c]], seen = 0;
+                for (uint32_t i = 0; i < nt; i++) seen |= set[i] == t;
+                if (!seen) set[nt++] = t;
+            }
+            if (pass == 0) {                 /* unique-read counts u_t */
+                if (nt == 1) unique[set[0]]++;
+                continue;
+            }
+            if (nt == 1) {
+                counts[set[0]] += (uint64_t)1 << 32;
+                continue;
+            }
+            uint64_t U = 0;
+            for (uint32_t i = 0; i < nt; i++) U += unique[set[i]];
+            for (uint32_t i = 0; i < nt; i++)
+                counts[set[i]] += U ? (uint64_t)(((unsigned __int128)unique[set[i]] << 32) / U)
+                                    : ((uint64_t)1 << 32) / nt;
+        }
+    }
+    unsigned __int128 C = 0, K = 0;
+    for (uint32_t t = 0; t < n_taxa; t++) C += counts[t];
+    int64_t kept = 0;
+    for (uint32_t t = 0; t < n_taxa; t++) {
+        int keep = C > 0 && (unsigned __int128)counts[t] * den >= C * num;
+        if (keep) { K += counts[t]; kept++; }
+    }
+    for (uint32_t t = 0; t < n_taxa; t++) {
+        int keep = C > 0 && (unsigned __int128)counts[t] * den >= C * num;
+        abund[t] = keep ? (double)counts[t] / (double)(uint64_t)K : 0.0;
+    }
+    free(unique);
+    free(set);
+    return kept;
 }

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "oracle", "oracle.c")
 PIN_FILES = [os.path.join(ROOT, "tests", f)
              for f in ("test_oracle_pins.py", "test_oracle_containment.py", "test_oracle_filters.py",
-                       "test_oracle_strands.py")]
+                       "test_oracle_strands.py", "test_oracle_abundance.py")]
 
 # (name, original text, planted mistake); each original occurs exactly once.
 MUTANTS = [
@@ -42,6 +42,13 @@ MUTANTS = [
     ("complement without reverse", "uint8_t c = q[m - 1 - j];", "uint8_t c = q[j];"),
     ("strands merged in counting", "hit[j].strand == hit[i].strand)", "1)"),
     ("strand-1 filter on the read", "filter_codes(kind, oriented[cand[c].strand], m,", "filter_codes(kind, oriented[0], m,"),
+    ("abundance ignores unique evidence",
+     "counts[set[i]] += U ? (uint64_t)(((unsigned __int128)unique[set[i]] << 32) / U)\n                                    : ((uint64_t)1 << 32) / nt;",
+     "counts[set[i]] += ((uint64_t)1 << 32) / nt;"),
+    ("abundance cutoff strict", "int keep = C > 0 && (unsigned __int128)counts[t] * den >= C * num;\n        if (keep)",
+     "int keep = C > 0 && (unsigned __int128)counts[t] * den > C * num;\n        if (keep)"),
+    ("multi reads counted as unique", "if (nt == 1) unique[set[0]]++;", "unique[set[0]]++;"),
+    ("abundance over all taxa", "if (keep) { K += counts[t]; kept++; }", "K += counts[t]; if (keep) kept++;"),
     ("top_n off by one", "if (top_n > 0 && nc > (int64_t)top_n) nc = top_n;",
      "if (top_n > 0 && nc > (int64_t)top_n + 1) nc = top_n + 1;"),
     ("N is a fifth letter", "    if (qc == 4) return 1;\n    if (p < 0 || p >= glen) return 1;\n    uint8_t rc = gcode[p];\n    if (rc == 4) return 1;",
