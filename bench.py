@@ -490,32 +490,51 @@ def main() -> int:
         filters["pairs"] = int(len(pr))
         log(f"[bench] filters on the pair stream (mt_filter_pairs_kind, incl. read packing): {json.dumps(filters)}")
 
+    # Stage 3b (relative abundance) on the batch's classification result.
+    abundance = None
+    if args.workload == "batched":
+        r = ix.classify(dreads, **q)
+        ix.abundance(r)  # warm
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(5):
+            counts, ab, kept = ix.abundance(r)
+        torch.cuda.synchronize()
+        a_ms = (time.perf_counter() - t) * 1000.0 / 5
+        abundance = {"ms": round(a_ms, 3), "reads_per_s": round(reads.n / (a_ms / 1000.0), 1), "kept_taxa": kept,
+                     "max_abundance": round(float(ab.max().item()), 6)}
+        r.free()
+        log(f"[bench] abundance (mt_abundance on the classification result): {json.dumps(abundance)}")
+
     # Both strands: the batch with half its reads taken from the reverse strand.
     strands = None
     if args.workload == "batched" and args.strands_bench:
         flipped = synth.from_reverse_strand(np.random.default_rng(77), reads, 0.5)
         dflip = mt.to_device(flipped)
         one = ix.classify(dflip, **q).to_host()
-        r = ix.classify(dflip, **dict(q, mode=mt.MT_MODE_PER_STAGE), strands=2)  # warm
-        r.free()
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(3):
-            r = ix.classify(dflip, **dict(q, mode=mt.MT_MODE_PER_STAGE), strands=2)
-            torch.cuda.synchronize()
-            nc2 = r.n_cands
+        strands = {}
+        for name, m in (("fused", q["mode"]), ("per_stage", mt.MT_MODE_PER_STAGE)):
+            r = ix.classify(dflip, **dict(q, mode=m), strands=2)  # warm
             r.free()
-        s_ms = (time.perf_counter() - t) * 1000.0 / 3
-        r = ix.classify(dflip, **dict(q, mode=mt.MT_MODE_PER_STAGE), strands=2)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(3):
+                r = ix.classify(dflip, **dict(q, mode=m), strands=2)
+                torch.cuda.synchronize()
+                nc2 = r.n_cands
+                r.free()
+            s_ms = (time.perf_counter() - t) * 1000.0 / 3
+            strands[name] = {"ms": round(s_ms, 3), "reads_per_s": round(flipped.n / (s_ms / 1000.0), 1),
+                             "pairs_per_s": round(nc2 / (s_ms / 1000.0), 1)}
+        r = ix.classify(dflip, **q, strands=2)
         two = r.to_host()
         r.free()
-        strands = {"ms": round(s_ms, 3), "reads_per_s": round(flipped.n / (s_ms / 1000.0), 1),
-                   "pairs_per_s": round(nc2 / (s_ms / 1000.0), 1), "pairs": int(nc2),
-                   "accepted_both": round(float(two["read_accepted"].mean()), 4),
-                   "accepted_forward_only": round(float(one["read_accepted"].mean()), 4),
-                   "reverse_cands": round(float(two["strand"].mean()), 4)}
+        strands.update({"pairs": int(len(two["genome"])),
+                        "accepted_both": round(float(two["read_accepted"].mean()), 4),
+                        "accepted_forward_only": round(float(one["read_accepted"].mean()), 4),
+                        "reverse_cands": round(float(two["strand"].mean()), 4)})
         del dflip
-        log(f"[bench] both strands (per-stage over the two-strand read set): {json.dumps(strands)}")
+        log(f"[bench] both strands (two-strand read set; fused kernel / per-stage chain): {json.dumps(strands)}")
 
     serving = None
     if pool is not None:
@@ -552,6 +571,7 @@ def main() -> int:
         "containment": containment,
         "filters": filters,
         "strands": strands,
+        "abundance": abundance,
         "serving": serving,
     }
     print(json.dumps(out), flush=True)

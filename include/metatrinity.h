@@ -189,6 +189,24 @@ int mt_result_taxa(const mt_result *res, uint32_t *n_taxa, const uint64_t **uniq
  * candidates of both strands are ordered together by (hits descending, genome,
  * diag, strand ascending) and one top_n cut applies to the union. */
 int mt_result_strands(const mt_result *res, const uint8_t **strand);
+
+/* Relative abundance of the taxa (Fig. 1 step 3b) from a classification
+ * result made with this index (device or served).  The paper takes the
+ * apportionment of multi-mapped reads from Metalign without stating it; the
+ * rule here: with u_t the unique reads of taxon t and T(r) the mapped taxa of
+ * a multi-mapped read r (mt_result_taxa's rule),
+ *   counts[t] = 2^32 u_t + sum over multi-mapped r with t in T(r) of
+ *               floor(2^32 u_t / U_r),  U_r = sum of u over T(r)
+ *               (floor(2^32 / |T(r)|) when U_r = 0),
+ * in units of 2^-32 read (exact integers); a taxon is kept iff
+ * counts[t] * cutoff_den >= (sum of counts) * cutoff_num (the paper drops taxa
+ * below 0.01%: 1 / 10000); abundance[t] = counts[t] / (sum of kept counts) as
+ * a correctly rounded double, 0 for dropped taxa and when no read is mapped.
+ * counts (uint64) and abundance (double): device arrays of n_taxa entries;
+ * *n_kept (host) receives the number of kept taxa.  Errors: null arguments,
+ * cutoff_den = 0, a result whose taxon count differs from the index's. */
+int mt_abundance(const mt_index *index, const mt_result *res, uint64_t cutoff_num, uint64_t cutoff_den,
+                 uint64_t *counts, double *abundance, uint64_t *n_kept, void *stream);
 int mt_result_free(mt_result *res);
 
 /* Per-launch kernel timings of the last mt_classify on this thread (ms,

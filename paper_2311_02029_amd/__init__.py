@@ -289,6 +289,18 @@ class Index:
                self.lib)
         return hits[:n]
 
+    def abundance(self, result: "Result", num: int = 1, den: int = 10_000, stream=None):
+        """Stage 3b (mt_abundance): (counts in units of 2^-32 read as a device int64
+        tensor holding uint64, abundances as a device float64 tensor, kept taxa)."""
+        torch = _torch()
+        n = self.n_taxa
+        counts = torch.empty(max(n, 1), dtype=torch.int64, device="cuda")
+        ab = torch.empty(max(n, 1), dtype=torch.float64, device="cuda")
+        kept = C.c_uint64()
+        _check(self.lib.mt_abundance(self.h, result.h, num, den, counts.data_ptr(), ab.data_ptr(),
+                                     C.byref(kept), _stream_ptr(stream)), self.lib)
+        return counts[:n], ab[:n], kept.value
+
     def classify(self, reads: DeviceSeqs, min_hits=3, top_n=3, e_mode=MT_E_FIXED, e_value=7,
                  mode=MT_MODE_PER_STAGE, stream=None, filter_kind=MT_FILTER_OBSTACLE, strands=1) -> Result:
         """mt_classify; strands=2 adds the reverse strand of every genome."""

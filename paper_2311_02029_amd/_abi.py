@@ -22,7 +22,7 @@ ABI_FUNCTIONS = (
     "mt_filter_pairs", "mt_trim", "mt_last_error", "mt_abi_version", "mt_last_stats", "mt_server_create",
     "mt_server_submit", "mt_server_wait", "mt_server_destroy", "mt_result_on_host", "mt_result_times",
     "mt_tune_buckets", "mt_tune_info", "mt_tune_set", "mt_tune_reset", "mt_autotune", "mt_tune_save",
-    "mt_tune_load", "mt_containment", "mt_select_genomes", "mt_filter_pairs_kind",
+    "mt_tune_load", "mt_containment", "mt_select_genomes", "mt_filter_pairs_kind", "mt_abundance",
 )
 
 
@@ -87,6 +87,7 @@ def load(path: str = LIB_PATH):
         "mt_result_reads": (i32, [vp, C.POINTER(u64), pp, pp, pp]),
         "mt_result_cands": (i32, [vp, C.POINTER(u64), pp, pp, pp, pp, pp]),
         "mt_result_strands": (i32, [vp, pp]),
+        "mt_abundance": (i32, [vp, vp, u64, u64, vp, vp, C.POINTER(u64), vp]),
         "mt_result_taxa": (i32, [vp, C.POINTER(u32), pp, pp, pp]),
         "mt_result_free": (i32, [vp]),
         "mt_last_timings": (i32, [C.POINTER(C.c_char_p), C.POINTER(C.c_float), u32, C.POINTER(u32)]),

@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 OUT = os.path.join(PKG, "libmetatrinity.so")
-SOURCES = ["runtime.hip", "seq.hip", "index.hip", "classify.hip", "filter.hip", "fused.hip", "server.hip", "tune.hip", "contain.hip"]
+SOURCES = ["runtime.hip", "seq.hip", "index.hip", "classify.hip", "filter.hip", "fused.hip", "server.hip", "tune.hip", "contain.hip",
+           "abundance.hip"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", os.path.join(ROOT, "include")]

@@ -767,9 +767,95 @@ __global__ void k_strand_merge(const u64 *__restrict__ read_hs, const u32 *__res
     read_E[r] = read_E2[2 * r];
 }
 
-// Both strands in the per-stage form: the per-stage seeding and counting over
-// the two-strand read set, one merge per read, then the filter on the
-// oriented sequences and the reduce per read.
+// Candidates kept per read from a finished two-strand result (its read 2r is
+// read r, 2r + 1 the reverse complement): the union, cut at top_n.
+__global__ void k_strand_count_done(const u64 *__restrict__ cand_off2, u64 n, u32 top_n,
+                                    u32 *__restrict__ nmerged) {
+    const u64 r = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const u64 c = cand_off2[2 * r + 2] - cand_off2[2 * r];
+    nmerged[r] = top_n && c > top_n ? top_n : (u32)c;
+}
+
+// k_strand_merge over filtered lists: the filter values travel with their
+// candidates (a candidate's value does not depend on the others).
+__global__ void k_strand_merge_done(const u64 *__restrict__ cand_off2, u64 n, const u32 *__restrict__ genome2,
+                                    const i64 *__restrict__ diag2, const u32 *__restrict__ hits2,
+                                    const u16 *__restrict__ approx2, const u8 *__restrict__ accept2,
+                                    const u16 *__restrict__ read_E2, const u64 *__restrict__ cand_off,
+                                    u32 *__restrict__ genome, i64 *__restrict__ diag, u32 *__restrict__ hits,
+                                    u16 *__restrict__ approx, u8 *__restrict__ accept, u8 *__restrict__ strand,
+                                    u16 *__restrict__ read_E) {
+    const u64 r = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    u64 i = cand_off2[2 * r], j = cand_off2[2 * r + 1];
+    const u64 e0 = j, e1 = cand_off2[2 * r + 2];
+    const u64 o = cand_off[r], cnt = cand_off[r + 1] - o;
+    for (u64 t = 0; t < cnt; t++) {
+        bool take_fwd;
+        if (i == e0) take_fwd = false;
+        else if (j == e1) take_fwd = true;
+        else {
+            const u32 a = hits2[i], b = hits2[j];
+            const u32 ga = genome2[i], gb = genome2[j];
+            take_fwd = a > b || (a == b && (ga < gb || (ga == gb && diag2[i] <= diag2[j])));
+        }
+        const u64 src = take_fwd ? i : j;
+        genome[o + t] = genome2[src];
+        diag[o + t] = diag2[src];
+        hits[o + t] = hits2[src];
+        approx[o + t] = approx2[src];
+        accept[o + t] = accept2[src];
+        strand[o + t] = take_fwd ? 0 : 1;
+        if (take_fwd) i++;
+        else j++;
+    }
+    read_E[r] = read_E2[2 * r];
+}
+
+// Both strands with the obstacle walk in a fused mode: the fused kernel over
+// the two-strand read set (each orientation keeps its own top_n and is
+// filtered), then one merge per read and the reduce per read.
+static void both_strands_fused(const mt_index &ix, const mt_query_params &q, const mt_seqs &two, ReadBatch &rb,
+                               mt_result &res, Timer &tm, hipStream_t s) {
+    const u64 n = res.n_reads;
+    mt_query_params q1 = q;
+    q1.strands = 1;
+    mt_result r2;
+    mt_result_init(r2, two.n, ix.n_taxa, s);
+    classify_fused(ix, q1, two, rb, r2, tm, s, q.mode == MT_MODE_FUSED_GRAPH);
+    DBuf<u32> nmerged(n);
+    if (n) {
+        k_strand_count_done<<<grid_for(n, 256), 256, 0, s>>>(r2.cand_off.p, n, q.top_n, nmerged.p);
+        MT_HIP(hipGetLastError());
+    }
+    scan_u32(nmerged.p, res.cand_off.p, n, s);
+    u64 total = 0;
+    read_back(s, res.cand_off.p + n, &total, sizeof total);
+    res.alloc_cands(total);
+    res.strand.alloc(total);
+    if (n) {
+        k_strand_merge_done<<<grid_for(n, 256), 256, 0, s>>>(
+            r2.cand_off.p, n, r2.genome.p, r2.diag.p, r2.hits.p, r2.approx.p, r2.accept.p, r2.read_E.p,
+            res.cand_off.p, res.genome.p, res.diag.p, res.hits.p, res.approx.p, res.accept.p, res.strand.p,
+            res.read_E.p);
+        MT_HIP(hipGetLastError());
+        tm.mark("merge");
+        const unsigned blocks = std::min<u64>(grid_for(n, RED_TPB), (u64)count_blocks() / 2);
+        k_reduce<<<blocks, RED_TPB, 0, s>>>(res.cand_off.p, n, res.genome.p, res.approx.p, res.read_E.p,
+                                            ix.taxon.p, ix.n_taxa, res.read_accepted.p,
+                                            (unsigned long long *)res.uniq.p, (unsigned long long *)res.multi.p,
+                                            (unsigned long long *)res.unmapped.p);
+        MT_HIP(hipGetLastError());
+        tm.mark("reduce");
+    }
+    res.n_cands = total;
+}
+
+// Both strands: reads and their reverse complements as one read set.  The
+// obstacle walk in a fused mode goes through the fused kernel; otherwise the
+// per-stage seeding and counting over the two-strand set, one merge per read,
+// then the filter on the oriented sequences and the reduce per read.
 static void classify_both_strands(const mt_index &ix, const mt_query_params &q, const mt_seqs &reads,
                                   ReadBatch &rb, mt_result &res, Timer &tm, hipStream_t s) {
     const u64 n = reads.n;
@@ -791,6 +877,11 @@ static void classify_both_strands(const mt_index &ix, const mt_query_params &q, 
         MT_HIP(hipGetLastError());
     }
     const mt_seqs two{(const char *)seq2.p, off2.p, 2 * n, 2 * reads.total};
+    if (q.mode != MT_MODE_PER_STAGE && q.filter == MT_FILTER_OBSTACLE) {
+        tm.mark("pack");
+        both_strands_fused(ix, q, two, rb, res, tm, s);
+        return;
+    }
     rb.prepare(two, q.e_mode, q.e_value, s);
     tm.mark("pack");
     StagedCands sc;

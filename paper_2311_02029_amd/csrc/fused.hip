@@ -48,7 +48,7 @@ constexpr int F_QCAP = 4;        // queued (read, candidate) pairs per wave: one
 constexpr int F_PCAP = 8;        // reads per wave waiting for their filter results
 constexpr int F_WORDS = F_MAX_M / 16 + 2;  // 2-bit stream words (16 bases per word) + padding
 
-enum : u32 { ST_READS, ST_BASES, ST_MINS, ST_WBLOCKS, ST_CANDS, ST_COUNT };
+enum : u32 { ST_READS, ST_BASES, ST_MINS, ST_WBLOCKS, ST_CANDS, ST_UNMAPPED, ST_COUNT };
 
 struct FusedArgs {
     const u8 *seq;
@@ -293,14 +293,14 @@ __device__ inline void filter_batch(const FusedArgs &a, const QEntry *q, int qn,
 // Read accept flag and per-taxon counts of a read whose candidates are all
 // filtered: the distinct taxa of its accepted candidates with the smallest
 // count; one taxon is unique, several are multi-mapped.
-__device__ inline void finalize_read(const FusedArgs &a, const PendRead &pr) {
+__device__ inline void finalize_read(const FusedArgs &a, const PendRead &pr, u64 *wst) {
     const int nc = (int)pr.nc, E = pr.E;
     int best = 0x7fffffff;
     for (int c = 0; c < nc; c++)
         if (pr.apx[c] <= E && pr.apx[c] < best) best = pr.apx[c];
     if (best == 0x7fffffff) {
         KA(read_accepted)[pr.r] = 0;
-        atomicAdd(KA(unmapped), 1ull);
+        atomicAdd(&wst[ST_UNMAPPED], 1ull);  // the block adds its count once at the end
         return;
     }
     KA(read_accepted)[pr.r] = 1;
@@ -330,7 +330,7 @@ __device__ inline void finalize_read(const FusedArgs &a, const PendRead &pr) {
 // finalizes every pending read whose last candidate it filtered.  Returns the
 // new set of used pending slots.
 __device__ inline u32 flush_queue(const FusedArgs &a, QEntry *q, int &qn, int qG, PendRead *pend, u32 used,
-                                  int lane) {
+                                  int lane, u64 *wst) {
     if (qn > 0) {
         if (qG == 16)
             filter_batch<16>(a, q, qn, pend, lane);
@@ -345,7 +345,7 @@ __device__ inline u32 flush_queue(const FusedArgs &a, QEntry *q, int &qn, int qG
         qn = 0;
     }
     bool done = lane < F_PCAP && ((used >> lane) & 1u) && pend[lane].left == 0;
-    if (done) finalize_read(a, pend[lane]);
+    if (done) finalize_read(a, pend[lane], wst);
     u32 fin = (u32)ballot64(done);
     wave_sync();
     return used & ~fin;
@@ -652,7 +652,7 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
         if (nc == 0) {
             if (lane == 0) {
                 KA(read_accepted)[r] = 0;
-                atomicAdd(KA(unmapped), 1ull);
+                atomicAdd(&wst[ST_UNMAPPED], 1ull);
             }
         } else {
             const int rows = 2 * E + 1;
@@ -669,7 +669,7 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
             // one flush site: the queue is flushed when it is full or holds
             // pairs of another group size
             for (int c = 0; c < nc; c++) {
-                if (qn > 0 && (qn == 64 / qG || qG != G)) used = flush_queue(a, queue, qn, qG, pend, used, lane);
+                if (qn > 0 && (qn == 64 / qG || qG != G)) used = flush_queue(a, queue, qn, qG, pend, used, lane, wst);
                 qG = G;
                 if (lane == 0) {
                     u32 si = sel[c];
@@ -689,7 +689,7 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
         cur = nxt;
         wave_sync();
     }
-    used = flush_queue(a, queue, qn, qG, pend, used, lane);
+    used = flush_queue(a, queue, qn, qG, pend, used, lane, wst);
     if (lane == 0) {
         if (used) wflags |= ERR_INTERNAL;  // every queued read is finalized by now
         if (wflags) atomicOr(KA(flags), wflags);
@@ -700,6 +700,8 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
         u64 t = 0;
         for (int w = 0; w < F_WPB; w++) t += sh_stats[w][threadIdx.x];
         KA(stats_part)[(u64)blockIdx.x * ST_COUNT + threadIdx.x] = t;
+        // unmapped reads: one global atomic per block instead of one per read
+        if (threadIdx.x == ST_UNMAPPED && t) atomicAdd(KA(unmapped), (unsigned long long)t);
     }
 }
 
