@@ -189,6 +189,7 @@ __device__ inline int long_walk(const u64x2 *L, const u64 *NB, const u64x2 *WL, 
     const int rows = 2 * E + 1;
     const int S = (rows + 63) / 64;
     const int r0 = min(lane * S, rows), r1 = min(r0 + S, rows);
+    const int SC = min(32, S);
     int j = 0, c = 0;
     for (;;) {
         // 32 read bases from j (one alignbit per plane)
@@ -212,35 +213,49 @@ __device__ inline int long_walk(const u64x2 *L, const u64 *NB, const u64x2 *WL, 
                 n2 = nb_dw(WN, k0 + 2);
             }
             const int cnt = min(32, r1 - s0);
-            const int split = min(cnt, 32 - (int)sh0);  // rows whose window starts in dword k0
-            for (int i = 0; i < cnt; i++) {
-                u32 wl, wh, wn;
-                if (i < split) {
-                    const u32 sh = sh0 + (u32)i;
-                    wl = __builtin_amdgcn_alignbit(l1, l0, sh);
-                    wh = __builtin_amdgcn_alignbit(h1, h0, sh);
-                    wn = kWithN ? __builtin_amdgcn_alignbit(n1, n0, sh) : 0u;
-                } else {
-                    const u32 sh = sh0 + (u32)i - 32u;
-                    wl = __builtin_amdgcn_alignbit(l2, l1, sh);
-                    wh = __builtin_amdgcn_alignbit(h2, h1, sh);
-                    wn = kWithN ? __builtin_amdgcn_alignbit(n2, n1, sh) : 0u;
-                }
+            // Bits [sh0, sh0 + 64) of the three dwords: row i's 32 window
+            // bases are bits [i, i + 32) of them, one alignbit per plane.
+            const u32 xl0 = __builtin_amdgcn_alignbit(l1, l0, sh0), xl1 = __builtin_amdgcn_alignbit(l2, l1, sh0);
+            const u32 xh0 = __builtin_amdgcn_alignbit(h1, h0, sh0), xh1 = __builtin_amdgcn_alignbit(h2, h1, sh0);
+            u32 xn0 = 0, xn1 = 0;
+            if constexpr (kWithN) {
+                xn0 = __builtin_amdgcn_alignbit(n1, n0, sh0);
+                xn1 = __builtin_amdgcn_alignbit(n2, n1, sh0);
+            }
+            // The rows without branches (a divergent branch costs scalar
+            // exec-mask instructions): the trip count is the wave's rows per
+            // lane, and rows past the lane's last repeat its last row, which
+            // leaves the maximum unchanged.  Rows whose 32 columns all match
+            // are marked in `full` and continued afterwards.
+            u32 full = 0, bmax = 0;
+#pragma unroll 4
+            for (int i = 0; i < SC; i++) {
+                const u32 ie = (u32)min(i, cnt - 1);
+                const u32 wl = __builtin_amdgcn_alignbit(xl1, xl0, ie);
+                const u32 wh = __builtin_amdgcn_alignbit(xh1, xh0, ie);
+                const u32 wn = kWithN ? __builtin_amdgcn_alignbit(xn1, xn0, ie) : 0u;
                 const u32 mm = (ql ^ wl) | (qh ^ wh) | qn | wn;
-                int run;
-                if (mm) {
-                    run = (int)__builtin_ctz(mm);
-                } else {  // 32 matching columns: continue 64 at a time
-                    run = 32;
-                    const i64 pos = p0 + i;
-                    while (j + run < m) {
-                        const u64 m2 = mismatch(lds_bits(L, NB, j + run), lds_bits<kWithN>(WL, WN, pos + run));
-                        if (m2) {
-                            run += (int)__builtin_ctzll(m2);
-                            break;
-                        }
-                        run += 64;
+                // first obstacle, all ones when the 32 columns match (the
+                // value the hardware's find-first-one gives for 0)
+                const u32 run = mm ? (u32)__builtin_ctz(mm) : ~0u;
+                full |= (run >> 31) << i;
+                bmax = max(bmax, run);
+            }
+            full &= cnt >= 32 ? ~0u : (1u << cnt) - 1u;  // the repeated rows are not continued
+            best = max(best, min((int)min(bmax, 32u), left));
+            // 32 matching columns: continue 64 at a time
+            while (full) {
+                const int i = (int)__builtin_ctz(full);
+                full &= full - 1;
+                int run = 32;
+                const i64 pos = p0 + i;
+                while (j + run < m) {
+                    const u64 m2 = mismatch(lds_bits(L, NB, j + run), lds_bits<kWithN>(WL, WN, pos + run));
+                    if (m2) {
+                        run += (int)__builtin_ctzll(m2);
+                        break;
                     }
+                    run += 64;
                 }
                 best = max(best, min(run, left));
             }

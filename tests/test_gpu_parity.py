@@ -410,6 +410,33 @@ def test_filter_long_pairs_at_edges_and_n(mt):
     assert inside.sum() > 100 and (~inside).sum() > 100 and (oap <= pe).mean() > 0.2
 
 
+def test_filter_long_pairs_very_large_E(mt):
+    """E of 1,000-1,600 (over 32 band rows per lane: a lane's rows take two
+    chunks, the second only partly filled), on long reads near and far from
+    their true diagonal."""
+    import torch
+    rnd = np.random.default_rng(29)
+    gen = synth.make_genomes(rnd, 2, 30_000, 0.5)
+    lens = rnd.integers(5000, 8000, 40)
+    reads, origin = synth.make_reads(rnd, gen, lens, 0.05, 0.05)
+    n = 48
+    pr = rnd.integers(0, reads.n, n).astype(np.uint32)
+    pg = origin[pr, 0].astype(np.uint32)
+    pdg = (origin[pr, 1] + rnd.integers(-900, 900, n)).astype(np.int64)
+    pdg[::2] = rnd.integers(-2000, 25_000, n // 2)  # unrelated windows: rejected
+    pe = rnd.integers(1000, 1600, n).astype(np.uint16)
+    ga = gen.ascii()
+    ix = mt.Index(ga, 15, 10)
+    ap, ac = ix.filter_pairs(mt.to_device(reads), torch.from_numpy(pr.view(np.int32)).cuda(),
+                             torch.from_numpy(pg.view(np.int32)).cuda(), torch.from_numpy(pdg).cuda(),
+                             torch.from_numpy(pe.view(np.int16)).cuda())
+    ap = ap.cpu().numpy().view(np.uint16)
+    oap, oac = oracle.Index(ga, 15, 10).filter_pairs(reads, pr, pg, pdg, pe)
+    assert np.array_equal(ap, oap), np.flatnonzero(ap != oap)[:10]
+    assert np.array_equal(ac.cpu().numpy(), oac)
+    assert (2 * pe.astype(int) + 1 > 64 * 32).sum() > 10 and 0 < oac.sum() < n
+
+
 def test_repeat_calls_and_modes_identical(mt):
     gen, reads, p = synth.workload_small(3000)
     ix = mt.Index(gen.ascii(), p["k"], p["w"])
