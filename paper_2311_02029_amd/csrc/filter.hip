@@ -234,7 +234,11 @@ __device__ inline int long_walk(const u64x2 *L, const u64 *NB, const u64x2 *WL, 
                 const u32 wl = __builtin_amdgcn_alignbit(xl1, xl0, ie);
                 const u32 wh = __builtin_amdgcn_alignbit(xh1, xh0, ie);
                 const u32 wn = kWithN ? __builtin_amdgcn_alignbit(xn1, xn0, ie) : 0u;
-                const u32 mm = (ql ^ wl) | (qh ^ wh) | qn | wn;
+                // (ql ^ wl) | (qh ^ wh) | qn | wn in two (three with the
+                // window's N plane) 3-input bit operations: truth table 0xde
+                // takes (x, z, y) to (x ^ y) | z
+                const u32 t = __builtin_amdgcn_bitop3_b32(ql, kWithN ? (qn | wn) : qn, wl, 0xde);
+                const u32 mm = __builtin_amdgcn_bitop3_b32(qh, t, wh, 0xde);
                 // first obstacle, all ones when the 32 columns match (the
                 // value the hardware's find-first-one gives for 0)
                 const u32 run = mm ? (u32)__builtin_ctz(mm) : ~0u;
