@@ -89,3 +89,16 @@ def test_null_arguments_are_errors_not_crashes():
     assert lib.mt_select_genomes(None, 0, 1, 10_000, None, C.byref(ns), C.byref(mx), None) == _abi.MT_OK
     assert ns.value == 0 and mx.value == 0
     assert lib.mt_filter_pairs_kind(None, None, None, None, None, None, 0, 0, None, None, None) == _abi.MT_EINVAL
+    st = C.c_void_p()
+    assert lib.mt_result_strands(None, C.byref(st)) == _abi.MT_EINVAL
+    kept = C.c_uint64()
+    assert lib.mt_abundance(None, None, 1, 10_000, None, None, C.byref(kept), None) == _abi.MT_EINVAL
+    assert b"null" in lib.mt_last_error()
+
+
+def test_query_struct_strands_field():
+    """strands sits where the first reserved word was: callers that zeroed the
+    reserved words ask for the forward strand alone (0 reads as 1)."""
+    q = _abi.mt_query_params(3, 3, 0, 7, 0, 0)
+    assert q.strands == 0 and q.reserved == 0
+    assert _abi.mt_query_params.strands.offset == 24 and C.sizeof(_abi.mt_query_params) == 32
