@@ -178,7 +178,8 @@ int mt_result_taxa(const mt_result *res, uint32_t *n_taxa, const uint64_t **uniq
 
 /* Strand of every candidate (device array of n_cands entries, or host for a
  * served result): 0 forward, 1 reverse.  *strand is NULL for a result of a
- * one-strand query (every candidate is forward).
+ * one-strand query (every candidate is forward) and for a served result
+ * without candidates.
  *
  * Both strands (Fig. 1 step 2b: reads come from either strand of a genome,
  * and the mapper the paper builds on maps both): the reverse strand is met by
