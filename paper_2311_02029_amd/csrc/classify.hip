@@ -685,9 +685,10 @@ __device__ inline u8 complement_base(u8 c) {
     }
 }
 
-// Offsets of the two-strand read set: read r becomes sequences 2r (the read)
-// and 2r + 1 (its reverse complement), stored back to back at 2 * off[r].
-// Checks the caller's offsets as the packing step does.
+// Offsets of the two-strand read set: sequence r is read r and sequence
+// n + r its reverse complement, the reverse complements stored after all the
+// reads (at total + off[r]).  Checks the caller's offsets as the packing step
+// does.
 __global__ void k_strand_offsets(const u64 *__restrict__ off, u64 n, u64 total, u64 *__restrict__ off2,
                                  u32 *__restrict__ flags) {
     const u64 r = (u64)blockIdx.x * blockDim.x + threadIdx.x;
@@ -698,28 +699,25 @@ __global__ void k_strand_offsets(const u64 *__restrict__ off, u64 n, u64 total, 
     }
     const u64 a = off[r], b = off[r + 1];
     if (b < a || b > total || (r == 0 && a != 0) || (r == n - 1 && b != total)) atomicOr(flags, ERR_OFFSETS);
-    off2[2 * r] = 2 * a;
-    off2[2 * r + 1] = a + b;
+    off2[r] = a;
+    off2[n + r] = total + a;
 }
 
 constexpr int SR_WPB = 4;  // reads (one wavefront each) per block
 
-// One wavefront per read: the read's bytes, then its reverse complement.
-// Runs only after the offsets passed k_strand_offsets.
-__global__ __launch_bounds__(64 * SR_WPB) void k_strand_reads(const u8 *__restrict__ seq,
-                                                              const u64 *__restrict__ off, u64 n,
-                                                              u8 *__restrict__ seq2) {
+// One wavefront per read: its reverse complement at rev + off[r] (the reads
+// themselves are one device copy).  Runs only after the offsets passed
+// k_strand_offsets.
+__global__ __launch_bounds__(64 * SR_WPB) void k_strand_revcomp(const u8 *__restrict__ seq,
+                                                                const u64 *__restrict__ off, u64 n,
+                                                                u8 *__restrict__ rev) {
     const u64 lane = threadIdx.x & 63;
     const u64 stride = (u64)gridDim.x * SR_WPB;
     for (u64 r = (u64)blockIdx.x * SR_WPB + (threadIdx.x >> 6); r < n; r += stride) {
         const u64 a = off[r], m = off[r + 1] - a;
         const u8 *src = seq + a;
-        u8 *fwd = seq2 + 2 * a, *rev = fwd + m;
-        for (u64 j = lane; j < m; j += 64) {
-            const u8 c = src[j];
-            fwd[j] = c;
-            rev[m - 1 - j] = complement_base(c);
-        }
+        u8 *dst = rev + a;
+        for (u64 j = lane; j < m; j += 64) dst[m - 1 - j] = complement_base(src[j]);
     }
 }
 
@@ -727,12 +725,12 @@ __global__ __launch_bounds__(64 * SR_WPB) void k_strand_reads(const u8 *__restri
 __global__ void k_strand_count(const u32 *__restrict__ ncand, u64 n, u32 top_n, u32 *__restrict__ nmerged) {
     const u64 r = (u64)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
-    const u32 c = ncand[2 * r] + ncand[2 * r + 1];
+    const u32 c = ncand[r] + ncand[n + r];
     nmerged[r] = top_n && c > top_n ? top_n : c;
 }
 
-// Merges the two sorted candidate lists of read r (forward: sequence 2r,
-// reverse: 2r + 1) in the order (hits desc, genome, diag, strand), keeping the
+// Merges the two sorted candidate lists of read r (forward: sequence r,
+// reverse: n + r) in the order (hits desc, genome, diag, strand), keeping the
 // first nmerged; pair_read names the oriented sequence the filter reads.
 __global__ void k_strand_merge(const u64 *__restrict__ read_hs, const u32 *__restrict__ ncand,
                                const u64 *__restrict__ cand_off, u64 n, const u64 *__restrict__ stage_key,
@@ -741,8 +739,8 @@ __global__ void k_strand_merge(const u64 *__restrict__ read_hs, const u32 *__res
                                u8 *__restrict__ strand, u32 *__restrict__ pair_read, u16 *__restrict__ read_E) {
     const u64 r = (u64)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
-    const u64 h0 = read_hs[2 * r], h1 = read_hs[2 * r + 1];
-    const u32 n0 = ncand[2 * r], n1 = ncand[2 * r + 1];
+    const u64 h0 = read_hs[r], h1 = read_hs[n + r];
+    const u32 n0 = ncand[r], n1 = ncand[n + r];
     const u64 o = cand_off[r], cnt = cand_off[r + 1] - o;
     u32 i = 0, j = 0;
     for (u64 t = 0; t < cnt; t++) {
@@ -760,20 +758,20 @@ __global__ void k_strand_merge(const u64 *__restrict__ read_hs, const u32 *__res
         diag[o + t] = key_diag(key);
         hits[o + t] = stage_hits[src];
         strand[o + t] = take_fwd ? 0 : 1;
-        pair_read[o + t] = (u32)(2 * r + (take_fwd ? 0 : 1));
+        pair_read[o + t] = (u32)(take_fwd ? r : n + r);
         if (take_fwd) i++;
         else j++;
     }
-    read_E[r] = read_E2[2 * r];
+    read_E[r] = read_E2[r];
 }
 
-// Candidates kept per read from a finished two-strand result (its read 2r is
-// read r, 2r + 1 the reverse complement): the union, cut at top_n.
+// Candidates kept per read from a finished two-strand result (its sequence
+// r is read r, n + r the reverse complement): the union, cut at top_n.
 __global__ void k_strand_count_done(const u64 *__restrict__ cand_off2, u64 n, u32 top_n,
                                     u32 *__restrict__ nmerged) {
     const u64 r = (u64)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
-    const u64 c = cand_off2[2 * r + 2] - cand_off2[2 * r];
+    const u64 c = (cand_off2[r + 1] - cand_off2[r]) + (cand_off2[n + r + 1] - cand_off2[n + r]);
     nmerged[r] = top_n && c > top_n ? top_n : (u32)c;
 }
 
@@ -788,8 +786,8 @@ __global__ void k_strand_merge_done(const u64 *__restrict__ cand_off2, u64 n, co
                                     u16 *__restrict__ read_E) {
     const u64 r = (u64)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
-    u64 i = cand_off2[2 * r], j = cand_off2[2 * r + 1];
-    const u64 e0 = j, e1 = cand_off2[2 * r + 2];
+    u64 i = cand_off2[r], j = cand_off2[n + r];
+    const u64 e0 = cand_off2[r + 1], e1 = cand_off2[n + r + 1];
     const u64 o = cand_off[r], cnt = cand_off[r + 1] - o;
     for (u64 t = 0; t < cnt; t++) {
         bool take_fwd;
@@ -810,7 +808,7 @@ __global__ void k_strand_merge_done(const u64 *__restrict__ cand_off2, u64 n, co
         if (take_fwd) i++;
         else j++;
     }
-    read_E[r] = read_E2[2 * r];
+    read_E[r] = read_E2[r];
 }
 
 // Both strands with the obstacle walk in a fused mode: the fused kernel over
@@ -871,9 +869,12 @@ static void classify_both_strands(const mt_index &ix, const mt_query_params &q, 
         read_back(s, f.p, &fh, sizeof fh);  // the offsets decide every address below
         check_flags(fh);
     }
+    if (n && reads.total)
+        MT_HIP(hipMemcpyAsync(seq2.p, reads.seq, reads.total, hipMemcpyDeviceToDevice, s));
     if (n) {
         const unsigned blocks = (unsigned)std::min<u64>(grid_for(n, SR_WPB), 1u << 20);
-        k_strand_reads<<<blocks, 64 * SR_WPB, 0, s>>>((const u8 *)reads.seq, reads.offsets, n, seq2.p);
+        k_strand_revcomp<<<blocks, 64 * SR_WPB, 0, s>>>((const u8 *)reads.seq, reads.offsets, n,
+                                                        seq2.p + reads.total);
         MT_HIP(hipGetLastError());
     }
     const mt_seqs two{(const char *)seq2.p, off2.p, 2 * n, 2 * reads.total};
