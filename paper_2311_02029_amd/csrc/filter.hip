@@ -174,6 +174,34 @@ __device__ inline u32 plane_dw(const u64x2 *lohi, int pl, u32 k) {
 }
 __device__ inline u32 nb_dw(const u64 *nb, u32 k) { return reinterpret_cast<const u32 *>(nb)[k]; }
 
+// One chunk of a lane's rows in the long walk, without branches (a divergent
+// branch costs scalar exec-mask instructions): row i's 32 window bases are
+// bits [i, i + 32) of (x1:x0) per plane.  The trip count is the wave's rows
+// per chunk (uniform); with kTail, rows past the lane's cnt repeat its last
+// row, which leaves the maximum unchanged.  bmax gets the largest run (all
+// ones for a row whose 32 columns match: the find-first-one value for 0), and
+// full the rows whose 32 columns all match, to be continued by the caller.
+template <bool kWithN, bool kTail>
+__device__ inline void chunk_rows(u32 xl0, u32 xl1, u32 xh0, u32 xh1, u32 xn0, u32 xn1, u32 ql, u32 qh, u32 qn,
+                                  int SC, int cnt, u32 &full, u32 &bmax) {
+#pragma unroll 4
+    for (int i = 0; i < SC; i++) {
+        const u32 ie = kTail ? (u32)min(i, cnt - 1) : (u32)i;
+        const u32 wl = __builtin_amdgcn_alignbit(xl1, xl0, ie);
+        const u32 wh = __builtin_amdgcn_alignbit(xh1, xh0, ie);
+        const u32 wn = kWithN ? __builtin_amdgcn_alignbit(xn1, xn0, ie) : 0u;
+        // (ql ^ wl) | (qh ^ wh) | qn | wn in two (three with the window's N
+        // plane) 3-input bit operations: truth table 0xde takes (x, z, y) to
+        // (x ^ y) | z
+        const u32 t = __builtin_amdgcn_bitop3_b32(ql, kWithN ? (qn | wn) : qn, wl, 0xde);
+        const u32 mm = __builtin_amdgcn_bitop3_b32(qh, t, wh, 0xde);
+        const u32 run = mm ? (u32)__builtin_ctz(mm) : ~0u;
+        full |= (run >> 31) << i;
+        bmax = max(bmax, run);
+    }
+    if (kTail) full &= cnt >= 32 ? ~0u : (1u << cnt) - 1u;  // the repeated rows are not continued
+}
+
 // The obstacle walk of one pair over planes staged in LDS (read at L / NB,
 // window at WL / WN, row 0 and column 0 at window offset wbase), rows in
 // contiguous strips per lane; returns the obstacle count.  kWithN = false
@@ -188,7 +216,9 @@ __device__ inline int long_walk(const u64x2 *L, const u64 *NB, const u64x2 *WL, 
     // in those columns continues 64 columns at a time
     const int rows = 2 * E + 1;
     const int S = (rows + 63) / 64;
-    const int r0 = min(lane * S, rows), r1 = min(r0 + S, rows);
+    // every lane takes S rows; the last lanes repeat the band's last rows,
+    // which leaves the maximum unchanged
+    const int r0 = min(lane * S, rows - S), r1 = r0 + S;
     const int SC = min(32, S);
     int j = 0, c = 0;
     for (;;) {
@@ -222,30 +252,11 @@ __device__ inline int long_walk(const u64x2 *L, const u64 *NB, const u64x2 *WL, 
                 xn0 = __builtin_amdgcn_alignbit(n1, n0, sh0);
                 xn1 = __builtin_amdgcn_alignbit(n2, n1, sh0);
             }
-            // The rows without branches (a divergent branch costs scalar
-            // exec-mask instructions): the trip count is the wave's rows per
-            // lane, and rows past the lane's last repeat its last row, which
-            // leaves the maximum unchanged.  Rows whose 32 columns all match
-            // are marked in `full` and continued afterwards.
             u32 full = 0, bmax = 0;
-#pragma unroll 4
-            for (int i = 0; i < SC; i++) {
-                const u32 ie = (u32)min(i, cnt - 1);
-                const u32 wl = __builtin_amdgcn_alignbit(xl1, xl0, ie);
-                const u32 wh = __builtin_amdgcn_alignbit(xh1, xh0, ie);
-                const u32 wn = kWithN ? __builtin_amdgcn_alignbit(xn1, xn0, ie) : 0u;
-                // (ql ^ wl) | (qh ^ wh) | qn | wn in two (three with the
-                // window's N plane) 3-input bit operations: truth table 0xde
-                // takes (x, z, y) to (x ^ y) | z
-                const u32 t = __builtin_amdgcn_bitop3_b32(ql, kWithN ? (qn | wn) : qn, wl, 0xde);
-                const u32 mm = __builtin_amdgcn_bitop3_b32(qh, t, wh, 0xde);
-                // first obstacle, all ones when the 32 columns match (the
-                // value the hardware's find-first-one gives for 0)
-                const u32 run = mm ? (u32)__builtin_ctz(mm) : ~0u;
-                full |= (run >> 31) << i;
-                bmax = max(bmax, run);
-            }
-            full &= cnt >= 32 ? ~0u : (1u << cnt) - 1u;  // the repeated rows are not continued
+            if (S <= 32)  // every chunk row is the lane's own: no tail to mask
+                chunk_rows<kWithN, false>(xl0, xl1, xh0, xh1, xn0, xn1, ql, qh, qn, SC, cnt, full, bmax);
+            else
+                chunk_rows<kWithN, true>(xl0, xl1, xh0, xh1, xn0, xn1, ql, qh, qn, SC, cnt, full, bmax);
             best = max(best, min((int)min(bmax, 32u), left));
             // 32 matching columns: continue 64 at a time
             while (full) {
