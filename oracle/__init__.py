@@ -24,7 +24,7 @@ _lib = None
 
 def build(out: str = _SO, extra_flags=()) -> str:
     """Compiles oracle.c with gcc into a shared library."""
-    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", *extra_flags, "-o", out, _SRC]
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", *extra_flags, "-o", out, _SRC]
     subprocess.check_call(cmd)
     return out
 
@@ -46,6 +46,10 @@ def _declare(lib):
     lib.or_index_free.argtypes = [C.c_void_p]
     lib.or_index_n_occ.restype = C.c_int64
     lib.or_index_n_occ.argtypes = [C.c_void_p]
+    lib.or_index_copy_occ.restype = None
+    lib.or_index_copy_occ.argtypes = [C.c_void_p, u64p, u32p, u32p]
+    lib.or_set_threads.restype = C.c_int
+    lib.or_set_threads.argtypes = [C.c_int]
     lib.or_approx.restype = C.c_int
     lib.or_approx.argtypes = [u8p, C.c_int64, u8p, C.c_int64, C.c_int64, C.c_int]
     lib.or_read_E.restype = C.c_int
@@ -132,6 +136,13 @@ def approx(q, ref, diag: int, E: int, lib=None) -> int:
     return int(lib.or_approx(_p(qa, C.c_uint8), len(qa), _p(ra, C.c_uint8), len(ra), int(diag), int(E)))
 
 
+def set_threads(n: int = 0, lib=None) -> int:
+    """Threads the oracle's parallel loops use from now on (0: the default,
+    OMP_NUM_THREADS if set, else every processor).  Returns the number in use.
+    Results do not depend on it."""
+    return int((lib or load()).or_set_threads(int(n)))
+
+
 def read_E(m: int, e_mode: int, e_value: int, lib=None) -> int:
     return int((lib or load()).or_read_E(m, e_mode, e_value))
 
@@ -164,6 +175,13 @@ class Index:
     @property
     def n_occ(self) -> int:
         return int(self.lib.or_index_n_occ(self.h))
+
+    def occurrences(self):
+        """The index's occurrence array as (x, genome, pos), in its stored order."""
+        n = self.n_occ
+        x, g, p = np.zeros(n, np.uint64), np.zeros(n, np.uint32), np.zeros(n, np.uint32)
+        self.lib.or_index_copy_occ(self.h, _p(x, C.c_uint64), _p(g, C.c_uint32), _p(p, C.c_uint32))
+        return x, g, p
 
     def classify(self, reads, min_hits=3, top_n=3, e_mode=0, e_value=7, filter_kind=0, strands=1) -> dict:
         """Stage 2 and the step-3a counts; filter_kind 0 is the obstacle walk, 1-4 the

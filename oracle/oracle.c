@@ -108,6 +108,28 @@
 
 #define MAX_READ_LEN 65535u
 
+/* ------------------------------------------------------------ threads ---- */
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads the parallel loops use from now on (n < 1: the default, which
+ * OMP_NUM_THREADS sets, else every processor); returns the number that will
+ * be used.  Built without OpenMP, always 1. */
+int or_set_threads(int n)
+{
+#ifdef _OPENMP
+    static int dflt = 0;
+    if (dflt == 0) dflt = omp_get_max_threads();
+    omp_set_num_threads(n >= 1 ? n : dflt);
+    return omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
+
 /* ---------------------------------------------------------------- O1 ---- */
 
 static int base_code(uint8_t c)
@@ -244,6 +266,13 @@ void or_index_free(or_index *ix)
  * Builds the index over genomes given as ASCII with offsets[n+1].
  * taxon: n entries (NULL = genome i is taxon i).  Returns NULL on error
  * (bad byte, k outside 1..31, w outside 1..255, genome length >= 2^32 - 2^16).
+ *
+ * Genomes are independent, so their encoding and their minimizers may be
+ * computed on several threads (OpenMP); every genome writes only its own
+ * arrays.  The occurrence array is then put in (x, genome, pos) order by one
+ * pass that deals the occurrences into buckets by the top bits of x (bucket
+ * b holds the x with x >> shift == b, so the buckets follow each other in x
+ * order) and a qsort with the full comparison inside every bucket.
  */
 or_index *or_index_build(const uint8_t *seq, const uint64_t *offsets, uint64_t n,
                          int k, int w, uint32_t max_occ,
@@ -256,35 +285,81 @@ or_index *or_index_build(const uint8_t *seq, const uint64_t *offsets, uint64_t n
     ix->glen = calloc(n ? n : 1, sizeof *ix->glen);
     ix->taxon = calloc(n ? n : 1, sizeof *ix->taxon);
     ix->n_taxa = n_taxa;
-    int64_t cap = 0;
+    int64_t maxlen = 1;
     for (uint64_t g = 0; g < n; g++) {
         int64_t len = (int64_t)(offsets[g + 1] - offsets[g]);
         if (len >= (int64_t)4294901760LL) { or_index_free(ix); return NULL; }
         ix->glen[g] = len;
-        ix->gcode[g] = malloc((size_t)(len > 0 ? len : 1));
-        if (encode(seq + offsets[g], len, ix->gcode[g]) != OR_OK) { or_index_free(ix); return NULL; }
         ix->taxon[g] = taxon ? taxon[g] : (uint32_t)g;
         if (ix->taxon[g] >= n_taxa) { or_index_free(ix); return NULL; }
-        cap += len;
+        if (len > maxlen) maxlen = len;
     }
-    ix->occ = malloc((size_t)(cap > 0 ? cap : 1) * sizeof *ix->occ);
-    int64_t maxlen = 1;
-    for (uint64_t g = 0; g < n; g++) if (ix->glen[g] > maxlen) maxlen = ix->glen[g];
-    int64_t *pos = malloc((size_t)maxlen * sizeof *pos);
-    uint64_t *x = malloc((size_t)maxlen * sizeof *x);
-    for (uint64_t g = 0; g < n; g++) {
-        int64_t c = minimizers_of_codes(ix->gcode[g], ix->glen[g], k, w, pos, x);
-        for (int64_t i = 0; i < c; i++) {
-            occ_t o = { x[i], (uint32_t)g, (uint32_t)pos[i] };
-            ix->occ[ix->n_occ++] = o;
+    int bad = 0;
+    #pragma omp parallel for schedule(dynamic, 1) reduction(|:bad)
+    for (int64_t g = 0; g < (int64_t)n; g++) {
+        ix->gcode[g] = malloc((size_t)(ix->glen[g] > 0 ? ix->glen[g] : 1));
+        if (encode(seq + offsets[g], ix->glen[g], ix->gcode[g]) != OR_OK) bad = 1;
+    }
+    if (bad) { or_index_free(ix); return NULL; }
+
+    /* the minimizers of every genome (stage 2a) */
+    occ_t **per = calloc(n ? n : 1, sizeof *per);
+    int64_t *cnt = calloc(n ? n : 1, sizeof *cnt);
+    #pragma omp parallel
+    {
+        int64_t *pos = malloc((size_t)maxlen * sizeof *pos);
+        uint64_t *x = malloc((size_t)maxlen * sizeof *x);
+        #pragma omp for schedule(dynamic, 1)
+        for (int64_t g = 0; g < (int64_t)n; g++) {
+            int64_t c = minimizers_of_codes(ix->gcode[g], ix->glen[g], k, w, pos, x);
+            per[g] = malloc((size_t)(c > 0 ? c : 1) * sizeof *per[g]);
+            for (int64_t i = 0; i < c; i++) {
+                occ_t o = { x[i], (uint32_t)g, (uint32_t)pos[i] };
+                per[g][i] = o;
+            }
+            cnt[g] = c;
         }
+        free(pos); free(x);
     }
-    free(pos); free(x);
-    qsort(ix->occ, (size_t)ix->n_occ, sizeof *ix->occ, cmp_occ);
+
+    /* sort by (x, genome, pos): buckets by the top bits of x, then qsort each */
+    int bits = 2 * k < 12 ? 2 * k : 12;
+    int shift = 2 * k - bits;
+    int64_t nb = (int64_t)1 << bits;
+    int64_t *bstart = calloc((size_t)nb + 1, sizeof *bstart);
+    int64_t total = 0;
+    for (uint64_t g = 0; g < n; g++) {
+        for (int64_t i = 0; i < cnt[g]; i++) bstart[(per[g][i].x >> shift) + 1]++;
+        total += cnt[g];
+    }
+    for (int64_t b = 0; b < nb; b++) bstart[b + 1] += bstart[b];
+    ix->occ = malloc((size_t)(total > 0 ? total : 1) * sizeof *ix->occ);
+    ix->n_occ = total;
+    int64_t *fill = malloc((size_t)nb * sizeof *fill);
+    memcpy(fill, bstart, (size_t)nb * sizeof *fill);
+    for (uint64_t g = 0; g < n; g++) {
+        for (int64_t i = 0; i < cnt[g]; i++) ix->occ[fill[per[g][i].x >> shift]++] = per[g][i];
+        free(per[g]);
+    }
+    free(per); free(cnt); free(fill);
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t b = 0; b < nb; b++)
+        qsort(ix->occ + bstart[b], (size_t)(bstart[b + 1] - bstart[b]), sizeof *ix->occ, cmp_occ);
+    free(bstart);
     return ix;
 }
 
 int64_t or_index_n_occ(const or_index *ix) { return ix->n_occ; }
+
+/* Copies the occurrence array (x, genome, pos), in its sorted order. */
+void or_index_copy_occ(const or_index *ix, uint64_t *x, uint32_t *genome, uint32_t *pos)
+{
+    for (int64_t i = 0; i < ix->n_occ; i++) {
+        x[i] = ix->occ[i].x;
+        genome[i] = ix->occ[i].genome;
+        pos[i] = ix->occ[i].pos;
+    }
+}
 
 /* First index in occ with occ.x >= x. */
 static int64_t lower_bound(const occ_t *occ, int64_t n, uint64_t x)
@@ -463,10 +538,109 @@ static int filter_codes(uint32_t kind, const uint8_t *q, int64_t m, const uint8_
     }
 }
 
+/* Stages 2b-2d of one read: its candidates in O5 order (top_n applied) with
+ * their filter values.  Reads are independent, so several threads may run
+ * this at once; each call writes only its own record. */
+typedef struct {
+    int err;            /* nonzero: bad byte, read longer than 65535 or E above 65534 */
+    int E;
+    int64_t nc;
+    cand_t *cand;
+    uint16_t *approx;
+    uint8_t *accept;
+} read_out_t;
+
+static void classify_read(const or_index *ix, const uint8_t *ascii, int64_t m, uint32_t min_hits, uint32_t top_n,
+                          uint32_t e_mode, uint32_t e_value, uint32_t kind, uint32_t strands, read_out_t *out)
+{
+    memset(out, 0, sizeof *out);
+    int E = or_read_E(m, e_mode, e_value);
+    if (m > (int64_t)MAX_READ_LEN || E > 65534) { out->err = 1; return; }
+    out->E = E;
+    /* the read (strand 0) and its reverse complement (strand 1, O15) */
+    uint8_t *oriented[2];
+    oriented[0] = malloc((size_t)(m > 0 ? m : 1));
+    oriented[1] = malloc((size_t)(m > 0 ? m : 1));
+    if (encode(ascii, m, oriented[0]) != OR_OK) {
+        free(oriented[0]); free(oriented[1]); out->err = 1; return;
+    }
+    reverse_complement_codes(oriented[0], m, oriented[1]);
+
+    /* stage 2b: read minimizers and their seed matches -> (genome, diag, strand) hits */
+    int64_t nk = m - ix->k + 1 > 0 ? m - ix->k + 1 : 0;
+    int64_t *mpos = malloc((size_t)(nk ? nk : 1) * sizeof *mpos);
+    uint64_t *mx = malloc((size_t)(nk ? nk : 1) * sizeof *mx);
+    int64_t nh = 0, hcap = 64;
+    hit_t *hit = malloc((size_t)hcap * sizeof *hit);
+    for (uint32_t st = 0; st < strands; st++) {
+        int64_t nmin = minimizers_of_codes(oriented[st], m, ix->k, ix->w, mpos, mx);
+        for (int64_t i = 0; i < nmin; i++) {
+            int64_t lo = lower_bound(ix->occ, ix->n_occ, mx[i]);
+            int64_t hi = lo;
+            while (hi < ix->n_occ && ix->occ[hi].x == mx[i]) hi++;
+            if (ix->max_occ > 0 && hi - lo > (int64_t)ix->max_occ) continue;
+            for (int64_t o = lo; o < hi; o++) {
+                if (nh == hcap) { hcap *= 2; hit = realloc(hit, (size_t)hcap * sizeof *hit); }
+                hit[nh].genome = ix->occ[o].genome;
+                hit[nh].diag = (int64_t)ix->occ[o].pos - mpos[i];
+                hit[nh].strand = (uint8_t)st;
+                nh++;
+            }
+        }
+    }
+    free(mpos); free(mx);
+
+    /* stage 2b/2c: seed hits per location, minimum, order, top N */
+    qsort(hit, (size_t)nh, sizeof *hit, cmp_hit);
+    cand_t *cand = malloc((size_t)(nh ? nh : 1) * sizeof *cand);
+    int64_t nc = 0;
+    for (int64_t i = 0; i < nh;) {
+        int64_t j = i;
+        while (j < nh && hit[j].genome == hit[i].genome && hit[j].diag == hit[i].diag &&
+               hit[j].strand == hit[i].strand)
+            j++;
+        if ((uint64_t)(j - i) >= min_hits) {
+            cand[nc].genome = hit[i].genome;
+            cand[nc].diag = hit[i].diag;
+            cand[nc].strand = hit[i].strand;
+            cand[nc].hits = (uint32_t)(j - i);
+            nc++;
+        }
+        i = j;
+    }
+    free(hit);
+    qsort(cand, (size_t)nc, sizeof *cand, cmp_cand);
+    if (top_n > 0 && nc > (int64_t)top_n) nc = top_n;
+
+    /* stage 2d: approximate edit distance + accept per pair */
+    out->nc = nc;
+    out->cand = cand;
+    out->approx = malloc((size_t)(nc ? nc : 1) * sizeof *out->approx);
+    out->accept = malloc((size_t)(nc ? nc : 1));
+    for (int64_t c = 0; c < nc; c++) {
+        uint32_t g = cand[c].genome;
+        int a = filter_codes(kind, oriented[cand[c].strand], m, ix->gcode[g], ix->glen[g], cand[c].diag, E);
+        out->approx[c] = (uint16_t)a;
+        out->accept[c] = (uint8_t)(a <= E);
+    }
+    free(oriented[0]); free(oriented[1]);
+}
+
+static void read_out_free(read_out_t *o)
+{
+    free(o->cand); free(o->approx); free(o->accept);
+}
+
+#define READ_BLOCK 65536
+
 /*
  * Classifies reads (ASCII + offsets[n+1]) on one strand or both (O15).
  * Returns NULL on an invalid input (bad byte, read longer than 65535, E above
  * 65534, unknown filter kind, strands other than 1 or 2).
+ *
+ * The reads of a block go through stages 2b-2d on all threads at once
+ * (classify_read); the block's results are then appended in read order and
+ * counted per taxon (stage 3a) on one thread.
  */
 or_result *or_classify_strands(const or_index *ix, const uint8_t *seq, const uint64_t *offsets, uint64_t n,
                                uint32_t min_hits, uint32_t top_n, uint32_t e_mode, uint32_t e_value,
@@ -482,104 +656,64 @@ or_result *or_classify_strands(const or_index *ix, const uint8_t *seq, const uin
     res->unique_reads = calloc(ix->n_taxa ? ix->n_taxa : 1, sizeof(uint64_t));
     res->multi_reads = calloc(ix->n_taxa ? ix->n_taxa : 1, sizeof(uint64_t));
     uint8_t *taxon_seen = calloc(ix->n_taxa ? ix->n_taxa : 1, 1);
+    read_out_t *outs = malloc(sizeof *outs * (n < READ_BLOCK ? (n ? n : 1) : READ_BLOCK));
 
-    for (uint64_t r = 0; r < n; r++) {
-        int64_t m = (int64_t)(offsets[r + 1] - offsets[r]);
-        int E = or_read_E(m, e_mode, e_value);
-        if (m > (int64_t)MAX_READ_LEN || E > 65534) { free(taxon_seen); or_result_free(res); return NULL; }
-        res->read_E[r] = (uint16_t)E;
-        /* the read (strand 0) and its reverse complement (strand 1, O15) */
-        uint8_t *oriented[2];
-        oriented[0] = malloc((size_t)(m > 0 ? m : 1));
-        oriented[1] = malloc((size_t)(m > 0 ? m : 1));
-        if (encode(seq + offsets[r], m, oriented[0]) != OR_OK) {
-            free(oriented[0]); free(oriented[1]); free(taxon_seen); or_result_free(res); return NULL;
+    for (uint64_t r0 = 0; r0 < n; r0 += READ_BLOCK) {
+        int64_t nb = (int64_t)(n - r0 < READ_BLOCK ? n - r0 : READ_BLOCK);
+        #pragma omp parallel for schedule(dynamic, 16)
+        for (int64_t i = 0; i < nb; i++) {
+            uint64_t r = r0 + (uint64_t)i;
+            classify_read(ix, seq + offsets[r], (int64_t)(offsets[r + 1] - offsets[r]), min_hits, top_n, e_mode,
+                          e_value, kind, strands, &outs[i]);
         }
-        reverse_complement_codes(oriented[0], m, oriented[1]);
+        int failed = 0;
+        for (int64_t i = 0; i < nb; i++) failed |= outs[i].err;
+        if (failed) {
+            for (int64_t i = 0; i < nb; i++) read_out_free(&outs[i]);
+            free(outs); free(taxon_seen); or_result_free(res);
+            return NULL;
+        }
+        for (int64_t i = 0; i < nb; i++) {
+            uint64_t r = r0 + (uint64_t)i;
+            read_out_t *o = &outs[i];
+            int E = o->E;
+            res->read_E[r] = (uint16_t)E;
+            uint64_t first = res->n_cands;
+            int best = -1;
+            for (int64_t c = 0; c < o->nc; c++) {
+                push_cand(res, &o->cand[c]);
+                int a = o->approx[c];
+                res->approx[res->n_cands - 1] = o->approx[c];
+                res->accept[res->n_cands - 1] = o->accept[c];
+                if (a <= E && (best < 0 || a < best)) best = a;
+            }
+            res->cand_offsets[r + 1] = res->n_cands;
+            read_out_free(o);
 
-        /* stage 2b: read minimizers and their seed matches -> (genome, diag, strand) hits */
-        int64_t nk = m - ix->k + 1 > 0 ? m - ix->k + 1 : 0;
-        int64_t *mpos = malloc((size_t)(nk ? nk : 1) * sizeof *mpos);
-        uint64_t *mx = malloc((size_t)(nk ? nk : 1) * sizeof *mx);
-        int64_t nh = 0, hcap = 64;
-        hit_t *hit = malloc((size_t)hcap * sizeof *hit);
-        for (uint32_t st = 0; st < strands; st++) {
-            int64_t nmin = minimizers_of_codes(oriented[st], m, ix->k, ix->w, mpos, mx);
-            for (int64_t i = 0; i < nmin; i++) {
-                int64_t lo = lower_bound(ix->occ, ix->n_occ, mx[i]);
-                int64_t hi = lo;
-                while (hi < ix->n_occ && ix->occ[hi].x == mx[i]) hi++;
-                if (ix->max_occ > 0 && hi - lo > (int64_t)ix->max_occ) continue;
-                for (int64_t o = lo; o < hi; o++) {
-                    if (nh == hcap) { hcap *= 2; hit = realloc(hit, (size_t)hcap * sizeof *hit); }
-                    hit[nh].genome = ix->occ[o].genome;
-                    hit[nh].diag = (int64_t)ix->occ[o].pos - mpos[i];
-                    hit[nh].strand = (uint8_t)st;
-                    nh++;
+            /* stage 3a: per-taxon unique / multi-mapped counts */
+            if (best < 0) {
+                res->unmapped++;
+                continue;
+            }
+            res->read_accepted[r] = 1;
+            uint32_t ntax = 0, only = 0;
+            for (uint64_t c = first; c < res->n_cands; c++) {
+                if (!res->accept[c] || res->approx[c] != best) continue;
+                uint32_t t = ix->taxon[res->genome[c]];
+                if (!taxon_seen[t]) { taxon_seen[t] = 1; ntax++; only = t; }
+            }
+            for (uint64_t c = first; c < res->n_cands; c++) {
+                if (!res->accept[c] || res->approx[c] != best) continue;
+                uint32_t t = ix->taxon[res->genome[c]];
+                if (taxon_seen[t]) {
+                    taxon_seen[t] = 0;
+                    if (ntax > 1) res->multi_reads[t]++;
                 }
             }
+            if (ntax == 1) res->unique_reads[only]++;
         }
-        free(mpos); free(mx);
-
-        /* stage 2b/2c: seed hits per location, minimum, order, top N */
-        qsort(hit, (size_t)nh, sizeof *hit, cmp_hit);
-        cand_t *cand = malloc((size_t)(nh ? nh : 1) * sizeof *cand);
-        int64_t nc = 0;
-        for (int64_t i = 0; i < nh;) {
-            int64_t j = i;
-            while (j < nh && hit[j].genome == hit[i].genome && hit[j].diag == hit[i].diag &&
-                   hit[j].strand == hit[i].strand)
-                j++;
-            if ((uint64_t)(j - i) >= min_hits) {
-                cand[nc].genome = hit[i].genome;
-                cand[nc].diag = hit[i].diag;
-                cand[nc].strand = hit[i].strand;
-                cand[nc].hits = (uint32_t)(j - i);
-                nc++;
-            }
-            i = j;
-        }
-        free(hit);
-        qsort(cand, (size_t)nc, sizeof *cand, cmp_cand);
-        if (top_n > 0 && nc > (int64_t)top_n) nc = top_n;
-
-        /* stage 2d: approximate edit distance + accept per pair */
-        uint64_t first = res->n_cands;
-        int best = -1;
-        for (int64_t c = 0; c < nc; c++) {
-            push_cand(res, &cand[c]);
-            uint32_t g = cand[c].genome;
-            int a = filter_codes(kind, oriented[cand[c].strand], m, ix->gcode[g], ix->glen[g], cand[c].diag, E);
-            res->approx[res->n_cands - 1] = (uint16_t)a;
-            res->accept[res->n_cands - 1] = (uint8_t)(a <= E);
-            if (a <= E && (best < 0 || a < best)) best = a;
-        }
-        res->cand_offsets[r + 1] = res->n_cands;
-        free(cand);
-        free(oriented[0]); free(oriented[1]);
-
-        /* stage 3a: per-taxon unique / multi-mapped counts */
-        if (best < 0) {
-            res->unmapped++;
-            continue;
-        }
-        res->read_accepted[r] = 1;
-        uint32_t ntax = 0, only = 0;
-        for (uint64_t c = first; c < res->n_cands; c++) {
-            if (!res->accept[c] || res->approx[c] != best) continue;
-            uint32_t t = ix->taxon[res->genome[c]];
-            if (!taxon_seen[t]) { taxon_seen[t] = 1; ntax++; only = t; }
-        }
-        for (uint64_t c = first; c < res->n_cands; c++) {
-            if (!res->accept[c] || res->approx[c] != best) continue;
-            uint32_t t = ix->taxon[res->genome[c]];
-            if (taxon_seen[t]) {
-                taxon_seen[t] = 0;
-                if (ntax > 1) res->multi_reads[t]++;
-            }
-        }
-        if (ntax == 1) res->unique_reads[only]++;
     }
+    free(outs);
     free(taxon_seen);
     return res;
 }
@@ -715,12 +849,16 @@ int or_filter_pairs_kind(const or_index *ix, const uint8_t *seq, const uint64_t 
                          uint8_t *accept_out)
 {
     if (kind > 4) return OR_EINVAL;
-    for (uint64_t p = 0; p < n_pairs; p++) {
-        if (pair_read[p] >= n_reads || pair_genome[p] >= ix->n_genomes) return OR_EINVAL;
+    int bad = 0;
+    /* pairs are independent: several threads may filter at once */
+    #pragma omp parallel for schedule(dynamic, 64) reduction(|:bad)
+    for (int64_t pi = 0; pi < (int64_t)n_pairs; pi++) {
+        uint64_t p = (uint64_t)pi;
+        if (pair_read[p] >= n_reads || pair_genome[p] >= ix->n_genomes) { bad = 1; continue; }
         uint64_t r = pair_read[p];
         int64_t m = (int64_t)(offsets[r + 1] - offsets[r]);
         uint8_t *q = malloc((size_t)(m > 0 ? m : 1));
-        if (encode(seq + offsets[r], m, q) != OR_OK) { free(q); return OR_EINVAL; }
+        if (encode(seq + offsets[r], m, q) != OR_OK) { free(q); bad = 1; continue; }
         uint32_t g = pair_genome[p];
         int E = pair_E[p];
         int a = filter_codes(kind, q, m, ix->gcode[g], ix->glen[g], pair_diag[p], E);
@@ -728,7 +866,7 @@ int or_filter_pairs_kind(const or_index *ix, const uint8_t *seq, const uint64_t 
         accept_out[p] = (uint8_t)(a <= E);
         free(q);
     }
-    return OR_OK;
+    return bad ? OR_EINVAL : OR_OK;
 }
 
 /* The obstacle filter alone over explicit pairs (pair_read indexes the reads). */
@@ -751,25 +889,37 @@ int or_filter_pairs(const or_index *ix, const uint8_t *seq, const uint64_t *offs
 int or_containment(const or_index *ix, const uint8_t *seq, const uint64_t *offsets, uint64_t n, uint64_t *hits)
 {
     for (uint64_t g = 0; g < ix->n_genomes; g++) hits[g] = 0;
-    for (uint64_t r = 0; r < n; r++) {
-        int64_t m = (int64_t)(offsets[r + 1] - offsets[r]);
-        if (m > (int64_t)MAX_READ_LEN) return OR_EINVAL;
-        uint8_t *q = malloc((size_t)(m > 0 ? m : 1));
-        if (encode(seq + offsets[r], m, q) != OR_OK) { free(q); return OR_EINVAL; }
-        int64_t nk = m - ix->k + 1 > 0 ? m - ix->k + 1 : 0;
-        int64_t *mpos = malloc((size_t)(nk ? nk : 1) * sizeof *mpos);
-        uint64_t *mx = malloc((size_t)(nk ? nk : 1) * sizeof *mx);
-        int64_t nmin = minimizers_of_codes(q, m, ix->k, ix->w, mpos, mx);
-        for (int64_t i = 0; i < nmin; i++) {
-            int64_t lo = lower_bound(ix->occ, ix->n_occ, mx[i]);
-            int64_t hi = lo;
-            while (hi < ix->n_occ && ix->occ[hi].x == mx[i]) hi++;
-            if (ix->max_occ && (uint64_t)(hi - lo) > ix->max_occ) continue; /* O4 cap */
-            for (int64_t o = lo; o < hi; o++) hits[ix->occ[o].genome] += 1;
+    int bad = 0;
+    /* reads are independent: each thread counts into its own array, and the
+     * arrays are summed into hits at the end */
+    #pragma omp parallel reduction(|:bad)
+    {
+        uint64_t *local = calloc(ix->n_genomes ? ix->n_genomes : 1, sizeof *local);
+        #pragma omp for schedule(dynamic, 64)
+        for (int64_t ri = 0; ri < (int64_t)n; ri++) {
+            uint64_t r = (uint64_t)ri;
+            int64_t m = (int64_t)(offsets[r + 1] - offsets[r]);
+            if (m > (int64_t)MAX_READ_LEN) { bad = 1; continue; }
+            uint8_t *q = malloc((size_t)(m > 0 ? m : 1));
+            if (encode(seq + offsets[r], m, q) != OR_OK) { free(q); bad = 1; continue; }
+            int64_t nk = m - ix->k + 1 > 0 ? m - ix->k + 1 : 0;
+            int64_t *mpos = malloc((size_t)(nk ? nk : 1) * sizeof *mpos);
+            uint64_t *mx = malloc((size_t)(nk ? nk : 1) * sizeof *mx);
+            int64_t nmin = minimizers_of_codes(q, m, ix->k, ix->w, mpos, mx);
+            for (int64_t i = 0; i < nmin; i++) {
+                int64_t lo = lower_bound(ix->occ, ix->n_occ, mx[i]);
+                int64_t hi = lo;
+                while (hi < ix->n_occ && ix->occ[hi].x == mx[i]) hi++;
+                if (ix->max_occ && (uint64_t)(hi - lo) > ix->max_occ) continue; /* O4 cap */
+                for (int64_t o = lo; o < hi; o++) local[ix->occ[o].genome] += 1;
+            }
+            free(mpos); free(mx); free(q);
         }
-        free(mpos); free(mx); free(q);
+        #pragma omp critical
+        for (uint64_t g = 0; g < ix->n_genomes; g++) hits[g] += local[g];
+        free(local);
     }
-    return OR_OK;
+    return bad ? OR_EINVAL : OR_OK;
 }
 
 /*

@@ -59,15 +59,14 @@ MUTANTS = [
      "        c += 1;\n        if (c > E) break;"),
     ("early stop", "        c += 1;\n        if (c > E) break;", "        c += 1;\n        if (c >= E) break;"),
     ("cap at E", "return c < E + 1 ? c : E + 1;", "return c < E ? c : E;"),
-    ("strict accept", "res->accept[res->n_cands - 1] = (uint8_t)(a <= E);",
-     "res->accept[res->n_cands - 1] = (uint8_t)(a < E);"),
+    ("strict accept", "out->accept[c] = (uint8_t)(a <= E);", "out->accept[c] = (uint8_t)(a < E);"),
     ("E rounds down", "if (e_mode == 1) return (int)((num + 999) / 1000);", "if (e_mode == 1) return (int)(num / 1000);"),
     ("worst accepted count", "if (a <= E && (best < 0 || a < best)) best = a;",
      "if (a <= E && (best < 0 || a > best)) best = a;"),
     ("multi counted once", "if (ntax > 1) res->multi_reads[t]++;", "if (ntax > 1 && t == only) res->multi_reads[t]++;"),
     ("unique ignores ties", "if (ntax == 1) res->unique_reads[only]++;", "if (ntax >= 1) res->unique_reads[only]++;"),
-    ("containment counts a key once", "for (int64_t o = lo; o < hi; o++) hits[ix->occ[o].genome] += 1;",
-     "if (hi > lo) hits[ix->occ[lo].genome] += 1;"),
+    ("containment counts a key once", "for (int64_t o = lo; o < hi; o++) local[ix->occ[o].genome] += 1;",
+     "if (hi > lo) local[ix->occ[lo].genome] += 1;"),
     ("containment cap inclusive", "if (ix->max_occ && (uint64_t)(hi - lo) > ix->max_occ) continue;",
      "if (ix->max_occ && (uint64_t)(hi - lo) >= ix->max_occ) continue;"),
     ("selection not strict", "> (unsigned __int128)M * num) selected", ">= (unsigned __int128)M * num) selected"),
@@ -96,7 +95,7 @@ def test_pins_catch_planted_mistake(name, orig, mut, tmp_path):
     mutant_c = tmp_path / "oracle_mutant.c"
     mutant_c.write_text(src.replace(orig, mut))
     lib = str(tmp_path / "liboracle_mutant.so")
-    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", lib, str(mutant_c)])
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-o", lib, str(mutant_c)])
     env = dict(os.environ, ORACLE_LIB=lib)
     r = subprocess.run([sys.executable, "-m", "pytest", *PIN_FILES, "-x", "-q", "-p", "no:cacheprovider"], cwd=ROOT,
                        env=env, capture_output=True, text=True, timeout=600)
