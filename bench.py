@@ -1,14 +1,27 @@
 #!/usr/bin/env python3
 """Throughput benchmark of the seed-count + approximate-edit-distance path.
 
-Workload: 200 synthetic genomes totalling 500 Mbp (per-genome GC ~ U(0.3, 0.7)),
-1M reads of 150 bp with 0.1-1% substitutions and 0.01-0.1% indels, k=21,
-w=11, >= 3 seed hits, top 3 locations, E = 7 (5% of 150).  One step is one
-classification of the whole read batch (seeding, lookup, hit counting, top-N,
-filter, per-taxon counts) with the reads and the index already in HBM.
+Headline workload (the largest single-GPU configuration, dense candidates):
+2,000 synthetic genomes = 400 random roots x 5 substitution-only strains
+(1-5% divergence) x 2 Mbp = 4 Gbp, taxon = strain; 10M reads of 150 bp at 1%
+error (0.9% substitutions, 0.1% indels); k=21, w=11, >= 3 seed hits, top 3,
+E = 7.  One step is one classification of the whole read batch (seeding,
+lookup, hit counting, top-N, filter, per-taxon counts).  `value` is measured
+with the reads and the index already in HBM; `end_to_end` adds the upload of
+the reads from pinned host memory and the download of every output into
+pinned host memory.
 
-Prints one JSON line.  The CPU baseline is the plain C oracle timed on a
-bounded sample of the same reads (its index build is not timed).
+Also measured (same JSON line): the plain one-launch-per-stage and graph
+forms of the headline workload; the served headline workload under a memory
+budget (admission control); the 500 Mbp batched workload across the E sweep
+{0, 3, 7, 15} fused and per-stage, with stage 1, the Table 1 filters, both
+strands and abundance; the uneven workload (2M reads up to 10 kbp,
+autotuned); the served workload (Poisson traces on the 500 Mbp index).  The
+CPU baseline is the plain C oracle on the machine's host cores, single-threaded
+and on all cores, each the median of 3 runs on a seeded sample of the
+headline reads (its index build is not timed).
+
+Prints one JSON line on stdout; progress goes to stderr.
 """
 from __future__ import annotations
 
@@ -25,87 +38,192 @@ sys.path.insert(0, ROOT)
 
 METRIC = "read×candidate pairs/s and reads/s at E=5%, bit-exact; p50/p99 latency served"
 HBM_PEAK_GBS = 8000.0
+# Integer VALU peak of the MI355X: 256 CUs x 4 SIMD16 units x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s,
+# i.e. one wave64 VALU instruction per CU per cycle.
+VALU_WAVE_INSTR_PEAK = 256 * 2.4e9
+VALU_LANE_OPS_PEAK = VALU_WAVE_INSTR_PEAK * 64
 
-# Algorithmic bytes per work unit of each stage (see the design notes):
-#   lookup: per minimizer  8 B k-mer in + 16 B table slot + 8 B value out + 4 B count out
-#   fused:  per read       its ASCII bases + 16 B slot per minimizer + 16 B reference
-#                          planes per 64 window bases + 19 B per candidate out + 11 B per read out
-LOOKUP_BYTES_PER_MIN = 8 + 16 + 8 + 4
+# Algorithmic bytes per work unit of the fused kernel (see the design notes):
+#   per read          its ASCII bases in + 11 B out (read flag, E, candidate count)
+#   per minimizer     its 16 B table slot
+#   per occurrence    8 B from the multi-occurrence array (k-mers with several occurrences)
+#   per window block  16 B of reference planes per 64 window bases
+#   per candidate     19 B out
+FUSED_MODEL = "bases + 16*minimizers + 8*occurrences + 16*window_blocks + 19*candidates + 11*reads"
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def measured_traffic(kernel: str):
-    """HBM bytes per dispatch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
-    record of this kernel (scaled by the plain-copy calibration), or None when
-    the record is missing or was taken on a different kernel source."""
+def fused_alg_bytes(stats: dict) -> int:
+    return int(stats["fused_bases"] + 16 * stats["fused_minimizers"] + 8 * stats.get("fused_occ", 0)
+               + 16 * stats["fused_window_blocks"] + 19 * stats["fused_cands"] + 11 * stats["fused_reads"])
+
+
+def counter_record(name: str):
+    """A committed rocprofv3 counter record under profiles/, or None when it is
+    missing or was taken on a different kernel source (sha256 of the sources)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "k_fused_hbm_counters_500mbp_1m.json")
-    if kernel != "fused" or not os.path.exists(path):
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
         return None
     rec = json.load(open(path))
     h = hashlib.sha256()
     for src in rec["kernel_sources"]:
         h.update(open(os.path.join(ROOT, src), "rb").read())
-    if h.hexdigest() != rec["source_sha256"]:
-        return None
-    return int(rec["traffic_bytes_per_dispatch"])
+    return rec if h.hexdigest() == rec["source_sha256"] else None
 
 
-def filter_useful_ops(host: dict, lengths) -> int:
-    """Useful int32 lane-ops of the filter over a result's pairs: building
-    the (2E+1) rows of ceil(m/64) mismatch words at 6 ops a word, plus 8 ops
-    per row for each step of the obstacle walk (min(approx, E) + 1 steps)."""
+def useful_ops(host: dict, lengths) -> np.ndarray:
+    """Useful int32 lane-ops of the obstacle filter per pair: building the (2E+1)
+    rows of ceil(m/64) mismatch words at 6 ops a word, plus 8 ops per row for
+    each step of the walk (min(approx, E) + 1 steps)."""
     co = np.asarray(host["cand_offsets"], dtype=np.int64)
     pr = np.repeat(np.arange(len(co) - 1), np.diff(co))
     E = np.asarray(host["read_E"], dtype=np.int64)[pr]
     m = np.asarray(lengths, dtype=np.int64)[pr]
     ap = np.asarray(host["approx"], dtype=np.int64)
     rows = 2 * E + 1
-    return int((6 * rows * ((m + 63) // 64) + 8 * rows * (np.minimum(ap, E) + 1)).sum())
+    return 6 * rows * ((m + 63) // 64) + 8 * rows * (np.minimum(ap, E) + 1)
+
+
+def pair_bucket(host: dict, lengths) -> np.ndarray:
+    """The filter bucket of every pair of a result, as the per-stage filter
+    forms them: 0 E<=7, 1 E<=15, 2 E<=31, 3..6 long bins by the 64-base blocks
+    of read and window staged (<= 96, 192, 384, 768), 7 general."""
+    co = np.asarray(host["cand_offsets"], dtype=np.int64)
+    pr = np.repeat(np.arange(len(co) - 1), np.diff(co))
+    E = np.asarray(host["read_E"], dtype=np.int64)[pr]
+    m = np.asarray(lengths, dtype=np.int64)[pr]
+    blocks = (m + 63) // 64 + 1 + ((m + 2 * E + 190) >> 6) + 2
+    b = np.full(len(pr), 7, np.int64)
+    for i, cap in reversed(list(enumerate((96, 192, 384, 768)))):
+        b = np.where((E > 31) & (blocks <= cap), 3 + i, b)
+    b = np.where(E <= 31, 2, b)
+    b = np.where(E <= 15, 1, b)
+    b = np.where(E <= 7, 0, b)
+    return b
+
+
+BUCKET_NAMES = ("E<=7", "E<=15", "E<=31", "long<=96", "long<=192", "long<=384", "long<=768", "general")
 
 
 def _pct(v, q):
     return float(np.percentile(np.asarray(v, dtype=np.float64), q)) if len(v) else None
 
 
-def serving_bench(mt, ix, pool, seconds: float = 2.0, loads=(0.5, 0.8, 0.95), threads: int = 8,
-                  baseline_s: float = 4.0, n_streams: int = 0, max_batch_reads: int = 0) -> dict:
-    """The served workload: requests of U{1..50,000} reads of one length in
-    100-250 bp at 0.5% error, E = ceil(5% of length), against the resident
-    index.  Measures
-      * the server's saturated reads/s (closed loop: `threads` clients submit
-        back to back for `seconds`);
-      * p50 / p99 request latency (completion minus scheduled arrival) on
-        Poisson traces offering each fraction in `loads` of that rate;
-      * the same trace served by sequential per-request solves (upload,
-        mt_classify, download, one request at a time), plain per-stage form
-        and fused form, for at most `baseline_s` seconds each.
-    """
+def time_form(mt, ix, dreads, q, steps, warmup, timing=True):
+    """Warm-up steps, then `steps` timed classifications (wall clock between two
+    device synchronizations); per-stage HIP-event timings averaged per step."""
+    import torch
+    for _ in range(warmup):
+        ix.classify(dreads, **q).free()
+    mt.mt_set_timing(timing)
+    stage = {}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_cands = 0
+    for _ in range(steps):
+        r = ix.classify(dreads, **q)
+        n_cands = r.n_cands
+        r.free()
+        if timing:
+            for name, ms in mt.last_timings():
+                stage[name] = stage.get(name, 0.0) + ms
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    mt.mt_set_timing(False)
+    stats = mt.last_stats()
+    return {"ms_per_step": round(dt * 1000, 4), "reads_per_s": round(dreads.n / dt, 1),
+            "pairs_per_s": round(n_cands / dt, 1), "pairs": int(n_cands),
+            "stages_ms": {k: round(v / steps, 4) for k, v in stage.items()}}, stats
+
+
+def end_to_end(mt, ix, reads, q, steps, warmup):
+    """Host reads in pinned memory -> device -> classification -> every output
+    back in pinned host memory, one step after the other on one stream."""
+    import ctypes as C
+    import torch
+    seq = torch.from_numpy(np.ascontiguousarray(reads.seq)).pin_memory()
+    off = torch.from_numpy(np.ascontiguousarray(reads.offsets).view(np.int64)).pin_memory()
+    n = reads.n
+    cap = n * max(q.get("top_n", 3), 1)
+    out = {"cand_offsets": torch.empty(n + 1, dtype=torch.int64).pin_memory(),
+           "read_accepted": torch.empty(n, dtype=torch.uint8).pin_memory(),
+           "read_E": torch.empty(n, dtype=torch.int16).pin_memory(),
+           "genome": torch.empty(cap, dtype=torch.int32).pin_memory(),
+           "diag": torch.empty(cap, dtype=torch.int64).pin_memory(),
+           "hits": torch.empty(cap, dtype=torch.int32).pin_memory(),
+           "approx": torch.empty(cap, dtype=torch.int16).pin_memory(),
+           "accept": torch.empty(cap, dtype=torch.uint8).pin_memory()}
+    hip = mt._hip()
+    hip.hipMemcpyAsync.restype = C.c_int
+    hip.hipMemcpyAsync.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int, C.c_void_p]
+    stream = torch.cuda.current_stream()
+    sp = C.c_void_p(stream.cuda_stream)
+
+    def step():
+        dseq = seq.to("cuda", non_blocking=True)
+        doff = off.to("cuda", non_blocking=True)
+        dr = mt.DeviceSeqs(dseq, doff, n, int(reads.offsets[-1]))
+        r = ix.classify(dr, **q)
+        nr, co, ra, re = r._reads()
+        nc, (g, d, h, a, ac) = r._cands()
+        assert nc <= cap
+        for name, ptr, cnt in (("cand_offsets", co, nr + 1), ("read_accepted", ra, nr), ("read_E", re, nr),
+                               ("genome", g, nc), ("diag", d, nc), ("hits", h, nc), ("approx", a, nc),
+                               ("accept", ac, nc)):
+            t = out[name]
+            rc = hip.hipMemcpyAsync(C.c_void_p(t.data_ptr()), C.c_void_p(ptr), C.c_size_t(cnt * t.element_size()),
+                                    2, sp)
+            assert rc == 0, rc
+        stream.synchronize()
+        r.free()
+        return nc
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        nc = step()
+    dt = (time.perf_counter() - t0) / steps
+    bytes_in = int(reads.offsets[-1]) + 8 * (n + 1)
+    bytes_out = 8 * (n + 1) + 3 * n + 19 * nc
+    return {"ms_per_step": round(dt * 1000, 3), "reads_per_s": round(n / dt, 1), "pairs_per_s": round(nc / dt, 1),
+            "bytes_in": bytes_in, "bytes_out": bytes_out,
+            "note": "reads uploaded from pinned host memory and every per-read and per-candidate output downloaded "
+                    "into pinned host memory inside each timed step (one stream, no overlap)"}
+
+
+def serving_bench(mt, ix, pool, seconds: float, loads=(0.5, 0.8, 0.95), runs: int = 2, threads: int = 8,
+                  baseline_s: float = 4.0, n_streams: int = 0, max_batch_reads: int = 0, mem_budget: int = 0,
+                  q=None, workload: str = "", reads_fn=None, mean_reads: float = 25_000.5) -> dict:
+    """Served requests: the server's saturated reads/s (clients submitting back
+    to back), then p50 / p99 request latency (completion minus scheduled
+    arrival) on Poisson traces offering each fraction in `loads` of that rate,
+    `runs` traces of `seconds` each per load; then, if baseline_s > 0, the 80%
+    trace served by sequential per-request solves (upload, mt_classify,
+    download, one request at a time) in the per-stage and fused forms."""
     import threading
     import synth
-    from collections import deque
 
-    q = dict(min_hits=3, top_n=3, e_mode=mt.MT_E_CEIL_PERMILLE, e_value=50)
-    mean_reads = 25_000.5
+    q = q or dict(min_hits=3, top_n=3, e_mode=mt.MT_E_CEIL_PERMILLE, e_value=50)
+    reads_fn = reads_fn or (lambda n, m: synth.request_reads(pool, n, m))
 
     def trace(seed, n, qps):
         return synth.request_trace(seed, n, qps, lengths=synth.SERVED_LENGTHS)
 
     def run_served(tr, paced: bool, stop_after: float | None = None):
-        """Submits tr (paced by arrival, or back to back); returns per-request
-        (arrival_ns, submit_ns, done_ns, reads) and the wall interval."""
         recs = [None] * len(tr)
         ids = [None] * len(tr)
         errs = []
-        with mt.Server(ix, pinned_arena_bytes=4 << 30, max_queued_requests=8192, n_streams=n_streams,
-                       max_batch_reads=max_batch_reads) as sv:
+        with mt.Server(ix, mem_budget_bytes=mem_budget, pinned_arena_bytes=4 << 30, max_queued_requests=8192,
+                       n_streams=n_streams, max_batch_reads=max_batch_reads) as sv:
             t0 = time.monotonic_ns()
             stop_at = None if stop_after is None else t0 + int(stop_after * 1e9)
             avail = [threading.Semaphore(0) for _ in range(threads)]
-            done_n = [0] * threads
 
             def client(k):
                 try:
@@ -119,7 +237,7 @@ def serving_bench(mt, ix, pool, seconds: float = 2.0, loads=(0.5, 0.8, 0.95), th
                                 if d <= 0:
                                     break
                                 time.sleep(min(d, 0.002))
-                        reads = synth.request_reads(pool, tr[i][1], tr[i][2])
+                        reads = reads_fn(tr[i][1], tr[i][2])
                         while True:
                             try:
                                 rid = sv.submit(reads, **q)
@@ -130,7 +248,6 @@ def serving_bench(mt, ix, pool, seconds: float = 2.0, loads=(0.5, 0.8, 0.95), th
                                 time.sleep(0.0002)
                         ids[i] = (rid, arr_ns)
                         avail[k].release()
-                        done_n[k] += 1
                     avail[k].release()  # end marker
                 except Exception as e:  # noqa: BLE001
                     errs.append(e)
@@ -158,49 +275,52 @@ def serving_bench(mt, ix, pool, seconds: float = 2.0, loads=(0.5, 0.8, 0.95), th
                 x.start()
             for x in ts + ws:
                 x.join()
+            st = sv.stats()
         if errs:
             raise errs[0]
-        recs = [r for r in recs if r is not None]
-        return recs, t0
+        return [r for r in recs if r is not None], st
 
-    def summarize(recs, t0):
+    def summarize(recs):
         if not recs:
             return None
         lat = [(d - a) / 1e6 for a, _, d, _ in recs]
         reads = sum(r[3] for r in recs)
-        first = min(r[0] for r in recs)
-        last = max(r[2] for r in recs)
-        span = (last - first) / 1e9
+        span = (max(r[2] for r in recs) - min(r[0] for r in recs)) / 1e9
         return {"requests": len(recs), "reads": int(reads), "reads_per_s": round(reads / span, 1),
                 "p50_ms": round(_pct(lat, 50), 3), "p99_ms": round(_pct(lat, 99), 3),
                 "mean_ms": round(float(np.mean(lat)), 3)}
 
-    out = {"workload": "requests of U{1..50,000} reads x one length in {100..250} bp (16 lengths), 0.5% error, "
-                       "E=ceil(5% of length), min_hits=3, top_n=3, 500 Mbp index resident; Poisson arrivals",
-           "threads": threads, "n_streams": n_streams or 4, "max_batch_reads": max_batch_reads or 1 << 18}
-    # warm up the server path (allocator, pinned buffers)
-    recs, t0 = run_served(trace(99, 64, 1.0), paced=False)
-    # saturation: back to back for `seconds`
-    recs, t0 = run_served(trace(3, 100_000, 1.0), paced=False, stop_after=seconds)
-    sat = summarize(recs, t0)
-    out["saturated"] = sat
-    log(f"[serve] saturated: {sat}")
-    sat_rps = sat["reads_per_s"]
+    out = {"workload": workload, "threads": threads, "n_streams": n_streams or 4,
+           "max_batch_reads": max_batch_reads or 1 << 18, "trace_seconds": seconds, "runs_per_load": runs}
+    run_served(trace(99, 64, 1.0), paced=False)  # warm-up
+    recs, st = run_served(trace(3, 1_000_000, 1.0), paced=False, stop_after=min(seconds, 10.0))
+    out["saturated"] = summarize(recs)
+    out["saturated"]["server"] = st
+    out["mem_budget_bytes"] = st["mem_budget_bytes"]
+    log(f"[serve] saturated: {out['saturated']}")
+    sat_rps = out["saturated"]["reads_per_s"]
     out["traces"] = []
     for i, load in enumerate(loads):
         qps = load * sat_rps / mean_reads
-        n = max(20, int(qps * seconds))
-        recs, t0 = run_served(trace(3 + i, n, qps), paced=True)
-        sm = summarize(recs, t0)
-        sm.update({"offered_load": load, "qps": round(qps, 1)})
-        out["traces"].append(sm)
-        log(f"[serve] load {load}: {sm}")
-
+        per = []
+        for k in range(runs):
+            recs, st = run_served(trace(3 + i + 10 * k, max(20, int(qps * seconds)), qps), paced=True)
+            sm = summarize(recs)
+            sm["server"] = st
+            per.append(sm)
+        p50 = [x["p50_ms"] for x in per]
+        p99 = [x["p99_ms"] for x in per]
+        agg = {"offered_load": load, "qps": round(qps, 1), "runs": per,
+               "reads_per_s": round(float(np.mean([x["reads_per_s"] for x in per])), 1),
+               "p50_ms": round(float(np.median(p50)), 3), "p99_ms": round(float(np.median(p99)), 3),
+               "p50_spread_ms": [min(p50), max(p50)], "p99_spread_ms": [min(p99), max(p99)]}
+        out["traces"].append(agg)
+        log(f"[serve] load {load}: p50 {agg['p50_ms']} ms (spread {agg['p50_spread_ms']}), "
+            f"p99 {agg['p99_ms']} ms (spread {agg['p99_spread_ms']}), {agg['reads_per_s']:.3e} reads/s")
     if baseline_s <= 0:
         return out
-    # sequential per-request solves on the 80% trace
     qps = 0.8 * sat_rps / mean_reads
-    tr = trace(4, max(20, int(qps * seconds)), qps)
+    tr = trace(4, max(20, int(qps * baseline_s * 4)), qps)
     for name, mode in (("sequential_per_stage", mt.MT_MODE_PER_STAGE), ("sequential_fused", mt.MT_MODE_FUSED)):
         recs = []
         t0 = time.monotonic_ns()
@@ -212,38 +332,60 @@ def serving_bench(mt, ix, pool, seconds: float = 2.0, loads=(0.5, 0.8, 0.95), th
                 break
             if arr_ns > now:
                 time.sleep((arr_ns - now) / 1e9)
-            reads = synth.request_reads(pool, n, m)
+            reads = reads_fn(n, m)
             res = ix.classify(mt.to_device(reads), mode=mode, **q)
             res.to_host()
             res.free()
             recs.append((arr_ns, arr_ns, time.monotonic_ns(), n))
-        sm = summarize(recs, t0)
+        sm = summarize(recs)
         sm.update({"offered_load": 0.8, "qps": round(qps, 1), "of_trace_requests": len(tr)})
         out[name] = sm
         log(f"[serve] {name}: {sm}")
     return out
 
 
-def measured_valu(kernel: str):
-    """VALU wave-instructions per dispatch from the committed rocprofv3 SQ_INSTS_VALU
-    record of this kernel, or None when it is missing or was taken on a different
-    kernel source."""
-    import hashlib
-    path = os.path.join(ROOT, "profiles", "k_fused_valu_counters_500mbp_1m.json")
-    if kernel != "fused" or not os.path.exists(path):
-        return None
-    rec = json.load(open(path))
-    h = hashlib.sha256()
-    for src in rec["kernel_sources"]:
-        h.update(open(os.path.join(ROOT, src), "rb").read())
-    if h.hexdigest() != rec["source_sha256"]:
-        return None
-    return float(rec["per_dispatch"]["SQ_INSTS_VALU"])
+def cpu_model() -> str:
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
-# Integer VALU peak of the MI355X: 256 CUs x 4 SIMD16 units x 16 lanes x 2.4 GHz = 39.3 T lane-ops/s,
-# i.e. one wave64 VALU instruction per CU per cycle.
-VALU_WAVE_INSTR_PEAK = 256 * 2.4e9
+def cpu_baseline(ga, reads, q, single_reads: int, all_reads: int, runs: int = 3) -> dict:
+    """The oracle on a seeded sample of the headline reads: single-threaded and
+    on every core it may use (OMP_NUM_THREADS), each the median of `runs`."""
+    import oracle
+    oracle.set_threads(0)
+    t = time.time()
+    oix = oracle.Index(ga, 21, 11)
+    log(f"[cpu] oracle index built in {time.time() - t:.1f}s (not timed)")
+    rng = np.random.default_rng(7)
+    out = {}
+    for leg, threads, size in (("single", 1, single_reads), ("all", 0, all_reads)):
+        used = oracle.set_threads(threads)
+        idx = np.sort(rng.choice(reads.n, min(size, reads.n), replace=False))
+        sample = reads.subset(idx)
+        times, pairs = [], 0
+        for _ in range(runs):
+            t = time.perf_counter()
+            res = oix.classify(sample, q["min_hits"], q["top_n"], q["e_mode"], q["e_value"])
+            times.append(time.perf_counter() - t)
+            pairs = len(res["genome"])
+        med = float(np.median(times))
+        out[leg] = {"value": round(pairs / med, 1), "unit": "pairs/s", "reads_per_s": round(sample.n / med, 1),
+                    "cores": used, "runs_s": [round(x, 3) for x in times],
+                    "sample": f"{sample.n} reads drawn uniformly (seed 7) from the headline batch"}
+        log(f"[cpu] {leg}: {out[leg]}")
+    oracle.set_threads(0)
+    del oix
+    a = out["all"]
+    return {"value": a["value"], "unit": "pairs/s", "cores": a["cores"], "kind": "oracle",
+            "sample": a["sample"] + f", median of {runs} runs on {a['cores']} threads",
+            "reads_per_s": a["reads_per_s"], "runs_s": a["runs_s"], "cpu_model": cpu_model(),
+            "host_cpus": os.cpu_count(), "single_thread": out["single"]}
 
 
 def main() -> int:
@@ -251,35 +393,19 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--mode", default="fused", choices=["fused", "graph", "per_stage"],
-                    help="fused: the fused kernel (launched eagerly); graph: the same launches replayed as one "
-                         "HIP graph; per_stage: one launch per step")
-    ap.add_argument("--E", type=int, default=7)
-    ap.add_argument("--reads", type=int, default=1_000_000)
-    ap.add_argument("--top-n", type=int, default=3, help="candidates kept per read (0 keeps all)")
-    ap.add_argument("--workload", default="batched", choices=["batched", "uneven", "strains"],
-                    help="batched: 500 Mbp, 1M x 150 bp, E=7 (the metric's workload); uneven: same database, "
-                         "2M reads of 75-300 bp plus 5%% of 1-10 kbp, E=ceil(5%% of length); strains: 2,000 "
-                         "near-duplicate strain genomes (4 Gbp), 10M x 150 bp at 1%% error, E=7")
-    ap.add_argument("--cpu-reads", type=int, default=-1,
-                    help="reads in the oracle's timed sample (0 skips the CPU baseline; default: 1M for batched, "
-                         "2000 for uneven, 0 for strains)")
-    ap.add_argument("--no-timing", action="store_true", help="do not record per-stage HIP events")
-    ap.add_argument("--genomes", type=int, default=200, help="genomes of 2.5 Mbp in the database")
-    ap.add_argument("--autotune", type=int, default=-1,
-                    help="1: time the filter variants on the batch (up to 2M reads) first and keep the fastest per "
-                         "bucket (default: on for the uneven workload); 0: built-in defaults")
-    ap.add_argument("--serving", type=int, default=1,
-                    help="1: also measure the served workload (batched workload only); 0: skip it")
-    ap.add_argument("--strands-bench", type=int, default=1,
-                    help="also time both-strand classification of the batch with half its reads reversed")
-    ap.add_argument("--serve-seconds", type=float, default=2.0, help="length of each served trace")
-    ap.add_argument("--serve-streams", type=int, default=0, help="server worker streams (0: library default, 4)")
-    ap.add_argument("--serve-threads", type=int, default=8, help="client threads submitting served requests")
-    ap.add_argument("--serve-max-batch", type=int, default=0,
-                    help="reads per served device batch (0: library default, 262,144)")
-    ap.add_argument("--serve-only", action="store_true",
-                    help="only the served workload (no batched timing, no sequential baselines)")
+    ap.add_argument("--workload", default="strains", choices=["strains", "batched", "uneven"],
+                    help="the headline workload (default: the strain database, the largest configuration)")
+    ap.add_argument("--mode", default="fused", choices=["fused", "graph", "per_stage"])
+    ap.add_argument("--reads", type=int, default=0, help="reads of the headline workload (0: its full size)")
+    ap.add_argument("--extras", type=int, default=1,
+                    help="1: also the other workloads, forms, serving and the CPU baseline; 0: the headline only")
+    ap.add_argument("--cpu", type=int, default=1, help="0 skips the CPU baseline")
+    ap.add_argument("--cpu-single-reads", type=int, default=60_000)
+    ap.add_argument("--cpu-all-reads", type=int, default=600_000)
+    ap.add_argument("--serve-seconds", type=float, default=20.0, help="length of each served trace")
+    ap.add_argument("--serve-runs", type=int, default=2, help="traces per offered load")
+    ap.add_argument("--only", default="", help="comma list of extras to run (strains_forms, e2e, cpu, "
+                                                 "strains_served, batched, uneven, serving); empty: all")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times), to scale HBM byte counters")
     args = ap.parse_args()
@@ -299,282 +425,309 @@ def main() -> int:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(reads are independent; see the design notes for how it would shard).", file=sys.stderr)
         return 2
+    only = set(x for x in args.only.split(",") if x)
+
+    def want(name):
+        return args.extras and (not only or name in only)
 
     import torch
     import paper_2311_02029_amd as mt
     import synth
 
     torch.cuda.set_device(0)
-    t = time.time()
-    if args.cpu_reads < 0:
-        args.cpu_reads = {"batched": 1_000_000, "uneven": 2000, "strains": 0}[args.workload]
-    e_mode, e_value = mt.MT_E_FIXED, args.E
-    if args.workload == "strains":
-        log("[bench] generating 400 roots x 5 strains x 2 Mbp and the reads ...")
-        db = synth.workload_strains_db()
-        reads = synth.workload_strain_reads(db, args.reads if args.reads != 1_000_000 else 10_000_000)
-        workload = (f"strains: 2,000 genomes (400 roots x 5 strains, 1-5% divergence) = 4 Gbp, {reads.n} x 150 bp "
-                    f"at 1% error, k=21 w=11, min_hits=3, top_n={args.top_n}, E={args.E}")
-    elif args.workload == "uneven":
-        log("[bench] generating the database and the uneven reads ...")
-        db = synth.workload_batched_db(n_genomes=args.genomes)
-        reads = synth.workload_uneven_reads(db, args.reads if args.reads != 1_000_000 else 2_000_000)
-        e_mode, e_value = mt.MT_E_CEIL_PERMILLE, 50
-        workload = (f"uneven: 500 Mbp / 200 genomes, {reads.n} reads (95% of 75-300 bp, 5% of 1-10 kbp), k=21 w=11, "
-                    f"min_hits=3, top_n={args.top_n}, E=ceil(5% of length)")
-    else:
-        db = synth.workload_batched_db(n_genomes=args.genomes)
-        reads = synth.workload_batched_reads(db, args.reads)
-        workload = (f"500 Mbp / 200 genomes, {reads.n // 1000}k x 150 bp reads, k=21 w=11, min_hits=3, top_n={args.top_n}, "
-                    f"E={args.E}")
-    log(f"[bench] data generated in {time.time() - t:.1f}s: {db.n} genomes, {reads.n} reads, "
-        f"{int(reads.offsets[-1])} bases")
-    pool = None
-    if args.serving and args.workload == "batched":
+    t_start = time.time()
+    mode = {"fused": mt.MT_MODE_FUSED, "graph": mt.MT_MODE_FUSED_GRAPH, "per_stage": mt.MT_MODE_PER_STAGE}[args.mode]
+    extras = {}
+
+    def guarded(name, fn):
         t = time.time()
-        pool = synth.served_read_pool(db)
-        log(f"[bench] served read pool generated in {time.time() - t:.1f}s")
-    ga = db.ascii()
-    dgen = mt.to_device(ga)
-    dreads = mt.to_device(reads)
-    del db
-    torch.cuda.synchronize()
-    log(f"[bench] inputs on the device")
-    mt.mt_set_timing(True)
+        try:
+            extras[name] = fn()
+        except Exception as e:  # noqa: BLE001  (an extra must not lose the headline)
+            extras[name] = {"error": f"{type(e).__name__}: {e}"}
+        log(f"[bench] {name} done in {time.time() - t:.1f}s")
+
+    # ------------------------------------------------------------ headline --
     t = time.time()
-    ix = mt.Index(dgen, 21, 11)
+    if args.workload == "strains":
+        db = synth.workload_strains_db()
+        reads = synth.workload_strain_reads(db, args.reads or 10_000_000)
+        q = dict(min_hits=3, top_n=3, e_mode=mt.MT_E_FIXED, e_value=7)
+        workload = (f"dense-candidate strains: 2,000 genomes (400 random roots x 5 substitution-only strains, "
+                    f"1-5% divergence) x 2 Mbp = 4 Gbp, taxon = strain; {reads.n} reads x 150 bp at 1% error; "
+                    f"k=21 w=11, min_hits=3, top_n=3, E=7")
+    elif args.workload == "uneven":
+        db = synth.workload_batched_db()
+        reads = synth.workload_uneven_reads(db, args.reads or 2_000_000)
+        q = dict(min_hits=3, top_n=3, e_mode=mt.MT_E_CEIL_PERMILLE, e_value=50)
+        workload = (f"uneven: 500 Mbp / 200 genomes, {reads.n} reads (95% of 75-300 bp, 5% of 1-10 kbp), k=21 w=11, "
+                    f"min_hits=3, top_n=3, E=ceil(5% of length)")
+    else:
+        db = synth.workload_batched_db()
+        reads = synth.workload_batched_reads(db, args.reads or 1_000_000)
+        q = dict(min_hits=3, top_n=3, e_mode=mt.MT_E_FIXED, e_value=7)
+        workload = f"batched: 500 Mbp / 200 genomes, {reads.n} x 150 bp reads, k=21 w=11, min_hits=3, top_n=3, E=7"
+    ga = db.ascii()
+    del db
+    log(f"[bench] headline data generated in {time.time() - t:.1f}s: {ga.n} genomes, {reads.n} reads")
+    dreads = mt.to_device(reads)
+    t = time.time()
+    ix = mt.Index(mt.to_device(ga), 21, 11)
     torch.cuda.synchronize()
     index_s = time.time() - t
-    log(f"[bench] index stages (ms): {mt.last_timings()}")
-    mt.mt_set_timing(False)
     info = ix.info()
     log(f"[bench] index built in {index_s:.2f}s: {info['n_minimizers']} minimizers, {info['n_keys']} keys, "
         f"{info['device_bytes'] / 2**30:.2f} GiB")
-    del dgen
+    if args.workload == "uneven":
+        ix.autotune(dreads, reps=3, **q)
+    qm = dict(q, mode=mode)
+    head, stats = time_form(mt, ix, dreads, qm, args.steps, args.warmup, timing=True)
+    log(f"[bench] headline {args.mode}: {head['ms_per_step']} ms/step, {head['pairs_per_s']:.3e} pairs/s, "
+        f"{head['reads_per_s']:.3e} reads/s; stages {head['stages_ms']}")
+    # the same steps without event timing: the figure the line reports
+    plain, _ = time_form(mt, ix, dreads, qm, args.steps, 1, timing=False)
+    log(f"[bench] headline without event timing: {plain['ms_per_step']} ms/step")
 
-    if args.serve_only:
-        sv = serving_bench(mt, ix, pool, seconds=args.serve_seconds, n_streams=args.serve_streams,
-                           max_batch_reads=args.serve_max_batch, baseline_s=0, threads=args.serve_threads)
-        print(json.dumps({"metric": "served reads/s; p50/p99 request latency", "serving": sv}), flush=True)
-        return 0
-
-    mode = {"fused": mt.MT_MODE_FUSED, "graph": mt.MT_MODE_FUSED_GRAPH, "per_stage": mt.MT_MODE_PER_STAGE}[args.mode]
-    q = dict(min_hits=3, top_n=args.top_n, e_mode=e_mode, e_value=e_value, mode=mode)
-
-    tune = None
-    if args.autotune < 0:
-        args.autotune = 1 if args.workload == "uneven" else 0
-    if args.autotune:
-        t = time.time()
-        sample = mt.to_device(reads.subset(np.arange(min(reads.n, 2_000_000))))
-        info = ix.autotune(sample, reps=3, **{k: v for k, v in q.items() if k != "mode"})
-        del sample
-        tune = {b["name"]: b["current"] for b in info if b["pairs"]}
-        log(f"[bench] autotuned in {time.time() - t:.1f}s: "
-            + "; ".join(f"{b['name']} ({b['pairs']} pairs): " + ", ".join(f"{k} {v:.3f} ms" for k, v in b["ms"].items())
-                        for b in info if b["pairs"]))
-
-    n_cands = 0
-    for i in range(args.warmup):
-        t = time.time()
-        r = ix.classify(dreads, **q)
-        n_cands = r.n_cands
-        r.free()
-        log(f"[bench] warmup step {i}: {time.time() - t:.3f}s")
-    log(f"[bench] warmup done ({args.warmup} steps), {n_cands} candidates per step")
-
-    mt.mt_set_timing(not args.no_timing)
-    stage_ms: dict[str, float] = {}
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        r = ix.classify(dreads, **q)
-        n_cands = r.n_cands
-        r.free()
-        if not args.no_timing:
-            for name, ms in mt.last_timings():
-                stage_ms[name] = stage_ms.get(name, 0.0) + ms
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    mt.mt_set_timing(False)
-    ms_per_step = (t1 - t0) * 1000.0 / args.steps
-    pairs_s = n_cands / (ms_per_step / 1000.0)
-    reads_s = reads.n / (ms_per_step / 1000.0)
-    stages = {k: v / args.steps for k, v in stage_ms.items()}
-    log(f"[bench] {ms_per_step:.3f} ms/step, {pairs_s:.3e} pairs/s, {reads_s:.3e} reads/s")
-    log(f"[bench] stages (ms/step): {json.dumps({k: round(v, 4) for k, v in stages.items()})}")
-
-    # Roofline of the dominant kernel from the live HIP-event timings.
+    # roofline of the dominant kernel (the fused kernel) from its live HIP-event time
     roofline = None
-    stats = mt.last_stats() if hasattr(mt, "last_stats") else {}
-    if stages:
-        dom = max(stages, key=stages.get)
-        dur_s = stages[dom] / 1000.0
-        if dom == "lookup" and stats.get("n_minimizers"):
-            alg = stats["n_minimizers"] * LOOKUP_BYTES_PER_MIN
-        elif dom == "fused" and stats.get("n_minimizers"):
-            alg = (stats["fused_bases"] + 16 * stats["fused_minimizers"] + 16 * stats["fused_window_blocks"]
-                   + 19 * stats["fused_cands"] + 11 * stats["fused_reads"])
-        else:
-            alg = None
-        if alg is not None and dur_s > 0:
-            ach = alg / dur_s / 1e9
-            roofline = {"kernel": dom, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                        "traffic": measured_traffic(dom) if args.workload == "batched" else None,
-                        "avg_ms": round(stages[dom], 4), "algorithmic_bytes": int(alg)}
-            if roofline["traffic"]:
-                # the same launch against its counter-measured HBM bytes
-                roofline["traffic_gbs"] = round(roofline["traffic"] / dur_s / 1e9, 1)
-                roofline["traffic_frac"] = round(roofline["traffic_gbs"] / HBM_PEAK_GBS, 4)
-            vi = measured_valu(dom) if args.workload == "batched" and args.E == 7 else None
-            if vi is not None:
-                # counter-measured VALU issue against the integer VALU peak (same live duration)
-                roofline["valu"] = {"wave_instructions": int(vi), "peak_lane_ops_per_s": VALU_WAVE_INSTR_PEAK * 64,
-                                    "issue_frac": round(vi / (dur_s * VALU_WAVE_INSTR_PEAK), 4)}
-            if dom == "fused":
-                # the filter's useful integer work by the op model (one more, untimed classification)
-                r = ix.classify(dreads, **q)
-                useful = filter_useful_ops(r.to_host(), reads.lengths())
-                r.free()
-                roofline["filter_useful_ops"] = {
-                    "lane_ops": int(useful),
-                    "model": "per pair 6*(2E+1)*ceil(m/64) + 8*(2E+1)*(min(approx,E)+1) int32 ops",
-                    "frac_of_peak_over_kernel_time": round(useful / (dur_s * VALU_WAVE_INSTR_PEAK * 64), 5)}
-        else:
-            roofline = {"kernel": dom, "bound": "hbm", "achieved": None, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": None, "traffic": None, "avg_ms": round(stages[dom], 4)}
-
-    # Stage 1 (containment search) on the same resident index and batch.
-    containment = None
-    if args.workload == "batched" and hasattr(ix, "containment"):
-        hits = ix.containment(dreads)  # warm
-        torch.cuda.synchronize()
-        reps = 5
-        t = time.perf_counter()
-        for _ in range(reps):
-            hits = ix.containment(dreads)
-            sel, mx = mt.select_genomes(hits, 1, 10_000)
-        torch.cuda.synchronize()
-        c_ms = (time.perf_counter() - t) * 1000.0 / reps
-        total = int(hits.cpu().numpy().view(np.uint64).sum())
-        containment = {"ms": round(c_ms, 3), "reads_per_s": round(reads.n / (c_ms / 1000.0), 1),
-                       "seed_hits_per_s": round(total / (c_ms / 1000.0), 1), "seed_hits": total,
-                       "genomes": int(hits.numel()), "kept_at_1e-4": int(sel.numel()), "max_hits": mx}
-        log(f"[bench] containment: {json.dumps(containment)}")
-
-    # Table 1's filter choice on the batch's own pair stream (its candidates).
-    filters = None
-    if args.workload == "batched" and hasattr(mt, "MT_FILTER_HAMMING"):
-        r = ix.classify(dreads, **q)
-        h = r.to_host()
+    stages = head["stages_ms"]
+    if "fused" in stages and stats.get("fused_reads"):
+        dur_s = stages["fused"] / 1000.0
+        alg = fused_alg_bytes(stats)
+        ach = alg / dur_s / 1e9
+        recname = {"strains": "k_fused_hbm_counters_4gbp_10m.json",
+                   "batched": "k_fused_hbm_counters_500mbp_1m.json"}.get(args.workload)
+        rec = counter_record(recname) if recname and not args.reads else None
+        roofline = {"kernel": "k_fused", "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                    "traffic": int(rec["traffic_bytes_per_dispatch"]) if rec else None,
+                    "avg_ms": round(stages["fused"], 4), "algorithmic_bytes": alg, "model": FUSED_MODEL,
+                    "units": {k: int(stats[k]) for k in ("fused_reads", "fused_bases", "fused_minimizers", "fused_occ",
+                                                         "fused_window_blocks", "fused_cands") if k in stats}}
+        if rec:
+            roofline["traffic_gbs"] = round(rec["traffic_bytes_per_dispatch"] / dur_s / 1e9, 1)
+            roofline["traffic_frac"] = round(roofline["traffic_gbs"] / HBM_PEAK_GBS, 4)
+        vrec = counter_record({"strains": "k_fused_valu_counters_4gbp_10m.json",
+                               "batched": "k_fused_valu_counters_500mbp_1m.json"}.get(args.workload, "-"))
+        if vrec and not args.reads:
+            vi = float(vrec["per_dispatch"]["SQ_INSTS_VALU"])
+            roofline["valu"] = {"wave_instructions": int(vi), "peak_lane_ops_per_s": VALU_LANE_OPS_PEAK,
+                                "issue_frac": round(vi / (dur_s * VALU_WAVE_INSTR_PEAK), 4),
+                                "per_read": {k: round(float(v) / stats["fused_reads"], 1)
+                                             for k, v in vrec["per_dispatch"].items()}}
+        r = ix.classify(dreads, **qm)
+        host = r.to_host()
         r.free()
-        co = np.asarray(h["cand_offsets"], dtype=np.int64)
-        pr = np.repeat(np.arange(len(co) - 1, dtype=np.int64), np.diff(co)).astype(np.int32)
-        pe = np.asarray(h["read_E"], dtype=np.uint16)[pr]
-        dev = [torch.from_numpy(x).cuda() for x in (pr, np.asarray(h["genome"]).view(np.int32),
-                                                    np.asarray(h["diag"], dtype=np.int64), pe.view(np.int16))]
-        filters = {}
-        for name, kind in (("obstacle", mt.MT_FILTER_OBSTACLE), ("hamming", mt.MT_FILTER_HAMMING),
-                           ("base_count", mt.MT_FILTER_BASE_COUNT), ("qgram", mt.MT_FILTER_QGRAM),
-                           ("shd", mt.MT_FILTER_SHD)):
-            ix.filter_pairs(dreads, *dev, kind=kind)  # warm
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            for _ in range(5):
-                _, acc = ix.filter_pairs(dreads, *dev, kind=kind)
-            torch.cuda.synchronize()
-            f_ms = (time.perf_counter() - t) * 1000.0 / 5
-            filters[name] = {"ms": round(f_ms, 3), "pairs_per_s": round(len(pr) / (f_ms / 1000.0), 1),
-                             "accepted": round(float(acc.float().mean().item()), 4)}
-        filters["pairs"] = int(len(pr))
-        log(f"[bench] filters on the pair stream (mt_filter_pairs_kind, incl. read packing): {json.dumps(filters)}")
+        uo = int(useful_ops(host, reads.lengths()).sum())
+        roofline["filter_useful_ops"] = {
+            "lane_ops": uo, "model": "per pair 6*(2E+1)*ceil(m/64) + 8*(2E+1)*(min(approx,E)+1) int32 ops",
+            "frac_of_peak_over_kernel_time": round(uo / (dur_s * VALU_LANE_OPS_PEAK), 5)}
+    log(f"[bench] roofline: {json.dumps(roofline)}")
 
-    # Stage 3b (relative abundance) on the batch's classification result.
-    abundance = None
-    if args.workload == "batched":
-        r = ix.classify(dreads, **q)
-        ix.abundance(r)  # warm
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        for _ in range(5):
-            counts, ab, kept = ix.abundance(r)
-        torch.cuda.synchronize()
-        a_ms = (time.perf_counter() - t) * 1000.0 / 5
-        abundance = {"ms": round(a_ms, 3), "reads_per_s": round(reads.n / (a_ms / 1000.0), 1), "kept_taxa": kept,
-                     "max_abundance": round(float(ab.max().item()), 6)}
-        r.free()
-        log(f"[bench] abundance (mt_abundance on the classification result): {json.dumps(abundance)}")
+    # ------------------------------------------------------ other forms --
+    if want("strains_forms"):
+        def forms():
+            out = {}
+            for name, m in (("per_stage", mt.MT_MODE_PER_STAGE), ("graph", mt.MT_MODE_FUSED_GRAPH),
+                            ("fused", mt.MT_MODE_FUSED)):
+                if m == mode:
+                    continue
+                res, _ = time_form(mt, ix, dreads, dict(q, mode=m), max(3, args.steps // 4), 1, timing=False)
+                res.pop("stages_ms")
+                out[name] = res
+                log(f"[bench] headline {name}: {res}")
+            out[args.mode] = {k: v for k, v in plain.items() if k != "stages_ms"}
+            return out
+        guarded("forms", forms)
+    if want("e2e"):
+        guarded("end_to_end", lambda: end_to_end(mt, ix, reads, qm, max(3, args.steps // 4), 1))
+        log(f"[bench] end to end: {extras.get('end_to_end')}")
+    if want("cpu") and args.cpu:
+        guarded("cpu_baseline", lambda: cpu_baseline(ga, reads, q, args.cpu_single_reads, args.cpu_all_reads))
+    if want("strains_served") and args.workload == "strains":
+        def strains_served():
+            # requests of the headline's reads (the first n of the batch), a tight memory budget
+            rq = dict(q)
 
-    # Both strands: the batch with half its reads taken from the reverse strand.
-    strands = None
-    if args.workload == "batched" and args.strands_bench:
-        flipped = synth.from_reverse_strand(np.random.default_rng(77), reads, 0.5)
-        dflip = mt.to_device(flipped)
-        one = ix.classify(dflip, **q).to_host()
-        strands = {}
-        for name, m in (("fused", q["mode"]), ("per_stage", mt.MT_MODE_PER_STAGE)):
-            r = ix.classify(dflip, **dict(q, mode=m), strands=2)  # warm
-            r.free()
-            torch.cuda.synchronize()
-            t = time.perf_counter()
-            for _ in range(3):
-                r = ix.classify(dflip, **dict(q, mode=m), strands=2)
-                torch.cuda.synchronize()
-                nc2 = r.n_cands
-                r.free()
-            s_ms = (time.perf_counter() - t) * 1000.0 / 3
-            strands[name] = {"ms": round(s_ms, 3), "reads_per_s": round(flipped.n / (s_ms / 1000.0), 1),
-                             "pairs_per_s": round(nc2 / (s_ms / 1000.0), 1)}
-        r = ix.classify(dflip, **q, strands=2)
-        two = r.to_host()
-        r.free()
-        strands.update({"pairs": int(len(two["genome"])),
-                        "accepted_both": round(float(two["read_accepted"].mean()), 4),
-                        "accepted_forward_only": round(float(one["read_accepted"].mean()), 4),
-                        "reverse_cands": round(float(two["strand"].mean()), 4)})
-        del dflip
-        log(f"[bench] both strands (two-strand read set; fused kernel / per-stage chain): {json.dumps(strands)}")
+            def reads_fn(n, m):
+                return synth.SeqSet(seq=reads.seq[:n * 150], offsets=reads.offsets[:n + 1])
+            budget = 768 << 20
+            return serving_bench(mt, ix, None, seconds=args.serve_seconds / 2, loads=(0.8,), runs=2,
+                                 baseline_s=0, mem_budget=budget, max_batch_reads=1 << 18, q=rq,
+                                 reads_fn=reads_fn,
+                                 workload="the headline database resident; Poisson requests of U{1..50,000} reads "
+                                          "of the headline batch (150 bp, 1% error), E=7; admission by a "
+                                          f"{budget >> 20} MiB device-memory budget")
+        guarded("strains_served", strains_served)
+    del ix, dreads
+    torch.cuda.empty_cache()
 
-    serving = None
-    if pool is not None:
-        serving = serving_bench(mt, ix, pool, seconds=args.serve_seconds, n_streams=args.serve_streams,
-                                max_batch_reads=args.serve_max_batch, threads=args.serve_threads)
-
-    cpu = None
-    if args.cpu_reads > 0:
-        import oracle
+    # ------------------------------------------------- batched workload --
+    bdb = None
+    if want("batched") or want("serving") or want("uneven"):
         t = time.time()
-        oix = oracle.Index(ga, 21, 11)
-        log(f"[bench] oracle index built in {time.time() - t:.1f}s (not timed)")
-        sample = reads.subset(np.arange(min(args.cpu_reads, reads.n)))
-        t = time.perf_counter()
-        out = oix.classify(sample, 3, args.top_n, e_mode, e_value)
-        dt = time.perf_counter() - t
-        cpu = {"value": round(len(out["genome"]) / dt, 1), "unit": "pairs/s", "cores": 1, "kind": "oracle",
-               "reads_per_s": round(sample.n / dt, 1),
-               "sample": f"first {sample.n} reads of the batch, single-threaded C oracle, {dt:.1f}s"}
-        log(f"[bench] oracle: {cpu['value']:.3e} pairs/s on {sample.n} reads in {dt:.1f}s")
+        bdb = synth.workload_batched_db()
+        bga = bdb.ascii()
+        bix = mt.Index(mt.to_device(bga), 21, 11)
+        log(f"[bench] 500 Mbp database and index in {time.time() - t:.1f}s")
+    if want("batched"):
+        def batched():
+            breads = synth.workload_batched_reads(bdb, 1_000_000)
+            dr = mt.to_device(breads)
+            out = {"workload": "batched: 500 Mbp / 200 genomes (GC ~ U(0.3, 0.7)), 1M x 150 bp, 0.1-1% "
+                               "substitutions, 0.01-0.1% indels, k=21 w=11, min_hits=3, top_n=3", "E_sweep": {}}
+            for E in (0, 3, 7, 15):
+                row = {}
+                for name, m in (("fused", mt.MT_MODE_FUSED), ("per_stage", mt.MT_MODE_PER_STAGE)):
+                    res, st = time_form(mt, bix, dr, dict(min_hits=3, top_n=3, e_value=E, mode=m), 10, 2,
+                                        timing=True)
+                    row[name] = res
+                    if name == "fused" and "fused" in res["stages_ms"]:
+                        d = res["stages_ms"]["fused"] / 1000.0
+                        alg = fused_alg_bytes(st)
+                        row["fused_roofline"] = {"kernel": "k_fused", "bound": "hbm", "achieved": round(alg / d / 1e9, 1),
+                                                 "frac": round(alg / d / 1e9 / HBM_PEAK_GBS, 4), "avg_ms": round(d * 1e3, 4),
+                                                 "algorithmic_bytes": alg}
+                    if name == "per_stage":
+                        r = bix.classify(dr, min_hits=3, top_n=3, e_value=E, mode=m)
+                        host = r.to_host()
+                        r.free()
+                        uo = useful_ops(host, breads.lengths())
+                        bk = pair_bucket(host, breads.lengths())
+                        per = {}
+                        for b in np.unique(bk):
+                            key = "filter " + BUCKET_NAMES[b]
+                            if key in res["stages_ms"]:
+                                ms = res["stages_ms"][key]
+                                per[BUCKET_NAMES[b]] = {"pairs": int((bk == b).sum()), "ms": ms,
+                                                        "useful_ops_frac": round(float(uo[bk == b].sum()) /
+                                                                                 (ms / 1e3 * VALU_LANE_OPS_PEAK), 4)}
+                        row["per_stage_filter"] = per
+                row["fused_over_per_stage"] = round(row["per_stage"]["ms_per_step"] / row["fused"]["ms_per_step"], 3)
+                out["E_sweep"][str(E)] = row
+                log(f"[bench] batched E={E}: fused {row['fused']['ms_per_step']} ms, per-stage "
+                    f"{row['per_stage']['ms_per_step']} ms")
+            res, _ = time_form(mt, bix, dr, dict(min_hits=3, top_n=3, e_value=7, mode=mt.MT_MODE_FUSED_GRAPH), 10, 2,
+                               timing=False)
+            res.pop("stages_ms")
+            out["graph_E7"] = res
+            # stage 1 on the same index and batch
+            hits = bix.containment(dr)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(5):
+                hits = bix.containment(dr)
+                sel, mx = mt.select_genomes(hits, 1, 10_000)
+            torch.cuda.synchronize()
+            c_ms = (time.perf_counter() - t0) * 1000.0 / 5
+            total = int(hits.cpu().numpy().view(np.uint64).sum())
+            out["containment"] = {"ms": round(c_ms, 3), "reads_per_s": round(breads.n / (c_ms / 1000.0), 1),
+                                  "seed_hits_per_s": round(total / (c_ms / 1000.0), 1), "seed_hits": total,
+                                  "kept_at_1e-4": int(sel.numel()), "max_hits": mx}
+            # Table 1's filters on the batch's own pair stream
+            r = bix.classify(dr, min_hits=3, top_n=3, e_value=7, mode=mt.MT_MODE_FUSED)
+            h = r.to_host()
+            co = np.asarray(h["cand_offsets"], dtype=np.int64)
+            pr = np.repeat(np.arange(len(co) - 1, dtype=np.int64), np.diff(co)).astype(np.int32)
+            pe = np.asarray(h["read_E"], dtype=np.uint16)[pr]
+            dev = [torch.from_numpy(x).cuda() for x in (pr, np.asarray(h["genome"]).view(np.int32),
+                                                        np.asarray(h["diag"], dtype=np.int64), pe.view(np.int16))]
+            filters = {}
+            for name, kind in (("obstacle", mt.MT_FILTER_OBSTACLE), ("hamming", mt.MT_FILTER_HAMMING),
+                               ("base_count", mt.MT_FILTER_BASE_COUNT), ("qgram", mt.MT_FILTER_QGRAM),
+                               ("shd", mt.MT_FILTER_SHD)):
+                bix.filter_pairs(dr, *dev, kind=kind)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(5):
+                    _, acc = bix.filter_pairs(dr, *dev, kind=kind)
+                torch.cuda.synchronize()
+                f_ms = (time.perf_counter() - t0) * 1000.0 / 5
+                filters[name] = {"ms": round(f_ms, 3), "pairs_per_s": round(len(pr) / (f_ms / 1000.0), 1),
+                                 "accepted": round(float(acc.float().mean().item()), 4)}
+            filters["pairs"] = int(len(pr))
+            out["filters"] = filters
+            # stage 3b on the classification result
+            bix.abundance(r)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(5):
+                counts, ab, kept = bix.abundance(r)
+            torch.cuda.synchronize()
+            a_ms = (time.perf_counter() - t0) * 1000.0 / 5
+            out["abundance"] = {"ms": round(a_ms, 3), "kept_taxa": kept, "max_abundance": round(float(ab.max().item()), 6)}
+            r.free()
+            # both strands: half the reads taken from the reverse strand
+            flipped = synth.from_reverse_strand(np.random.default_rng(77), breads, 0.5)
+            dflip = mt.to_device(flipped)
+            st = {}
+            for name, m in (("fused", mt.MT_MODE_FUSED), ("per_stage", mt.MT_MODE_PER_STAGE)):
+                res, _ = time_form(mt, bix, dflip, dict(min_hits=3, top_n=3, e_value=7, mode=m, strands=2), 3, 1,
+                                   timing=False)
+                res.pop("stages_ms")
+                st[name] = res
+            out["strands"] = st
+            return out
+        guarded("batched", batched)
+    if want("serving"):
+        def serving():
+            pool = synth.served_read_pool(bdb)
+            return serving_bench(mt, bix, pool, seconds=args.serve_seconds, runs=args.serve_runs,
+                                 workload="requests of U{1..50,000} reads x one length in {100..250} bp (16 lengths), "
+                                          "0.5% error, E=ceil(5% of length), min_hits=3, top_n=3, 500 Mbp index "
+                                          "resident; Poisson arrivals")
+        guarded("serving", serving)
+    if want("uneven"):
+        def uneven():
+            ur = synth.workload_uneven_reads(bdb, 2_000_000)
+            dr = mt.to_device(ur)
+            uq = dict(min_hits=3, top_n=3, e_mode=mt.MT_E_CEIL_PERMILLE, e_value=50)
+            t0 = time.time()
+            tune = bix.autotune(dr, reps=3, **uq)
+            out = {"workload": "uneven: 500 Mbp; 2M reads, 95% of U{75..300} bp, 5% of U{1000..10000} bp at 2% "
+                               "substitutions + 3% indels; E=ceil(5% of length); autotuned",
+                   "autotune_s": round(time.time() - t0, 1),
+                   "tuning": {b["name"]: b["current"] for b in tune if b["pairs"]}}
+            for name, m in (("fused", mt.MT_MODE_FUSED), ("per_stage", mt.MT_MODE_PER_STAGE),
+                            ("graph", mt.MT_MODE_FUSED_GRAPH)):
+                res, _ = time_form(mt, bix, dr, dict(uq, mode=m), 3, 1, timing=(name != "graph"))
+                out[name] = res
+            out["fused_over_per_stage"] = round(out["per_stage"]["ms_per_step"] / out["fused"]["ms_per_step"], 3)
+            r = bix.classify(dr, mode=mt.MT_MODE_PER_STAGE, **uq)
+            host = r.to_host()
+            r.free()
+            uo = useful_ops(host, ur.lengths())
+            bk = pair_bucket(host, ur.lengths())
+            per = {}
+            for b in np.unique(bk):
+                key = "filter " + BUCKET_NAMES[b]
+                ms = out["per_stage"]["stages_ms"].get(key)
+                if ms:
+                    per[BUCKET_NAMES[b]] = {"pairs": int((bk == b).sum()), "ms": ms,
+                                            "useful_ops_frac": round(float(uo[bk == b].sum()) /
+                                                                     (ms / 1e3 * VALU_LANE_OPS_PEAK), 4)}
+            out["per_stage_filter"] = per
+            return out
+        guarded("uneven", uneven)
 
-    out = {
-        "metric": METRIC, "value": round(pairs_s, 1), "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
+    line = {
+        "metric": METRIC, "value": plain["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": plain["ms_per_step"], "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "u64", "data": "synthetic",
         "config": {"workload": workload, "reads": reads.n, "bases": int(reads.offsets[-1]),
-                   "pairs_per_step": int(n_cands), "mode": args.mode, "parallelism": "single GPU"},
-        "reads_per_s": round(reads_s, 1),
+                   "pairs_per_step": plain["pairs"], "mode": args.mode, "parallelism": "single GPU",
+                   "inputs": "reads and index resident in HBM"},
+        "reads_per_s": plain["reads_per_s"],
         "index_build_s": round(index_s, 3),
-        "stages_ms": {k: round(v, 4) for k, v in stages.items()},
+        "stages_ms": head["stages_ms"],
         "roofline": roofline,
-        "filter_tuning": tune,
-        "cpu_baseline": cpu,
-        "containment": containment,
-        "filters": filters,
-        "strands": strands,
-        "abundance": abundance,
-        "serving": serving,
+        "cpu_baseline": extras.pop("cpu_baseline", None),
+        "end_to_end": extras.pop("end_to_end", None),
+        "forms": extras.pop("forms", None),
     }
-    print(json.dumps(out), flush=True)
+    line.update(extras)
+    line["bench_wall_s"] = round(time.time() - t_start, 1)
+    print(json.dumps(line), flush=True)
     return 0
 
 

@@ -202,7 +202,9 @@ int mt_result_strands(const mt_result *res, const uint8_t **strand);
  * in units of 2^-32 read (exact integers); a taxon is kept iff
  * counts[t] * cutoff_den >= (sum of counts) * cutoff_num (the paper drops taxa
  * below 0.01%: 1 / 10000); abundance[t] = counts[t] / (sum of kept counts) as
- * a correctly rounded double, 0 for dropped taxa and when no read is mapped.
+ * the nearest double of the exact ratio (rounded once, ties to even, also when
+ * the sum needs more than 53 bits), 0 for dropped taxa and when no read is
+ * mapped.  The sums are 64-bit: up to 2^32 mapped reads per result.
  * counts (uint64) and abundance (double): device arrays of n_taxa entries;
  * *n_kept (host) receives the number of kept taxa.  Errors: null arguments,
  * cutoff_den = 0, a result whose taxon count differs from the index's. */
@@ -228,6 +230,7 @@ typedef struct mt_stats {
     uint64_t fused_minimizers;    /* their minimizers */
     uint64_t fused_window_blocks; /* 64-base reference blocks their filter read */
     uint64_t fused_cands;         /* their candidates */
+    uint64_t fused_occ;           /* entries their probes read from the multi-occurrence array */
 } mt_stats;
 int mt_last_stats(mt_stats *out);
 
@@ -318,7 +321,8 @@ int mt_select_genomes(const uint64_t *hits, uint64_t n_genomes, uint64_t cutoff_
 typedef struct mt_server mt_server;
 
 typedef struct mt_server_params {
-    uint64_t mem_budget_bytes;      /* device bytes admitted at once; 0 = 4 GiB */
+    uint64_t mem_budget_bytes;      /* device bytes admitted at once; 0 = a quarter of the device
+                                       memory free when the server is created (at least 256 MiB) */
     uint64_t max_batch_reads;       /* reads per device batch; 0 = 262,144 (smaller batches
                                        cut the latency tail, larger ones raise throughput) */
     uint32_t n_streams;             /* batches in flight (worker threads); 0 = 4 */
@@ -359,6 +363,23 @@ int mt_server_wait(mt_server *server, uint64_t request_id, int64_t timeout_us, m
  * Results not yet waited for are released; results already handed over stay
  * valid.  No other call on this server may be in progress or follow. */
 int mt_server_destroy(mt_server *server);
+
+/* Counters of a server since its creation (host struct): batches run and
+ * the reads in them; batches that the memory budget cut short (admission
+ * control held reads back until memory of running batches was released);
+ * the largest estimated device bytes and the most batches in flight at once;
+ * and the budget and batch cap in force (defaults resolved). */
+typedef struct mt_server_counters {
+    uint64_t batches;
+    uint64_t reads;
+    uint64_t budget_limited;
+    uint64_t peak_inflight_bytes;
+    uint64_t mem_budget_bytes;
+    uint64_t max_batch_reads;
+    uint32_t peak_batches;
+    uint32_t reserved;
+} mt_server_counters;
+int mt_server_stats(mt_server *server, mt_server_counters *out);
 
 /* 1 if the result's arrays live in host memory (served results), 0 if on
  * the device (mt_classify). */
@@ -411,6 +432,48 @@ int mt_autotune(const mt_index *index, const mt_query_params *params, const mt_s
  * architecture or naming unknown buckets or variants. */
 int mt_tune_save(const char *path);
 int mt_tune_load(const char *path);
+
+/*
+ * Device memory of the library.  Every device buffer the library holds -- an
+ * index, a result's arrays, per-call scratch, a server's batches and request
+ * counters -- comes from one allocator.  By default it is the library's own
+ * caching pool (hipMalloc'd blocks kept on free lists for reuse).
+ *
+ * mt_set_allocator installs the caller's allocator instead (the binding
+ * installs PyTorch's caching allocator, so that one allocator owns HBM and
+ * its statistics cover the library): from then on every device allocation is
+ * alloc(bytes, stream, ctx) and every release free_(ptr, ctx), and the library
+ * keeps no cache of its own (its idle pool blocks are released by the call).
+ *   alloc   returns device memory of at least `bytes` bytes (256-byte aligned
+ *           or better), or NULL when none is left (the library call then
+ *           fails with MT_ENOMEM).  `stream` is the hipStream_t (as void*,
+ *           NULL = the null stream) on which the library first uses the
+ *           memory; a stream-ordered allocator may hand out memory whose
+ *           earlier use on that stream is still queued.  Called from any
+ *           host thread, including the server's workers.
+ *   free_   takes back a pointer alloc returned.  The library calls it only
+ *           after its own work on the memory is complete.
+ *   ctx     passed through to both.
+ * alloc and free_ both NULL restore the built-in pool.  Blocks keep the
+ * allocator that made them: memory allocated before a switch is released
+ * to its own allocator.  The hook must stay valid while any block it made
+ * is alive.  Errors: MT_EINVAL (exactly one of alloc and free_ is NULL).
+ * (The paper leaves memory management open; this is the boundary's hook for
+ * a host framework that owns device memory.)
+ */
+int mt_set_allocator(void *(*alloc)(size_t bytes, void *stream, void *ctx), void (*free_)(void *ptr, void *ctx),
+                     void *ctx);
+
+/* Allocation counters since the library was loaded (host struct). */
+typedef struct mt_mem_stats {
+    uint64_t device_mallocs;  /* hipMalloc calls made by the built-in pool */
+    uint64_t hook_allocs;     /* allocations made through an mt_set_allocator hook */
+    uint64_t live_bytes;      /* device bytes held by live blocks (handles and calls in progress) */
+    uint64_t cached_bytes;    /* idle bytes on the built-in pool's free lists */
+    uint32_t hooked;          /* 1 while a hook is installed */
+    uint32_t reserved;
+} mt_mem_stats;
+int mt_memory_stats(mt_mem_stats *out);
 
 /* Releases device memory cached by the library's allocator (not held by any handle). */
 int mt_trim(void);

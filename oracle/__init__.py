@@ -24,7 +24,7 @@ _lib = None
 
 def build(out: str = _SO, extra_flags=()) -> str:
     """Compiles oracle.c with gcc into a shared library."""
-    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", *extra_flags, "-o", out, _SRC]
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", *extra_flags, "-o", out, _SRC, "-lm"]
     subprocess.check_call(cmd)
     return out
 

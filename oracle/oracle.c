@@ -98,6 +98,7 @@
  *       in double precision with K the sum over kept taxa; dropped taxa (and
  *       every taxon when C = 0) get 0.
  */
+#include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -944,6 +945,34 @@ int64_t or_select_genomes(const uint64_t *hits, uint64_t n, uint64_t num, uint64
 /* ------------------------------------------------ stage 3b abundance ---- */
 
 /*
+ * num / den as the nearest double, ties to even (0 <= num <= den, den > 0,
+ * den < 2^127): the quotient's binary expansion by schoolbook long division,
+ * its first 53 significant bits rounded with the next bit and whether any
+ * remainder is left.  Converting num and den to double first and dividing
+ * would round twice once den needs more than 53 bits.
+ */
+static double div_nearest(unsigned __int128 num, unsigned __int128 den)
+{
+    if (num == 0) return 0.0;
+    if (num >= den) return 1.0;
+    int e = 0;                        /* num / den lies in [2^-e, 2^(1-e)) */
+    unsigned __int128 r = num;
+    while (r < den) { r <<= 1; e++; }
+    r -= den;                         /* the leading quotient bit, weight 2^-e */
+    uint64_t q = 1;
+    for (int i = 1; i < 53; i++) {
+        r <<= 1;
+        q <<= 1;
+        if (r >= den) { r -= den; q |= 1; }
+    }
+    r <<= 1;                          /* the next bit, then the rest */
+    int half = r >= den;
+    if (half) r -= den;
+    if (half && (r != 0 || (q & 1))) q++;
+    return ldexp((double)q, -e - 52);  /* q <= 2^53: exact */
+}
+
+/*
  * Relative abundance from a classification's candidates (reading O16):
  * cand_offsets[n_reads + 1], genome / approx / accept per candidate,
  * taxon_of_genome.  counts (n_taxa, units of 2^-32 read) and abund (n_taxa)
@@ -995,7 +1024,7 @@ int64_t or_abundance(uint64_t n_reads, const uint64_t *cand_offsets, const uint3
     }
     for (uint32_t t = 0; t < n_taxa; t++) {
         int keep = C > 0 && (unsigned __int128)counts[t] * den >= C * num;
-        abund[t] = keep ? (double)counts[t] / (double)(uint64_t)K : 0.0;
+        abund[t] = keep ? div_nearest(counts[t], K) : 0.0;
     }
     free(unique);
     free(set);

@@ -18,6 +18,7 @@ from ._abi import (MT_E_CEIL_PERMILLE, MT_E_FIXED, MT_E_FLOOR_PERMILLE, MT_FILTE
                    MT_MODE_PER_STAGE, MT_OK)
 
 __all__ = ["MTError", "DeviceSeqs", "Index", "Result", "Server", "to_device", "mt_set_timing", "last_timings",
+           "memory_stats", "use_torch_allocator",
            "tune_info", "tune_set", "tune_reset", "tune_save", "tune_load", "select_genomes"]
 
 
@@ -113,6 +114,23 @@ def _check_hip(rc: int) -> None:
 def mt_set_timing(enabled: bool) -> None:
     lib = _abi.load()
     _check(lib.mt_set_timing(1 if enabled else 0), lib)
+
+
+def memory_stats() -> dict:
+    """The library's allocation counters (mt_memory_stats): hipMalloc calls of its
+    own pool, allocations through the installed hook (torch's allocator by
+    default), live and cached device bytes, and whether a hook is installed."""
+    lib = _abi.load()
+    st = _abi.mt_mem_stats()
+    _check(lib.mt_memory_stats(C.byref(st)), lib)
+    return {f: getattr(st, f) for f, _ in st._fields_ if f != "reserved"}
+
+
+def use_torch_allocator(on: bool = True) -> bool:
+    """Device memory of the library from torch's caching allocator (on, the
+    default) or from the library's own pool (off)."""
+    _abi.load()
+    return _abi.use_torch_allocator(on)
 
 
 def last_stats() -> dict:
@@ -392,6 +410,12 @@ class Server:
             return None
         _check(rc, self.lib)
         return Result(h.value, self.lib)
+
+    def stats(self) -> dict:
+        """mt_server_stats: batches, reads, budget-limited admissions, peaks."""
+        st = _abi.mt_server_counters()
+        _check(self.lib.mt_server_stats(self.h, C.byref(st)), self.lib)
+        return {f: getattr(st, f) for f, _ in st._fields_ if f != "reserved"}
 
     def close(self) -> None:
         if getattr(self, "h", None):

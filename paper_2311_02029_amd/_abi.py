@@ -9,6 +9,7 @@ import ctypes as C
 import os
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmetatrinity.so")
+TORCH_ALLOC_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libmt_torch_alloc.so")
 
 MT_OK, MT_EINVAL, MT_ENOMEM, MT_EDEVICE, MT_EAGAIN, MT_ETIMEDOUT, MT_ECANCELED, MT_EINTERNAL = 0, -1, -2, -3, -4, -5, -6, -7
 MT_E_FIXED, MT_E_CEIL_PERMILLE, MT_E_FLOOR_PERMILLE = 0, 1, 2
@@ -23,6 +24,7 @@ ABI_FUNCTIONS = (
     "mt_server_submit", "mt_server_wait", "mt_server_destroy", "mt_result_on_host", "mt_result_times",
     "mt_tune_buckets", "mt_tune_info", "mt_tune_set", "mt_tune_reset", "mt_autotune", "mt_tune_save",
     "mt_tune_load", "mt_containment", "mt_select_genomes", "mt_filter_pairs_kind", "mt_abundance",
+    "mt_set_allocator", "mt_memory_stats", "mt_server_stats",
 )
 
 
@@ -48,13 +50,29 @@ class mt_index_info(C.Structure):
 
 class mt_stats(C.Structure):
     _fields_ = [(f, C.c_uint64) for f in ("n_reads", "n_minimizers", "n_hits", "n_cands", "fused_reads",
-                                          "fused_bases", "fused_minimizers", "fused_window_blocks", "fused_cands")]
+                                          "fused_bases", "fused_minimizers", "fused_window_blocks", "fused_cands",
+                                          "fused_occ")]
+
+
+class mt_mem_stats(C.Structure):
+    _fields_ = [("device_mallocs", C.c_uint64), ("hook_allocs", C.c_uint64), ("live_bytes", C.c_uint64),
+                ("cached_bytes", C.c_uint64), ("hooked", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 
 class mt_server_params(C.Structure):
     _fields_ = [("mem_budget_bytes", C.c_uint64), ("max_batch_reads", C.c_uint64), ("n_streams", C.c_uint32),
                 ("max_queued_requests", C.c_uint32), ("pinned_arena_bytes", C.c_uint64),
                 ("reserved", C.c_uint32 * 4)]
+
+
+class mt_server_counters(C.Structure):
+    _fields_ = [("batches", C.c_uint64), ("reads", C.c_uint64), ("budget_limited", C.c_uint64),
+                ("peak_inflight_bytes", C.c_uint64), ("mem_budget_bytes", C.c_uint64),
+                ("max_batch_reads", C.c_uint64), ("peak_batches", C.c_uint32), ("reserved", C.c_uint32)]
 
 
 class mt_tune_bucket(C.Structure):
@@ -113,6 +131,9 @@ def load(path: str = LIB_PATH):
         "mt_containment": (i32, [vp, C.POINTER(mt_seqs), vp, vp]),
         "mt_filter_pairs_kind": (i32, [vp, C.POINTER(mt_seqs), vp, vp, vp, vp, u64, u32, vp, vp, vp]),
         "mt_select_genomes": (i32, [vp, u64, u64, u64, vp, C.POINTER(u64), C.POINTER(u64), vp]),
+        "mt_set_allocator": (i32, [vp, vp, vp]),
+        "mt_memory_stats": (i32, [C.POINTER(mt_mem_stats)]),
+        "mt_server_stats": (i32, [vp, C.POINTER(mt_server_counters)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -120,4 +141,41 @@ def load(path: str = LIB_PATH):
         f.argtypes = args
     if path == LIB_PATH:
         _lib = lib
+        if os.environ.get("MT_TORCH_ALLOCATOR", "1") != "0":
+            use_torch_allocator(True)
     return lib
+
+
+_shim = None
+
+
+def use_torch_allocator(on: bool = True) -> bool:
+    """Installs PyTorch's caching allocator as the library's device allocator
+    (mt_set_allocator with the shim's two functions), or with on=False goes
+    back to the library's own pool.  Needs a GPU (torch's allocator is set up
+    by its CUDA initialisation); without one nothing is installed.  Returns
+    whether torch's allocator is now in use.  Loading the library installs it
+    unless MT_TORCH_ALLOCATOR=0 is set."""
+    global _shim
+    import torch
+    lib = _lib
+    if lib is None:
+        raise RuntimeError("load() the library first")
+    if not on:
+        rc = lib.mt_set_allocator(None, None, None)
+        if rc != MT_OK:
+            raise RuntimeError(lib.mt_last_error().decode())
+        return False
+    if not torch.cuda.is_available():
+        return False
+    if not os.path.exists(TORCH_ALLOC_PATH):
+        raise RuntimeError(f"{TORCH_ALLOC_PATH} is missing: build it with __graft_entry__.build()")
+    torch.cuda.init()
+    if _shim is None:
+        _shim = C.CDLL(TORCH_ALLOC_PATH)
+    alloc = C.cast(_shim.mt_torch_alloc, C.c_void_p)
+    free = C.cast(_shim.mt_torch_free, C.c_void_p)
+    rc = lib.mt_set_allocator(alloc, free, None)
+    if rc != MT_OK:
+        raise RuntimeError(lib.mt_last_error().decode())
+    return True

@@ -102,6 +102,41 @@ __device__ inline bool ge128(u64 a, u64 b, u64 c, u64 d) {
     return lh > rh || (lh == rh && ll >= rl);
 }
 
+// num / den as the nearest double, ties to even (0 <= num <= den, den > 0):
+// the quotient's bits by long division (the remainder doubled with its carry
+// out of 64 bits kept), 53 significant bits rounded with the next bit and
+// whether a remainder is left.  Dividing the two converted doubles would
+// round twice once den needs more than 53 bits.
+__device__ inline double div_nearest(u64 num, u64 den) {
+    if (num == 0) return 0.0;
+    if (num >= den) return 1.0;
+    int e = 0;  // num / den lies in [2^-e, 2^(1-e))
+    u64 r = num;
+    for (;;) {  // double r until it reaches den (a carry out of 64 bits means it has)
+        const bool carry = (r >> 63) != 0;
+        r <<= 1;
+        e++;
+        if (carry || r >= den) break;
+    }
+    r -= den;  // the true 2r - den is below den: the wrapped difference is exact
+    u64 q = 1;
+    for (int i = 1; i < 53; i++) {
+        const bool carry = (r >> 63) != 0;
+        r <<= 1;
+        q <<= 1;
+        if (carry || r >= den) {
+            r -= den;  // the true 2r - den is below den: the wrapped difference is exact
+            q |= 1;
+        }
+    }
+    const bool carry = (r >> 63) != 0;
+    r <<= 1;
+    const bool half = carry || r >= den;
+    if (half) r -= den;
+    if (half && (r != 0 || (q & 1))) q++;
+    return ldexp((double)q, -e - 52);
+}
+
 // One block: the total, the cutoff, the kept total, the abundances.
 // out[0] = kept taxa.
 __global__ __launch_bounds__(AF_TPB) void k_abundance_final(const u64 *__restrict__ counts, u32 n_taxa, u64 num,
@@ -121,7 +156,7 @@ __global__ __launch_bounds__(AF_TPB) void k_abundance_final(const u64 *__restric
     K = block_sum(K, sh);
     for (u32 t = threadIdx.x; t < n_taxa; t += AF_TPB) {
         const bool keep = C && ge128(counts[t], den, C, num);
-        abund[t] = keep ? (double)counts[t] / (double)K : 0.0;
+        abund[t] = keep ? div_nearest(counts[t], K) : 0.0;
     }
     if (threadIdx.x == 0) out[0] = kept;
 }

@@ -17,6 +17,27 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-I", os.path.join(ROOT, "include")]
 
 
+TORCH_ALLOC_OUT = os.path.join(PKG, "libmt_torch_alloc.so")
+
+
+def build_torch_alloc(out: str = TORCH_ALLOC_OUT, verbose: bool = False) -> str:
+    """The binding's shim that hands PyTorch's caching allocator to
+    mt_set_allocator (host C++ against the installed torch)."""
+    import torch
+    tdir = os.path.dirname(torch.__file__)
+    cmd = ["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-D__HIP_PLATFORM_AMD__", "-DUSE_ROCM",
+           "-I", os.path.join(tdir, "include"), "-I", "/opt/rocm/include", os.path.join(HERE, "torch_alloc.cpp"),
+           "-L", os.path.join(tdir, "lib"), "-lc10_hip", "-lc10", "-Wl,-rpath," + os.path.join(tdir, "lib"),
+           "-o", out + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"torch allocator shim failed:\n{r.stdout}\n{r.stderr}")
+    os.replace(out + ".tmp", out)
+    return out
+
+
 def build(out: str = OUT, verbose: bool = False) -> str:
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
@@ -39,6 +60,7 @@ def build(out: str = OUT, verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, out)
+    build_torch_alloc(verbose=verbose)
     return out
 
 

@@ -630,11 +630,12 @@ static void stage_filter_reduce(const mt_index &ix, const mt_query_params &q, co
     fa.approx = res.approx.p;
     fa.accept = res.accept.p;
     fa.flags = rb.flags.p;
-    if (q.filter == MT_FILTER_OBSTACLE)
-        launch_filter(fa, cap, max_E, s);
-    else
+    if (q.filter == MT_FILTER_OBSTACLE) {
+        launch_filter(fa, cap, max_E, s, &tm);
+    } else {
         launch_filter_simple(fa, cap, q.filter, s);
-    tm.mark("filter");
+        tm.mark("filter");
+    }
     // reduce
     if (n) {
         const unsigned blocks = std::min<u64>(grid_for(n, RED_TPB), (u64)count_blocks() / 2);

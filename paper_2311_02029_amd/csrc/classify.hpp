@@ -73,7 +73,7 @@ struct FilterArgs {
 // Filters pairs [0, n) (n = *n_dev if set, else n_host; n_cap bounds it):
 // pairs are bucketed by their E (one synchronization to size the buckets),
 // then each bucket runs the kernel shaped for it.
-void launch_filter(const FilterArgs &a, u64 n_cap, u32 max_E, hipStream_t s);
+void launch_filter(const FilterArgs &a, u64 n_cap, u32 max_E, hipStream_t s, Timer *tm = nullptr);
 // Pairs [0, count) through the Hamming (MT_FILTER_HAMMING), base-counting
 // (MT_FILTER_BASE_COUNT), q-gram (MT_FILTER_QGRAM) or shifted Hamming (MT_FILTER_SHD)
 // filter; count = *n_dev if set, else n_host, at most n.

@@ -658,12 +658,22 @@ void launch_filter_simple(const FilterArgs &a, u64 n, u32 kind, hipStream_t s) {
     MT_HIP(hipGetLastError());
 }
 
-void launch_filter(const FilterArgs &a, u64 n_cap, u32 /*max_E*/, hipStream_t s) {
+// Stage names of the per-bucket timing marks.
+static const char *const BUCKET_MARKS[N_CLASSES] = {"filter E<=7",     "filter E<=15",    "filter E<=31",
+                                                    "filter long<=96", "filter long<=192", "filter long<=384",
+                                                    "filter long<=768", "filter general"};
+
+void launch_filter(const FilterArgs &a, u64 n_cap, u32 /*max_E*/, hipStream_t s, Timer *tm) {
     if (n_cap == 0) return;
     DBuf<u32> idx;
     u32 hc[N_CLASSES], hb[N_CLASSES];
     bucket_pairs(a, n_cap, idx, hc, hb, s);
-    for (int c = 0; c < N_CLASSES; c++) launch_bucket(a, idx.p + hb[c], hc[c], c, current_variant(c), s);
+    if (tm) tm->mark("filter buckets");
+    for (int c = 0; c < N_CLASSES; c++) {
+        if (hc[c] == 0) continue;
+        launch_bucket(a, idx.p + hb[c], hc[c], c, current_variant(c), s);
+        if (tm) tm->mark(BUCKET_MARKS[c]);
+    }
 }
 
 // Times every variant of every bucket that holds pairs (best of `reps`

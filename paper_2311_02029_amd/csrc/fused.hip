@@ -48,7 +48,7 @@ constexpr int F_QCAP = 4;        // queued (read, candidate) pairs per wave: one
 constexpr int F_PCAP = 8;        // reads per wave waiting for their filter results
 constexpr int F_WORDS = F_MAX_M / 16 + 2;  // 2-bit stream words (16 bases per word) + padding
 
-enum : u32 { ST_READS, ST_BASES, ST_MINS, ST_WBLOCKS, ST_CANDS, ST_UNMAPPED, ST_COUNT };
+enum : u32 { ST_READS, ST_BASES, ST_MINS, ST_WBLOCKS, ST_CANDS, ST_UNMAPPED, ST_OCC, ST_COUNT };
 
 struct FusedArgs {
     const u8 *seq;
@@ -513,7 +513,7 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
         // and each probe found at most one occurrence (the common case), the
         // hits are counted in registers: one ballot per distinct location;
         // otherwise they go through the per-read LDS table.
-        int H = 0, C = 0;
+        int H = 0, C = 0, nocc = 0;  // nocc: entries read from the multi-occurrence array
         bool overflow = false, counted = false;
         for (int t0 = 0; t0 < nmin; t0 += 64) {
             int j = t0 + lane;
@@ -551,6 +551,7 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
             u32 tot = (u32)__popcll(sm);
             for (u64 rem = mm; rem; rem &= rem - 1)
                 tot += __builtin_amdgcn_readlane(cnt, __builtin_amdgcn_readfirstlane(__builtin_ctzll(rem)));
+            nocc += (int)(tot - (u32)__popcll(sm));
             if (H + (int)tot > F_HIT_CAP) {
                 overflow = true;
                 break;
@@ -685,6 +686,7 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
             wst[ST_MINS] += (u64)nmin;
             wst[ST_CANDS] += (u64)nc;
             wst[ST_WBLOCKS] += (u64)nc * (u64)((m + 2 * E + 63) / 64);
+            wst[ST_OCC] += (u64)nocc;
         }
         cur = nxt;
         wave_sync();
@@ -1018,7 +1020,12 @@ void classify_fused(const mt_index &ix, const mt_query_params &q, const mt_seqs 
     ls.fused_minimizers += h.stats[ST_MINS];
     ls.fused_window_blocks += h.stats[ST_WBLOCKS];
     ls.fused_cands += h.stats[ST_CANDS];
+    ls.fused_occ += h.stats[ST_OCC];
     ls.n_minimizers += h.stats[ST_MINS];
+    // Every read's count is at most N (k_fused writes one count per read), so
+    // the total fits the staged capacity; a result never claims more
+    // candidates than its arrays hold.
+    if (h.n_cands > res.cap) throw Error(MT_EINTERNAL, "fused candidate count exceeds the staged capacity");
     res.n_cands = h.n_cands;
     const u32 nfb = h.nfb;
     if (nfb == 0) return;

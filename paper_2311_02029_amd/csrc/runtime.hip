@@ -32,10 +32,24 @@ void check_flags(u32 f) {
 // --------------------------------------------------------------- allocator --
 
 namespace {
+// A device allocation hook (mt_set_allocator); alloc == nullptr means the
+// built-in caching pool.
+struct Hook {
+    void *(*alloc)(size_t, void *, void *) = nullptr;
+    void (*free_)(void *, void *) = nullptr;
+    void *ctx = nullptr;
+};
+struct Block {
+    size_t size;
+    Hook hook;  // the allocator that made the block (hook.alloc null: the pool)
+};
 struct Pool {
     std::mutex mu;
     std::multimap<size_t, void *> free_blocks;
-    std::unordered_map<void *, size_t> live;
+    std::unordered_map<void *, Block> live;
+    Hook hook;
+    size_t cached_bytes = 0;
+    mt_mem_stats stats{};
 };
 Pool &pool() {
     static Pool *p = new Pool();  // never destroyed: outlives static handles at exit
@@ -52,8 +66,28 @@ size_t round_size(size_t b) {
 }
 }  // namespace
 
-void *pool_alloc(size_t bytes) {
+static thread_local CallScope *g_scope = nullptr;
+
+void *pool_alloc(size_t bytes) { return pool_alloc_on(bytes, g_scope ? g_scope->stream : nullptr); }
+
+void *pool_alloc_on(size_t bytes, hipStream_t stream) {
     Pool &P = pool();
+    Hook h;
+    {
+        std::lock_guard<std::mutex> g(P.mu);
+        h = P.hook;
+    }
+    if (h.alloc) {
+        // the caller's allocator: no cache here (it keeps its own)
+        const size_t sz = bytes ? bytes : 1;
+        void *p = h.alloc(sz, (void *)stream, h.ctx);
+        if (!p) throw Error(MT_ENOMEM, "device allocation of " + std::to_string(sz) + " bytes failed (allocator hook)");
+        std::lock_guard<std::mutex> g(P.mu);
+        P.live[p] = Block{sz, h};
+        P.stats.hook_allocs++;
+        P.stats.live_bytes += sz;
+        return p;
+    }
     size_t sz = round_size(bytes);
     {
         std::lock_guard<std::mutex> g(P.mu);
@@ -61,7 +95,9 @@ void *pool_alloc(size_t bytes) {
         if (it != P.free_blocks.end()) {
             void *p = it->second;
             P.free_blocks.erase(it);
-            P.live[p] = sz;
+            P.cached_bytes -= sz;
+            P.live[p] = Block{sz, Hook{}};
+            P.stats.live_bytes += sz;
             return p;
         }
     }
@@ -78,11 +114,11 @@ void *pool_alloc(size_t bytes) {
                     "device allocation of " + std::to_string(sz) + " bytes failed: " + hipGetErrorString(e));
     }
     std::lock_guard<std::mutex> g(P.mu);
-    P.live[p] = sz;
+    P.live[p] = Block{sz, Hook{}};
+    P.stats.device_mallocs++;
+    P.stats.live_bytes += sz;
     return p;
 }
-
-static thread_local CallScope *g_scope = nullptr;
 
 CallScope::CallScope(hipStream_t s) : stream(s), prev(g_scope) { g_scope = this; }
 
@@ -99,11 +135,21 @@ void pool_free(void *p) {
         return;
     }
     Pool &P = pool();
-    std::lock_guard<std::mutex> g(P.mu);
-    auto it = P.live.find(p);
-    if (it == P.live.end()) return;
-    P.free_blocks.emplace(it->second, p);
-    P.live.erase(it);
+    Block b;
+    {
+        std::lock_guard<std::mutex> g(P.mu);
+        auto it = P.live.find(p);
+        if (it == P.live.end()) return;
+        b = it->second;
+        P.live.erase(it);
+        P.stats.live_bytes -= b.size;
+        if (!b.hook.alloc) {
+            P.free_blocks.emplace(b.size, p);
+            P.cached_bytes += b.size;
+            return;
+        }
+    }
+    b.hook.free_(p, b.hook.ctx);  // outside the lock: the hook may allocate or free itself
 }
 
 void pool_trim() {
@@ -111,6 +157,26 @@ void pool_trim() {
     std::lock_guard<std::mutex> g(P.mu);
     for (auto &kv : P.free_blocks) (void)hipFree(kv.second);
     P.free_blocks.clear();
+    P.cached_bytes = 0;
+}
+
+void set_allocator(void *(*alloc)(size_t, void *, void *), void (*free_)(void *, void *), void *ctx) {
+    MT_REQUIRE((alloc == nullptr) == (free_ == nullptr), "alloc and free must both be set or both be NULL");
+    pool_trim();  // the library keeps no idle device memory of its own behind a hook
+    Pool &P = pool();
+    std::lock_guard<std::mutex> g(P.mu);
+    P.hook.alloc = alloc;
+    P.hook.free_ = free_;
+    P.hook.ctx = ctx;
+}
+
+mt_mem_stats memory_stats() {
+    Pool &P = pool();
+    std::lock_guard<std::mutex> g(P.mu);
+    mt_mem_stats s = P.stats;
+    s.cached_bytes = P.cached_bytes;
+    s.hooked = P.hook.alloc != nullptr;
+    return s;
 }
 
 // ------------------------------------------------------------------- scans --
@@ -277,6 +343,19 @@ extern "C" int mt_abi_version(void) { return MT_ABI_VERSION; }
 
 extern "C" int mt_trim(void) {
     mt::pool_trim();
+    return MT_OK;
+}
+
+extern "C" int mt_set_allocator(void *(*alloc)(size_t, void *, void *), void (*free_)(void *, void *), void *ctx) {
+    return mt::guarded("mt_set_allocator", [&] { mt::set_allocator(alloc, free_, ctx); });
+}
+
+extern "C" int mt_memory_stats(mt_mem_stats *out) {
+    if (!out) {
+        mt::set_last_error("mt_memory_stats: null argument");
+        return MT_EINVAL;
+    }
+    *out = mt::memory_stats();
     return MT_OK;
 }
 

@@ -35,14 +35,20 @@ void set_last_error(const std::string &msg);
         if (!(cond)) throw ::mt::Error(MT_EINVAL, (msg));                                                \
     } while (0)
 
-// Caching device allocator.  Blocks are rounded up (power of two below 1 MiB,
-// 2 MiB multiples above) and kept on free lists after release, so the
-// per-call scratch of a classification costs no hipMalloc after warm-up.
-// Every library call synchronizes its stream before releasing scratch, so a
-// released block is idle when it is handed out again.
-void *pool_alloc(size_t bytes);
+// Device allocator.  By default a caching pool: blocks are rounded up (power
+// of two below 1 MiB, 2 MiB multiples above) and kept on free lists after
+// release, so the per-call scratch of a classification costs no hipMalloc
+// after warm-up.  With an allocator hook installed (mt_set_allocator) every
+// allocation goes to the hook, with the stream its memory is first used on,
+// and every release back to it; the pool then holds nothing.  Every library
+// call synchronizes its stream before releasing scratch, so a released block
+// is idle when it is handed out again.
+void *pool_alloc(size_t bytes);                      // stream: the open CallScope's, else the null stream
+void *pool_alloc_on(size_t bytes, hipStream_t stream);
 void pool_free(void *p);
 void pool_trim();
+void set_allocator(void *(*alloc)(size_t, void *, void *), void (*free_)(void *, void *), void *ctx);
+mt_mem_stats memory_stats();
 
 // Scope of one ABI call on one stream.  Blocks released while a scope is open
 // on the calling thread are parked until the scope ends; the scope then

@@ -215,6 +215,8 @@ struct mt_server {
     std::deque<Request *> queue;  // requests with reads not yet in a batch
     u64 next_id = 1;
     u64 inflight = 0;             // estimated device bytes of the batches in flight
+    u32 running = 0;              // batches in flight
+    mt_server_counters stats{};   // guarded by mu
     bool stopping = false;
     std::vector<std::thread> workers;
 
@@ -222,6 +224,7 @@ struct mt_server {
     // admitted now.
     bool form_batch(Batch &b) {
         if (queue.empty()) return false;
+        bool limited = false;
         const u64 budget = p.mem_budget_bytes;
         const u64 avail = budget > inflight ? budget - inflight : 0;
         b.q = queue.front()->q;
@@ -238,6 +241,7 @@ struct mt_server {
                 return batch_bytes(b.reads + take, b.bases + (r->off[r0 + take] - r->off[r0]), b.q) <= avail;
             };
             if (!fits(hi)) {  // largest number of reads that fits the budget
+                limited = true;
                 while (hi - lo > 1) {
                     const u64 mid = lo + (hi - lo) / 2;
                     if (fits(mid)) lo = mid; else hi = mid;
@@ -258,9 +262,15 @@ struct mt_server {
             if (r->next < r->n) break;  // the batch is full
             it = queue.erase(it);
         }
+        if (limited) stats.budget_limited++;
         if (b.slices.empty()) return false;
         b.est = batch_bytes(b.reads, b.bases, b.q);
         inflight += b.est;
+        running++;
+        stats.batches++;
+        stats.reads += b.reads;
+        stats.peak_inflight_bytes = std::max<u64>(stats.peak_inflight_bytes, inflight);
+        stats.peak_batches = std::max<u32>(stats.peak_batches, running);
         return true;
     }
 
@@ -475,6 +485,7 @@ void mt_server::worker() {
         {
             std::lock_guard<std::mutex> lk(mu);
             inflight -= b.est;
+            running--;
             for (size_t i = 0; i < b.slices.size(); i++) {
                 Request *r = b.slices[i].req;
                 if (status != MT_OK && r->status == MT_OK) {
@@ -519,6 +530,18 @@ out:
 
 // ---------------------------------------------------------------------- ABI --
 
+extern "C" int mt_server_stats(mt_server *server, mt_server_counters *out) {
+    if (!server || !out) {
+        mt::set_last_error("mt_server_stats: null argument");
+        return MT_EINVAL;
+    }
+    std::lock_guard<std::mutex> lk(server->mu);
+    *out = server->stats;
+    out->mem_budget_bytes = server->p.mem_budget_bytes;
+    out->max_batch_reads = server->p.max_batch_reads;
+    return MT_OK;
+}
+
 extern "C" int mt_server_create(const mt_index *index, const mt_server_params *params, mt_server **out) {
     if (!index || !out) {
         mt::set_last_error("mt_server_create: null argument");
@@ -531,7 +554,11 @@ extern "C" int mt_server_create(const mt_index *index, const mt_server_params *p
         if (params) p = *params;
         MT_REQUIRE(p.reserved[0] == 0 && p.reserved[1] == 0 && p.reserved[2] == 0 && p.reserved[3] == 0,
                    "reserved fields must be 0");
-        if (!p.mem_budget_bytes) p.mem_budget_bytes = 4ull << 30;
+        if (!p.mem_budget_bytes) {
+            size_t free_b = 0, total_b = 0;
+            MT_HIP(hipMemGetInfo(&free_b, &total_b));
+            p.mem_budget_bytes = std::max<u64>(free_b / 4, 256ull << 20);
+        }
         if (!p.max_batch_reads) p.max_batch_reads = 1ull << 18;
         if (!p.n_streams) p.n_streams = 4;
         if (!p.max_queued_requests) p.max_queued_requests = 4096;
@@ -621,7 +648,7 @@ extern "C" int mt_server_submit(mt_server *sv, const mt_query_params *params, co
                     }
                 }
                 if (!r->zeroed) MT_HIP(hipEventCreateWithFlags(&r->zeroed, hipEventDisableTiming));
-                r->counts = (unsigned long long *)pool_alloc((2 * nt + 1) * 8);
+                r->counts = (unsigned long long *)pool_alloc_on((2 * nt + 1) * 8, sv->ctl);
                 MT_HIP(hipMemsetAsync(r->counts, 0, (2 * nt + 1) * 8, sv->ctl));
                 MT_HIP(hipEventRecord(r->zeroed, sv->ctl));
             } catch (...) {

@@ -132,9 +132,8 @@ def test_served_query_mix_and_oracle(env):
     oix = oracle.Index(env["ga"], env["k"], env["w"], taxon=env["taxon"], n_taxa=5)
     for i, (r, q) in enumerate(zip(reqs, queries)):
         _same(got[i], _alone(env, r, q), f"request {i}")
-        if r.n <= 600:
-            ref = oix.classify(r, q["min_hits"], q["top_n"], q["e_mode"], q["e_value"])
-            _same(got[i], ref, f"request {i} vs oracle")
+        ref = oix.classify(r, q["min_hits"], q["top_n"], q["e_mode"], q["e_value"])
+        _same(got[i], ref, f"request {i} vs oracle")
 
 
 def test_tight_memory_budget_still_exact(env):
@@ -198,3 +197,57 @@ def test_destroy_with_pending_requests(env):
     with mt.Server(env["ix"]) as sv2:  # the index still serves afterwards
         r = sv2.wait(sv2.submit(reqs[3]))
         _same(r.to_host(), _alone(env, reqs[3], {}), "after destroy")
+
+
+def test_served_trace_on_500mbp_index_matches_oracle(env, batched_db, batched_oracle):
+    """The served workload on its own database: 160 requests of a Poisson trace
+    (U{1..50,000} reads of one length in 100-250 bp at 0.5% error, E = ceil(5%
+    of m)) submitted at their arrival times by 8 client threads to a server
+    holding the 500 Mbp index, several requests in flight at once; every
+    request's result, taken from the mix, equals the oracle's classification of
+    that request's reads alone, per-request taxon counts included."""
+    import time
+    mt = env["mt"]
+    ix = mt.Index(mt.to_device(batched_db["ga"]), 21, 11)
+    pool = synth.served_read_pool(batched_db["db"])
+    trace = synth.request_trace(3, 160, 3000.0, lengths=synth.SERVED_LENGTHS)
+    reqs = [synth.request_reads(pool, n, m) for _, n, m in trace]
+    q = dict(min_hits=3, top_n=3, e_mode=1, e_value=50)
+    results = [None] * len(reqs)
+    spans = [None] * len(reqs)
+    errors = []
+    threads = 8
+    with mt.Server(ix, n_streams=4, max_batch_reads=1 << 18) as sv:
+        t0 = time.monotonic()
+
+        def client(tid):
+            try:
+                mine = list(range(tid, len(reqs), threads))
+                ids = []
+                for i in mine:
+                    delay = t0 + trace[i][0] - time.monotonic()
+                    if delay > 0:
+                        time.sleep(delay)
+                    ids.append(sv.submit(reqs[i], **q))
+                for i, rid in zip(mine, ids):
+                    res = sv.wait(rid)
+                    spans[i] = res.times_ns()
+                    results[i] = res.to_host()
+                    res.free()
+            except Exception as e:  # noqa: BLE001
+                errors.append(e)
+        ts = [threading.Thread(target=client, args=(t,)) for t in range(threads)]
+        for t in ts:
+            t.start()
+        for t in ts:
+            t.join()
+    assert not errors, errors
+    for i, r in enumerate(reqs):
+        ref = batched_oracle.classify(r, q["min_hits"], q["top_n"], q["e_mode"], q["e_value"])
+        _same(results[i], ref, f"served request {i} ({r.n} reads of {trace[i][2]} bp) vs oracle")
+    # requests overlapped: some request was submitted before an earlier one completed
+    order = np.argsort([s for s, _ in spans])
+    sub = np.array([spans[i][0] for i in order])
+    done = np.array([spans[i][1] for i in order])
+    assert (sub[1:] < np.maximum.accumulate(done)[:-1]).any()
+    assert sum(r.n for r in reqs) > 1_000_000

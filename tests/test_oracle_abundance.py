@@ -113,3 +113,34 @@ def test_invariants_on_classifications_with_multi_mapped_reads(seed):
     perm = rng.permutation(n_taxa).astype(np.uint32)
     c2, a2, _ = oracle.abundance(res, perm[taxon], n_taxa)
     assert np.array_equal(c2[perm], c) and np.array_equal(a2[perm], a)
+
+
+def _big_mixture(seed, n_reads=3_000_000, n_taxa=40):
+    """A result of n_reads mapped reads in arrays: a third unique to one taxon,
+    the rest on two or three taxa at the best value (so the counts carry
+    fractional shares), which puts the kept total above 2^53 units."""
+    rng = np.random.default_rng(seed)
+    k = rng.choice([1, 1, 2, 3], n_reads)
+    co = np.zeros(n_reads + 1, np.uint64)
+    np.cumsum(k, out=co[1:])
+    weights = rng.random(n_taxa) ** 3 + 0.01
+    g = rng.choice(n_taxa, int(co[-1]), p=weights / weights.sum()).astype(np.uint32)
+    return dict(cand_offsets=co, genome=g, approx=np.zeros(len(g), np.uint16), accept=np.ones(len(g), np.uint8))
+
+
+def test_abundance_is_the_nearest_double_of_the_exact_ratio():
+    """count_t / K is rounded once, to the nearest double, even when K needs
+    more than 53 bits: against Python's exact rationals (Fraction to float
+    rounds correctly), on a mixture whose kept total is above 2^53 and where
+    converting count and K to double before dividing would differ."""
+    from fractions import Fraction
+    n_taxa = 40
+    res = _big_mixture(5, n_taxa=n_taxa)
+    c, a, kept = oracle.abundance(res, np.arange(n_taxa), n_taxa)
+    total = sum(int(x) for x in c)
+    K = sum(int(x) for x in c if int(x) * 10_000 >= total)
+    assert K > 2 ** 53 and kept > 0
+    want = [float(Fraction(int(x), K)) if int(x) * 10_000 >= total else 0.0 for x in c]
+    assert a.tolist() == want
+    naive = [float(int(x)) / float(K) if int(x) * 10_000 >= total else 0.0 for x in c]
+    assert naive != want  # the double rounding the nearest-double rule avoids happens here

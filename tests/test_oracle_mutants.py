@@ -49,6 +49,8 @@ MUTANTS = [
      "int keep = C > 0 && (unsigned __int128)counts[t] * den > C * num;\n        if (keep)"),
     ("multi reads counted as unique", "if (nt == 1) unique[set[0]]++;", "unique[set[0]]++;"),
     ("abundance over all taxa", "if (keep) { K += counts[t]; kept++; }", "K += counts[t]; if (keep) kept++;"),
+    ("abundance rounded twice", "abund[t] = keep ? div_nearest(counts[t], K) : 0.0;",
+     "abund[t] = keep ? (double)counts[t] / (double)(uint64_t)K : 0.0;"),
     ("top_n off by one", "if (top_n > 0 && nc > (int64_t)top_n) nc = top_n;",
      "if (top_n > 0 && nc > (int64_t)top_n + 1) nc = top_n + 1;"),
     ("N is a fifth letter", "    if (qc == 4) return 1;\n    if (p < 0 || p >= glen) return 1;\n    uint8_t rc = gcode[p];\n    if (rc == 4) return 1;",
@@ -95,7 +97,7 @@ def test_pins_catch_planted_mistake(name, orig, mut, tmp_path):
     mutant_c = tmp_path / "oracle_mutant.c"
     mutant_c.write_text(src.replace(orig, mut))
     lib = str(tmp_path / "liboracle_mutant.so")
-    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-o", lib, str(mutant_c)])
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-o", lib, str(mutant_c), "-lm"])
     env = dict(os.environ, ORACLE_LIB=lib)
     r = subprocess.run([sys.executable, "-m", "pytest", *PIN_FILES, "-x", "-q", "-p", "no:cacheprovider"], cwd=ROOT,
                        env=env, capture_output=True, text=True, timeout=600)
