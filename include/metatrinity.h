@@ -309,6 +309,21 @@ int mt_select_genomes(const uint64_t *hits, uint64_t n_genomes, uint64_t cutoff_
                       uint32_t *selected, uint64_t *n_selected, uint64_t *max_hits, void *stream);
 
 /*
+ * mt_select_genomes for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  Same arguments, results and errors as mt_select_genomes, plus
+ * MT_EINVAL for n_genomes above 1,048,576.  It allocates nothing: its scratch
+ * (the maximum, per-genome keep flags and offsets, the scan's block sums) is
+ * a static device array of the library, about 12.6 MB, which every GPU the
+ * library runs on holds until the process ends.  All calls on one GPU share
+ * that array, so calls that overlap on one GPU race: issue them one at a
+ * time (one stream, or wait for the previous call).  The call waits for its
+ * stream (it returns n_selected and max_hits on the host).
+ */
+int mt_select_genomes_noalloc(const uint64_t *hits, uint64_t n_genomes, uint64_t cutoff_num, uint64_t cutoff_den,
+                              uint32_t *selected, uint64_t *n_selected, uint64_t *max_hits, void *stream);
+
+/*
  * Serving loop: continuous batching of classification requests on one GPU
  * with the index resident in HBM.  Requests that arrive while others run are
  * admitted as batch slots and device memory free up; reads of several

@@ -24,7 +24,7 @@ ABI_FUNCTIONS = (
     "mt_server_submit", "mt_server_wait", "mt_server_destroy", "mt_result_on_host", "mt_result_times",
     "mt_tune_buckets", "mt_tune_info", "mt_tune_set", "mt_tune_reset", "mt_autotune", "mt_tune_save",
     "mt_tune_load", "mt_containment", "mt_select_genomes", "mt_filter_pairs_kind", "mt_abundance",
-    "mt_set_allocator", "mt_memory_stats", "mt_server_stats",
+    "mt_set_allocator", "mt_memory_stats", "mt_server_stats", "mt_select_genomes_noalloc",
 )
 
 
@@ -131,6 +131,7 @@ def load(path: str = LIB_PATH):
         "mt_containment": (i32, [vp, C.POINTER(mt_seqs), vp, vp]),
         "mt_filter_pairs_kind": (i32, [vp, C.POINTER(mt_seqs), vp, vp, vp, vp, u64, u32, vp, vp, vp]),
         "mt_select_genomes": (i32, [vp, u64, u64, u64, vp, C.POINTER(u64), C.POINTER(u64), vp]),
+        "mt_select_genomes_noalloc": (i32, [vp, u64, u64, u64, vp, C.POINTER(u64), C.POINTER(u64), vp]),
         "mt_set_allocator": (i32, [vp, vp, vp]),
         "mt_memory_stats": (i32, [C.POINTER(mt_mem_stats)]),
         "mt_server_stats": (i32, [vp, C.POINTER(mt_server_counters)]),

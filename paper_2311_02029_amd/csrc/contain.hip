@@ -7,6 +7,8 @@
 // then one kernel that probes the table for every read minimizer and adds one
 // hit to the genome of each occurrence.  Integer atomics on per-block LDS
 // counters take the place of the paper's mutex-guarded per-thread seed maps.
+#include <mutex>
+
 #include "classify.hpp"
 #include "seq.hpp"
 
@@ -72,6 +74,65 @@ __global__ void k_keep(const u64 *__restrict__ hits, u64 n, const unsigned long 
 __global__ void k_place(const u32 *__restrict__ keep, const u64 *__restrict__ at, u64 n, u32 *__restrict__ out) {
     const u64 g = (u64)blockIdx.x * blockDim.x + threadIdx.x;
     if (g < n && keep[g]) out[at[g]] = (u32)g;
+}
+
+__global__ void k_zero_u64(unsigned long long *__restrict__ p) {
+    if (threadIdx.x == 0) *p = 0;
+}
+
+// The selection's launches on caller-provided buffers: mx (one word), keep (n),
+// at (n + 1) and the scan workspace; `ws == nullptr` lets the scan allocate.
+static void select_into(const u64 *hits, u64 n, u64 num, u64 den, u32 *selected, unsigned long long *mx, u32 *keep,
+                        u64 *at, u64 *ws, u64 ws_words, hipStream_t s) {
+    k_zero_u64<<<1, 64, 0, s>>>(mx);  // a kernel rather than a memset node: callers may capture this
+    MT_HIP(hipGetLastError());
+    k_max_hits<<<(unsigned)std::min<u64>(grid_for(n, 256), 1024), 256, 0, s>>>(hits, n, mx);
+    MT_HIP(hipGetLastError());
+    k_keep<<<grid_for(n, 256), 256, 0, s>>>(hits, n, mx, num, den, keep);
+    MT_HIP(hipGetLastError());
+    if (ws)
+        scan_u32_ws(keep, at, n, ws, ws_words, s);
+    else
+        scan_u32(keep, at, n, s);
+    k_place<<<grid_for(n, 256), 256, 0, s>>>(keep, at, n, selected);
+    MT_HIP(hipGetLastError());
+}
+
+// ---------------------------------------------- the allocation-free variant --
+//
+// mt_select_genomes_noalloc keeps its scratch in one static device array of
+// fixed size (each GPU holds its own copy until the process ends).  Host code
+// reaches it only through the address hipGetSymbolAddress returns for the
+// current device, taken once per device.  Layout: the maximum (one word, its
+// own 256-byte line), keep flags (u32 per genome), offsets (u64 per genome +
+// 1), the scan workspace.
+constexpr u64 SEL_NOALLOC_MAX = 1ull << 20;  // genomes
+constexpr u64 SEL_KEEP_OFF = 256;
+constexpr u64 SEL_AT_OFF = SEL_KEEP_OFF + ((SEL_NOALLOC_MAX * 4 + 255) / 256) * 256;
+constexpr u64 SEL_WS_OFF = SEL_AT_OFF + (((SEL_NOALLOC_MAX + 1) * 8 + 255) / 256) * 256;
+constexpr u64 SEL_WS_WORDS = 2 * ((SEL_NOALLOC_MAX + 2047) / 2048) + 1;
+constexpr u64 SEL_SCRATCH_BYTES = SEL_WS_OFF + SEL_WS_WORDS * 8;
+
+static __device__ __align__(256) unsigned char scratch[SEL_SCRATCH_BYTES];
+
+constexpr int SEL_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static unsigned char *g_scratch_ptr[SEL_MAX_DEVICES];
+
+// The current device's copy of `scratch` (its address looked up on the first
+// call on that device).
+static unsigned char *scratch_on_device() {
+    int dev = 0;
+    MT_HIP(hipGetDevice(&dev));
+    MT_REQUIRE(dev >= 0 && dev < SEL_MAX_DEVICES, "device index beyond the scratch table");
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        MT_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        MT_REQUIRE(p != nullptr, "no device address for the selection scratch");
+        g_scratch_ptr[dev] = (unsigned char *)p;
+    }
+    return g_scratch_ptr[dev];
 }
 
 static unsigned contain_blocks(u64 n_min) {
@@ -142,17 +203,49 @@ extern "C" int mt_select_genomes(const uint64_t *hits, uint64_t n_genomes, uint6
         DBuf<unsigned long long> mx(1);
         DBuf<u32> keep(n_genomes);
         DBuf<u64> at(n_genomes + 1);
-        MT_HIP(hipMemsetAsync(mx.p, 0, sizeof(unsigned long long), s));
-        k_max_hits<<<(unsigned)std::min<u64>(grid_for(n_genomes, 256), 1024), 256, 0, s>>>(hits, n_genomes, mx.p);
-        MT_HIP(hipGetLastError());
-        k_keep<<<grid_for(n_genomes, 256), 256, 0, s>>>(hits, n_genomes, mx.p, cutoff_num, cutoff_den, keep.p);
-        MT_HIP(hipGetLastError());
-        scan_u32(keep.p, at.p, n_genomes, s);
-        k_place<<<grid_for(n_genomes, 256), 256, 0, s>>>(keep.p, at.p, n_genomes, selected);
-        MT_HIP(hipGetLastError());
+        select_into(hits, n_genomes, cutoff_num, cutoff_den, selected, mx.p, keep.p, at.p, nullptr, 0, s);
         u64 out[2];
         MT_HIP(hipMemcpyAsync(&out[0], at.p + n_genomes, sizeof(u64), hipMemcpyDeviceToHost, s));
         MT_HIP(hipMemcpyAsync(&out[1], mx.p, sizeof(u64), hipMemcpyDeviceToHost, s));
+        MT_HIP(hipStreamSynchronize(s));
+        *n_selected = out[0];
+        *max_hits = out[1];
+    });
+}
+
+extern "C" int mt_select_genomes_noalloc(const uint64_t *hits, uint64_t n_genomes, uint64_t cutoff_num,
+                                         uint64_t cutoff_den, uint32_t *selected, uint64_t *n_selected,
+                                         uint64_t *max_hits, void *stream) {
+    if ((!hits || !selected) && n_genomes) {
+        set_last_error("mt_select_genomes_noalloc: null argument");
+        return MT_EINVAL;
+    }
+    if (!n_selected || !max_hits) {
+        set_last_error("mt_select_genomes_noalloc: null argument");
+        return MT_EINVAL;
+    }
+    if (cutoff_den == 0) {
+        set_last_error("mt_select_genomes_noalloc: cutoff denominator must be nonzero");
+        return MT_EINVAL;
+    }
+    if (n_genomes > SEL_NOALLOC_MAX) {
+        set_last_error("mt_select_genomes_noalloc: more than 1,048,576 genomes (use mt_select_genomes)");
+        return MT_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    return guarded("mt_select_genomes_noalloc", [&] {
+        *n_selected = 0;
+        *max_hits = 0;
+        if (n_genomes == 0) return;
+        unsigned char *base = scratch_on_device();
+        auto *mx = (unsigned long long *)base;
+        auto *keep = (u32 *)(base + SEL_KEEP_OFF);
+        auto *at = (u64 *)(base + SEL_AT_OFF);
+        auto *ws = (u64 *)(base + SEL_WS_OFF);
+        select_into(hits, n_genomes, cutoff_num, cutoff_den, selected, mx, keep, at, ws, SEL_WS_WORDS, s);
+        u64 out[2];
+        MT_HIP(hipMemcpyAsync(&out[0], at + n_genomes, sizeof(u64), hipMemcpyDeviceToHost, s));
+        MT_HIP(hipMemcpyAsync(&out[1], mx, sizeof(u64), hipMemcpyDeviceToHost, s));
         MT_HIP(hipStreamSynchronize(s));
         *n_selected = out[0];
         *max_hits = out[1];

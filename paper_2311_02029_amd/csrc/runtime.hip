@@ -261,6 +261,28 @@ static void scan_impl(const T *in, u64 *out, u64 n, hipStream_t s) {
 void scan_u64(const u64 *in, u64 *out, u64 n, hipStream_t s) { scan_impl<u64>(in, out, n, s); }
 void scan_u32(const u32 *in, u64 *out, u64 n, hipStream_t s) { scan_impl<u32>(in, out, n, s); }
 
+u64 scan_ws_words(u64 n) {
+    const u64 nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    return nb <= 1 ? 0 : 2 * nb + 1;
+}
+
+void scan_u32_ws(const u32 *in, u64 *out, u64 n, u64 *ws, u64 ws_words, hipStream_t s) {
+    const u64 nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    if (nb <= 1) {
+        k_scan_final<u32><<<1, SCAN_THREADS, 0, s>>>(in, n, out, nullptr);
+        MT_HIP(hipGetLastError());
+        return;
+    }
+    if (nb > (u64)SCAN_TILE || ws_words < 2 * nb + 1) throw Error(MT_EINTERNAL, "scan workspace too small");
+    u64 *sums = ws, *sums_scan = ws + nb;  // nb block sums, then their nb + 1 offsets
+    k_scan_sums<u32><<<grid_for(n, SCAN_TILE), SCAN_THREADS, 0, s>>>(in, n, sums);
+    MT_HIP(hipGetLastError());
+    k_scan_final<u64><<<1, SCAN_THREADS, 0, s>>>(sums, nb, sums_scan, nullptr);
+    MT_HIP(hipGetLastError());
+    k_scan_final<u32><<<grid_for(n, SCAN_TILE), SCAN_THREADS, 0, s>>>(in, n, out, sums_scan);
+    MT_HIP(hipGetLastError());
+}
+
 __global__ void k_segment_map(const u64 *__restrict__ off, u64 n, u32 *__restrict__ map, u64 cap) {
     u64 sidx = (u64)blockIdx.x * blockDim.x + threadIdx.x;
     if (sidx >= n) return;

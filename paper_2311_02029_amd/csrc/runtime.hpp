@@ -108,6 +108,10 @@ struct DBuf {
 // out[n] = total.  in and out may not alias.
 void scan_u64(const u64 *in, u64 *out, u64 n, hipStream_t s);
 void scan_u32(const u32 *in, u64 *out, u64 n, hipStream_t s);
+// The same scan with the caller's workspace instead of the allocator: ws
+// holds scan_ws_words(n) words (n up to 2048 * 2048).
+u64 scan_ws_words(u64 n);
+void scan_u32_ws(const u32 *in, u64 *out, u64 n, u64 *ws, u64 ws_words, hipStream_t s);
 
 // Writes map[b] = s for every block b < cap of segment s given the segment
 // offsets off[0..n] (exclusive scan of the segment sizes).
