@@ -344,6 +344,66 @@ def serving_bench(mt, ix, pool, seconds: float, loads=(0.5, 0.8, 0.95), runs: in
     return out
 
 
+def trace_overlap(path: str, kernel: str = "k_fused") -> dict:
+    """From a rocprofv3 kernel-trace CSV: the dispatches of `kernel`, the queues
+    they ran on, the time during which dispatches of two or more different
+    queues were running at once, and how many dispatches overlapped one of
+    another queue."""
+    import csv
+    rows = []
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            if kernel in r.get("Kernel_Name", ""):
+                rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r.get("Queue_Id", r.get("Stream_Id"))))
+    rows.sort()
+    queues = sorted(set(q for _, _, q in rows))
+    overlapped = 0
+    for i, (s0, e0, q0) in enumerate(rows):
+        for j in range(max(0, i - 64), min(len(rows), i + 64)):
+            s1, e1, q1 = rows[j]
+            if j != i and q1 != q0 and s1 < e0 and s0 < e1:
+                overlapped += 1
+                break
+    ev = sorted([(s, 1, q) for s, _, q in rows] + [(e, -1, q) for _, e, q in rows])
+    active, busy, multi, last = {}, 0, 0, None
+    for t, d, q in ev:
+        if last is not None:
+            n_q = sum(1 for v in active.values() if v > 0)
+            if n_q >= 1:
+                busy += t - last
+            if n_q >= 2:
+                multi += t - last
+        active[q] = active.get(q, 0) + d
+        last = t
+    return {"kernel": kernel, "dispatches": len(rows), "queues": len(queues),
+            "dispatches_overlapping_another_queue": overlapped,
+            "busy_ns": busy, "ns_with_two_or_more_queues_running": multi,
+            "share_of_busy_time_overlapped": round(multi / busy, 4) if busy else 0.0}
+
+
+def counter_summary(paths) -> dict:
+    """rocprofv3 --pmc CSVs -> {kernel [lds bytes]: {counter: mean per dispatch, dispatches: n}}.  Launches of
+    one kernel with different dynamic LDS sizes (the long-read filter's bins) are kept apart."""
+    import csv
+    acc = {}
+    for path in paths:
+        with open(path) as f:
+            for r in csv.DictReader(f):
+                name = r["Kernel_Name"].split("(")[0]
+                lds = r.get("LDS_Block_Size", "")
+                wg = r.get("Workgroup_Size", "")
+                key = f"{name} [lds {lds}, wg {wg}]" if "k_filter_long" in name else name
+                d = acc.setdefault(key, {})
+                c = d.setdefault(r["Counter_Name"], {})
+                did = r.get("Dispatch_Id", r.get("Correlation_Id"))
+                c[did] = c.get(did, 0.0) + float(r["Counter_Value"])  # rows of one dispatch add up
+    out = {}
+    for key, d in sorted(acc.items()):
+        out[key] = {cn: round(sum(v.values()) / len(v), 1) for cn, v in sorted(d.items())}
+        out[key]["dispatches"] = max(len(v) for v in d.values())
+    return out
+
+
 def cpu_model() -> str:
     try:
         for ln in open("/proc/cpuinfo"):
@@ -400,15 +460,30 @@ def main() -> int:
     ap.add_argument("--extras", type=int, default=1,
                     help="1: also the other workloads, forms, serving and the CPU baseline; 0: the headline only")
     ap.add_argument("--cpu", type=int, default=1, help="0 skips the CPU baseline")
-    ap.add_argument("--cpu-single-reads", type=int, default=60_000)
-    ap.add_argument("--cpu-all-reads", type=int, default=600_000)
+    ap.add_argument("--cpu-single-reads", type=int, default=150_000)
+    ap.add_argument("--cpu-all-reads", type=int, default=2_000_000)
     ap.add_argument("--serve-seconds", type=float, default=20.0, help="length of each served trace")
     ap.add_argument("--serve-runs", type=int, default=2, help="traces per offered load")
     ap.add_argument("--only", default="", help="comma list of extras to run (strains_forms, e2e, cpu, "
                                                  "strains_served, batched, uneven, serving); empty: all")
+    ap.add_argument("--extra-steps", type=int, default=10, help="timed steps of each extra measurement")
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="1: autotune the filter variants of the uneven workload first; 0: built-in defaults")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times), to scale HBM byte counters")
+    ap.add_argument("--counter-summary", nargs="+", default=[], metavar="CSV",
+                    help="only summarise rocprofv3 --pmc counter CSVs: per kernel (and dynamic LDS size), the mean "
+                         "of every counter per dispatch")
+    ap.add_argument("--trace-overlap", default="", metavar="CSV",
+                    help="only summarise a rocprofv3 kernel-trace CSV: how often k_fused dispatches of different "
+                         "queues (the server's worker streams) ran at the same time")
     args = ap.parse_args()
+    if args.trace_overlap:
+        print(json.dumps(trace_overlap(args.trace_overlap)), flush=True)
+        return 0
+    if args.counter_summary:
+        print(json.dumps(counter_summary(args.counter_summary), indent=1), flush=True)
+        return 0
     if args.calibrate_copy:
         import torch
         nbytes = args.calibrate_copy << 20
@@ -579,8 +654,8 @@ def main() -> int:
             for E in (0, 3, 7, 15):
                 row = {}
                 for name, m in (("fused", mt.MT_MODE_FUSED), ("per_stage", mt.MT_MODE_PER_STAGE)):
-                    res, st = time_form(mt, bix, dr, dict(min_hits=3, top_n=3, e_value=E, mode=m), 10, 2,
-                                        timing=True)
+                    res, st = time_form(mt, bix, dr, dict(min_hits=3, top_n=3, e_value=E, mode=m),
+                                        args.extra_steps, 2, timing=True)
                     row[name] = res
                     if name == "fused" and "fused" in res["stages_ms"]:
                         d = res["stages_ms"]["fused"] / 1000.0
@@ -607,10 +682,20 @@ def main() -> int:
                 out["E_sweep"][str(E)] = row
                 log(f"[bench] batched E={E}: fused {row['fused']['ms_per_step']} ms, per-stage "
                     f"{row['per_stage']['ms_per_step']} ms")
-            res, _ = time_form(mt, bix, dr, dict(min_hits=3, top_n=3, e_value=7, mode=mt.MT_MODE_FUSED_GRAPH), 10, 2,
-                               timing=False)
+            res, _ = time_form(mt, bix, dr, dict(min_hits=3, top_n=3, e_value=7, mode=mt.MT_MODE_FUSED_GRAPH),
+                               args.extra_steps, 2, timing=False)
             res.pop("stages_ms")
             out["graph_E7"] = res
+            # E = 31 per stage: the rows-in-lanes filter with one 64-lane group per pair
+            res, _ = time_form(mt, bix, dr, dict(min_hits=3, top_n=3, e_value=31, mode=mt.MT_MODE_PER_STAGE),
+                               args.extra_steps, 2, timing=True)
+            r = bix.classify(dr, min_hits=3, top_n=3, e_value=31, mode=mt.MT_MODE_PER_STAGE)
+            host = r.to_host()
+            r.free()
+            uo = float(useful_ops(host, breads.lengths()).sum())
+            ms = res["stages_ms"].get("filter E<=31")
+            res["filter_useful_ops_frac"] = round(uo / (ms / 1e3 * VALU_LANE_OPS_PEAK), 4) if ms else None
+            out["per_stage_E31"] = res
             # stage 1 on the same index and batch
             hits = bix.containment(dr)
             torch.cuda.synchronize()
@@ -683,14 +768,16 @@ def main() -> int:
             dr = mt.to_device(ur)
             uq = dict(min_hits=3, top_n=3, e_mode=mt.MT_E_CEIL_PERMILLE, e_value=50)
             t0 = time.time()
-            tune = bix.autotune(dr, reps=3, **uq)
+            mt.tune_reset()
+            tune = bix.autotune(dr, reps=3, **uq) if args.autotune else mt.tune_info()
             out = {"workload": "uneven: 500 Mbp; 2M reads, 95% of U{75..300} bp, 5% of U{1000..10000} bp at 2% "
                                "substitutions + 3% indels; E=ceil(5% of length); autotuned",
                    "autotune_s": round(time.time() - t0, 1),
                    "tuning": {b["name"]: b["current"] for b in tune if b["pairs"]}}
             for name, m in (("fused", mt.MT_MODE_FUSED), ("per_stage", mt.MT_MODE_PER_STAGE),
                             ("graph", mt.MT_MODE_FUSED_GRAPH)):
-                res, _ = time_form(mt, bix, dr, dict(uq, mode=m), 3, 1, timing=(name != "graph"))
+                res, _ = time_form(mt, bix, dr, dict(uq, mode=m), max(1, min(3, args.extra_steps)), 1,
+                                   timing=(name != "graph"))
                 out[name] = res
             out["fused_over_per_stage"] = round(out["per_stage"]["ms_per_step"] / out["fused"]["ms_per_step"], 3)
             r = bix.classify(dr, mode=mt.MT_MODE_PER_STAGE, **uq)

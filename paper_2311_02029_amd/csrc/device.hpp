@@ -137,6 +137,75 @@ __device__ inline Bits64 fetch_ref(const u64x2 *__restrict__ lohi, const u64 *__
     return r;
 }
 
+// Reference block blk (bases 64 blk .. 64 blk + 63) of a genome of length L
+// with its bounds applied: a block before the genome or wholly past its end
+// reads as invalid (nb = 1), and positions at or past L inside the last
+// block get nb = 1.  has_n = 0 skips the N plane (the genome has no N).
+__device__ inline Bits64 ref_block(const u64x2 *__restrict__ lohi, const u64 *__restrict__ nb, i64 L, bool has_n,
+                                   i64 blk) {
+    Bits64 r;
+    if (blk < 0 || blk * 64 >= L) {
+        r.lo = r.hi = 0;
+        r.nb = ~0ull;
+        return r;
+    }
+    const u64x2 a = lohi[blk];
+    r.lo = a.lo;
+    r.hi = a.hi;
+    r.nb = has_n ? nb[blk] : 0ull;
+    const i64 room = L - blk * 64;
+    if (room < 64) r.nb |= ~0ull << room;
+    return r;
+}
+
+// The mismatch words of one band row over read words 0..NW-1 (columns
+// 64w .. 64w + 63), the row's reference starting at position p0 = diag + d
+// (any sign): the NW + 1 reference blocks the row spans are each fetched once
+// and every word is one funnel shift of two neighbouring blocks by p0 mod 64.
+// The blocks are taken in order with only two of them live at a time (the
+// caller's registers are scarce).  qword(w) gives the read's lo / hi / nb
+// word w (nb 1 past the read's end, so the row's bits past column m are set).
+template <int NW, class QWord>
+__device__ inline void band_row(QWord qword, const u64x2 *__restrict__ rl, const u64 *__restrict__ rn, i64 L,
+                                bool has_n, i64 p0, u64 (&row)[NW]) {
+    const i64 blk = p0 >> 6;  // floor division: p0 may be negative
+    const u32 s = (u32)p0 & 63u;
+    Bits64 prev = ref_block(rl, rn, L, has_n, blk);
+#pragma unroll
+    for (int w = 0; w < NW; w++) {
+        const Bits64 next = ref_block(rl, rn, L, has_n, blk + w + 1);
+        const Bits64 q = qword(w);
+        row[w] = (q.lo ^ funnel(prev.lo, next.lo, s)) | (q.hi ^ funnel(prev.hi, next.hi, s)) | q.nb |
+                 funnel(prev.nb, next.nb, s);
+        prev = next;
+    }
+}
+
+// Word w of a row held in NW registers (all ones past the last word), by a
+// chain of selects: a dynamically indexed array would go to scratch memory.
+template <int NW>
+__device__ inline u64 row_word(const u64 (&r)[NW], int w) {
+    u64 v = ~0ull;
+#pragma unroll
+    for (int i = NW - 1; i >= 0; i--) v = w == i ? r[i] : v;
+    return v;
+}
+
+// Obstacle-free run of a row held in registers from column j (the row's bits
+// past the read's end are set, so the run stops by the end).
+template <int NW>
+__device__ inline int reg_run(const u64 (&r)[NW], int j) {
+    int w = j >> 6;
+    const u32 s = (u32)j & 63u;
+    int run = 0;
+    for (;;) {
+        const u64 v = funnel(row_word<NW>(r, w), row_word<NW>(r, w + 1), s);
+        if (v) return run + (int)__builtin_ctzll(v);
+        run += 64;
+        w += 1;
+    }
+}
+
 // Mismatch ("obstacle") bits of 64 columns: 1 where the read base cannot match.
 __device__ inline u64 mismatch(const Bits64 &q, const Bits64 &w) {
     return (q.lo ^ w.lo) | (q.hi ^ w.hi) | q.nb | w.nb;

@@ -110,7 +110,46 @@ __global__ void k_pair_scatter(FilterArgs a, u64 n_cap, const u8 *__restrict__ c
     }
 }
 
-// G lanes per pair over the bucket idx[0, n).
+// The obstacle walk of one pair by a group of G lanes with one band row per
+// lane (2E + 1 <= G) for a read of at most 64 NW bases: lane l builds row
+// d = l - E in NW registers (rows past 2E + 1 read as all obstacles and never
+// lead), then every step is a run length per lane from its registers and a
+// maximum over the group.  Returns min(count, E + 1).
+template <int G, int NW>
+__device__ inline int walk_in_registers(const PairView &v, int E, int lane) {
+    const int nwr = (v.m + 63) / 64 + 1;  // the read's blocks, its padding block included
+    u64 row[NW];
+    if (lane < 2 * E + 1) {
+        auto qword = [&](int w) {
+            Bits64 q;
+            if (w < nwr) {
+                const u64x2 x = v.qlohi[w];
+                q.lo = x.lo;
+                q.hi = x.hi;
+                q.nb = v.qnb[w];
+            } else {
+                q.lo = q.hi = 0;
+                q.nb = ~0ull;
+            }
+            return q;
+        };
+        band_row<NW>(qword, v.rlohi, v.rnb, v.L, v.has_n, v.diag + (lane - E), row);
+    } else {
+#pragma unroll
+        for (int w = 0; w < NW; w++) row[w] = ~0ull;
+    }
+    int j = 0, c = 0;
+    for (;;) {
+        j += group_max<G>(reg_run<NW>(row, j));
+        if (j >= v.m) break;
+        c += 1;
+        if (c > E) break;
+        j += 1;
+    }
+    return c < E + 1 ? c : E + 1;
+}
+
+// G lanes per pair over the bucket idx[0, n).// G lanes per pair over the bucket idx[0, n).
 template <int G>
 __global__ __launch_bounds__(256) void k_filter(FilterArgs a, const u32 *__restrict__ idx, u64 n) {
     u64 tid = (u64)blockIdx.x * blockDim.x + threadIdx.x;
@@ -140,7 +179,18 @@ __global__ __launch_bounds__(256) void k_filter(FilterArgs a, const u32 *__restr
     v.L = (i64)gm.len;
     v.has_n = meta_has_n(gm);
     v.diag = a.pair_diag[p];
-    int approx = obstacle_walk<G>(v, E, lane);
+    const int rows = 2 * E + 1;
+    int approx;
+    // One band row per lane and reads of up to 256 bases (the E <= 7 / 15 / 31
+    // buckets but their reads of 257+ bases): the row's mismatch words are
+    // built once, from one fetch of each reference block it spans, and the
+    // walk runs on registers.  The branch is uniform over the group.  (A
+    // five-word path for reads up to 320 bases took the kernel from 69 to 81
+    // registers and 7 to 5 wavefronts per SIMD.)
+    if (rows <= G && v.m <= 256)
+        approx = walk_in_registers<G, 4>(v, E, lane);
+    else
+        approx = obstacle_walk<G>(v, E, lane);
     if (lane == 0) {
         a.approx[p] = (u16)approx;
         a.accept[p] = approx <= E;

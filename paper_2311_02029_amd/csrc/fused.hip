@@ -132,36 +132,6 @@ __device__ inline u32 lanes_below(u64 m, int lane) {
     return (u32)__popcll(lane ? m & ((~0ull) >> (64 - lane)) : 0ull);
 }
 
-// The mismatch words of one band row over the whole read (bases 0..255).
-// Kept as four scalars, never as an array: a dynamically indexed array would
-// be placed in scratch memory.  Word 4 and beyond read as all ones.
-struct RowBits {
-    u64 w0, w1, w2, w3;
-};
-
-__device__ inline u64 row_word(RowBits r, int w) {
-    u64 v = ~0ull;
-    v = w == 3 ? r.w3 : v;
-    v = w == 2 ? r.w2 : v;
-    v = w == 1 ? r.w1 : v;
-    v = w == 0 ? r.w0 : v;
-    return v;
-}
-
-// Obstacle-free run of a row from column j (bits past the read's end are
-// set, so the run stops by the end).
-__device__ inline int reg_run(RowBits r, int j) {
-    int w = j >> 6;
-    u32 s = (u32)j & 63u;
-    int run = 0;
-    for (;;) {
-        u64 v = funnel(row_word(r, w), row_word(r, w + 1), s);
-        if (v) return run + (int)__builtin_ctzll(v);
-        run += 64;
-        w += 1;
-    }
-}
-
 // Slot of a location key in the per-read LDS table.
 __device__ inline u32 tslot(u64 key) {
     u32 x = (u32)key ^ (u32)(key >> 29);
@@ -253,25 +223,28 @@ __device__ inline void filter_batch(const FusedArgs &a, const QEntry *q, int qn,
     const u32 g = key_genome(e.key);
     const i64 diag = key_diag(e.key);
     const GenomeMeta gm = KA(meta)[g];
-    RowBits row{~0ull, ~0ull, ~0ull, ~0ull};
+    u64 row[4] = {~0ull, ~0ull, ~0ull, ~0ull};
     if (lane_g < 2 * E + 1) {
+        // four 64-base fetches per row (building the row from the five blocks it
+        // spans, each fetched once, needs more live registers than this kernel
+        // has to spare: it spilled four times as many)
         const i64 base = diag + (lane_g - E);
         const u64x2 *rl = KA(ref_lohi) + gm.blk;
         const u64 *rn = KA(ref_nb) + gm.blk;
         const i64 L = (i64)gm.len;
         const bool hn = meta_has_n(gm);
-        Bits64 w0 = fetch_ref(rl, rn, L, hn, base);
-        Bits64 w1 = fetch_ref(rl, rn, L, hn, base + 64);
-        Bits64 w2 = fetch_ref(rl, rn, L, hn, base + 128);
-        Bits64 w3 = fetch_ref(rl, rn, L, hn, base + 192);
-        row.w0 = (pr.plane[0] ^ w0.lo) | (pr.plane[4] ^ w0.hi) | pr.plane[8] | w0.nb;
-        row.w1 = (pr.plane[1] ^ w1.lo) | (pr.plane[5] ^ w1.hi) | pr.plane[9] | w1.nb;
-        row.w2 = (pr.plane[2] ^ w2.lo) | (pr.plane[6] ^ w2.hi) | pr.plane[10] | w2.nb;
-        row.w3 = (pr.plane[3] ^ w3.lo) | (pr.plane[7] ^ w3.hi) | pr.plane[11] | w3.nb;
+        const Bits64 w0 = fetch_ref(rl, rn, L, hn, base);
+        const Bits64 w1 = fetch_ref(rl, rn, L, hn, base + 64);
+        const Bits64 w2 = fetch_ref(rl, rn, L, hn, base + 128);
+        const Bits64 w3 = fetch_ref(rl, rn, L, hn, base + 192);
+        row[0] = (pr.plane[0] ^ w0.lo) | (pr.plane[4] ^ w0.hi) | pr.plane[8] | w0.nb;
+        row[1] = (pr.plane[1] ^ w1.lo) | (pr.plane[5] ^ w1.hi) | pr.plane[9] | w1.nb;
+        row[2] = (pr.plane[2] ^ w2.lo) | (pr.plane[6] ^ w2.hi) | pr.plane[10] | w2.nb;
+        row[3] = (pr.plane[3] ^ w3.lo) | (pr.plane[7] ^ w3.hi) | pr.plane[11] | w3.nb;
     }
     int j = 0, c = 0;
     for (;;) {
-        int run = group_max<G>(reg_run(row, j));
+        int run = group_max<G>(reg_run<4>(row, j));
         j += run;
         if (j >= m) break;
         c += 1;
@@ -329,12 +302,13 @@ __device__ inline void finalize_read(const FusedArgs &a, const PendRead &pr, u64
 // Runs the queued filter batch (group size by the queue's class), then
 // finalizes every pending read whose last candidate it filtered.  Returns the
 // new set of used pending slots.
+template <int MAXG>
 __device__ inline u32 flush_queue(const FusedArgs &a, QEntry *q, int &qn, int qG, PendRead *pend, u32 used,
                                   int lane, u64 *wst) {
     if (qn > 0) {
-        if (qG == 16)
+        if (MAXG == 16 || qG == 16)
             filter_batch<16>(a, q, qn, pend, lane);
-        else if (qG == 32)
+        else if (MAXG == 32 || qG == 32)
             filter_batch<32>(a, q, qn, pend, lane);
         else
             filter_batch<64>(a, q, qn, pend, lane);
@@ -371,6 +345,11 @@ __device__ inline void issue_read_bytes(const FusedArgs &a, u64 r, int lane, Rea
 
 // Five wavefronts per SIMD (96 registers, a few spilled; the LDS of 4-wave
 // blocks also allows five): the kernel waits on memory as much as it issues.
+//
+// MAXG: the widest filter group the launch needs (16 when every read's E is at
+// most 7, 32 when at most 15, 64 in general); narrower instances hold fewer
+// copies of the filter, which leaves the register allocator more room.
+template <int MAXG>
 __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_fused(FusedArgs a) {
     __shared__ u64 sh_h[F_WPB][F_MAX_M];     // k-mer hashes (~0 when invalid); later candidate keys
     __shared__ u64 sh_tkey[F_WPB][F_TSLOTS]; // per-read hash table of (genome, diagonal) keys
@@ -657,7 +636,7 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
             }
         } else {
             const int rows = 2 * E + 1;
-            const int G = rows <= 16 ? 16 : rows <= 32 ? 32 : 64;
+            const int G = (MAXG == 16 || rows <= 16) ? 16 : (MAXG == 32 || rows <= 32) ? 32 : 64;
             used |= 1u << slot;
             if (lane == 0) {
                 pr.r = r;
@@ -670,7 +649,8 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
             // one flush site: the queue is flushed when it is full or holds
             // pairs of another group size
             for (int c = 0; c < nc; c++) {
-                if (qn > 0 && (qn == 64 / qG || qG != G)) used = flush_queue(a, queue, qn, qG, pend, used, lane, wst);
+                if (qn > 0 && (qn == 64 / qG || qG != G))
+                    used = flush_queue<MAXG>(a, queue, qn, qG, pend, used, lane, wst);
                 qG = G;
                 if (lane == 0) {
                     u32 si = sel[c];
@@ -691,7 +671,7 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
         cur = nxt;
         wave_sync();
     }
-    used = flush_queue(a, queue, qn, qG, pend, used, lane, wst);
+    used = flush_queue<MAXG>(a, queue, qn, qG, pend, used, lane, wst);
     if (lane == 0) {
         if (used) wflags |= ERR_INTERNAL;  // every queued read is finalized by now
         if (wflags) atomicOr(KA(flags), wflags);
@@ -866,7 +846,14 @@ static void enqueue_fused(const FusedLaunch &L, Timer *tm, hipStream_t s) {
     k_fused_init<<<1, 64, 0, s>>>(L.ctl);
     k_check_reads<<<grid_for(L.n, 256), 256, 0, s>>>(a.off, L.n, L.total, L.ctl + CTL_GATE);
     if (tm) tm->mark("check");
-    k_fused<<<L.blocks, 64 * F_WPB, 0, s>>>(a);
+    // the widest filter group any read can need: E is fixed, or at most 31 in the kernel
+    const u32 maxE = a.e_mode == MT_E_FIXED ? a.e_value : (u32)F_MAX_E;
+    if (maxE <= 7)
+        k_fused<16><<<L.blocks, 64 * F_WPB, 0, s>>>(a);
+    else if (maxE <= 15)
+        k_fused<32><<<L.blocks, 64 * F_WPB, 0, s>>>(a);
+    else
+        k_fused<64><<<L.blocks, 64 * F_WPB, 0, s>>>(a);
     if (tm) tm->mark("fused");
     scan_u32(a.ncand, L.res->cand_off.p, L.n, s);
     k_compact_staged<<<grid_for(L.n, 256), 256, 0, s>>>(L.ctl + CTL_GATE, L.res->cand_off.p, L.n, L.N, L.res->cap,
