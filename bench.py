@@ -626,7 +626,7 @@ def main() -> int:
 
             def reads_fn(n, m):
                 return synth.SeqSet(seq=reads.seq[:n * 150], offsets=reads.offsets[:n + 1])
-            budget = 768 << 20
+            budget = 256 << 20
             return serving_bench(mt, ix, None, seconds=args.serve_seconds / 2, loads=(0.8,), runs=2,
                                  baseline_s=0, mem_budget=budget, max_batch_reads=1 << 18, q=rq,
                                  reads_fn=reads_fn,

@@ -139,14 +139,19 @@ __device__ inline u32 tslot(u64 key) {
 }
 
 // Counts one seed hit of `key` in the per-read LDS table (linear probing; the
-// table never holds more than F_HIT_CAP <= F_TSLOTS distinct keys).
-__device__ inline void table_add(u64 *tkey, u32 *tcnt, u64 key) {
+// table never holds more than F_HIT_CAP <= F_TSLOTS distinct keys).  A key's
+// first hit also lists its slot (tlist, count *tn), so that the candidate
+// scan visits only the slots in use.
+__device__ inline void table_add(u64 *tkey, u32 *tcnt, u8 *tlist, u32 *tn, u64 key) {
     u32 s = tslot(key);
     for (int probe = 0; probe < F_TSLOTS; probe++, s = (s + 1) & (F_TSLOTS - 1)) {
         u64 cur = tkey[s];
         if (cur == ~0ull) {
             cur = atomicCAS((unsigned long long *)&tkey[s], ~0ull, (unsigned long long)key);
-            if (cur == ~0ull) cur = key;
+            if (cur == ~0ull) {
+                cur = key;
+                tlist[atomicAdd(tn, 1u)] = (u8)s;
+            }
         }
         if (cur == key) {
             atomicAdd(&tcnt[s], 1u);
@@ -213,8 +218,26 @@ __device__ inline int window_argmin_any(const u64 *hh, int ws, int win) {
 // come from the read planes (LDS) and 64-base reference fetches, then the
 // obstacle walk runs on registers.  Results go to the staging slot and to the
 // pair's pending read.
+// Obstacle-free run from column j of a row kept in LDS as four words (all
+// ones past them; the row's bits past the read's end are set, so the run
+// stops by the end).
+__device__ inline int lds_run(const u64 *row, int j) {
+    int w = j >> 6;
+    const u32 s = (u32)j & 63u;
+    int run = 0;
+    for (;;) {
+        const u64 lo = w < 4 ? row[w < 3 ? w : 3] : ~0ull;
+        const u64 hi = w + 1 < 4 ? row[w + 1 < 3 ? w + 1 : 3] : ~0ull;
+        const u64 v = funnel(lo, hi, s);
+        if (v) return run + (int)__builtin_ctzll(v);
+        run += 64;
+        w += 1;
+    }
+}
+
 template <int G>
-__device__ inline void filter_batch(const FusedArgs &a, const QEntry *q, int qn, PendRead *pend, int lane) {
+__device__ inline void filter_batch(const FusedArgs &a, const QEntry *q, int qn, PendRead *pend, int lane,
+                                    u64 *rowbuf) {
     const int gi = lane / G, lane_g = lane % G;
     if (gi >= qn) return;
     const QEntry e = q[gi];
@@ -242,15 +265,25 @@ __device__ inline void filter_batch(const FusedArgs &a, const QEntry *q, int qn,
         row[2] = (pr.plane[2] ^ w2.lo) | (pr.plane[6] ^ w2.hi) | pr.plane[10] | w2.nb;
         row[3] = (pr.plane[3] ^ w3.lo) | (pr.plane[7] ^ w3.hi) | pr.plane[11] | w3.nb;
     }
+    // the row goes to this lane's four words of the per-read LDS table (empty
+    // while candidates are filtered: 64 lanes x 4 words fill its 256 slots)
+    // and is walked from there, which keeps registers free; the table is
+    // emptied again afterwards
+    u64 *myrow = rowbuf + 4 * lane;
+    myrow[0] = row[0];
+    myrow[1] = row[1];
+    myrow[2] = row[2];
+    myrow[3] = row[3];
     int j = 0, c = 0;
     for (;;) {
-        int run = group_max<G>(reg_run<4>(row, j));
+        int run = group_max<G>(lds_run(myrow, j));
         j += run;
         if (j >= m) break;
         c += 1;
         if (c > E) break;
         j += 1;
     }
+    myrow[0] = myrow[1] = myrow[2] = myrow[3] = ~0ull;
     const int ap = c < E + 1 ? c : E + 1;
     if (lane_g == 0) {
         KA(st_genome)[e.out] = g;
@@ -304,14 +337,14 @@ __device__ inline void finalize_read(const FusedArgs &a, const PendRead &pr, u64
 // new set of used pending slots.
 template <int MAXG>
 __device__ inline u32 flush_queue(const FusedArgs &a, QEntry *q, int &qn, int qG, PendRead *pend, u32 used,
-                                  int lane, u64 *wst) {
+                                  int lane, u64 *wst, u64 *rowbuf) {
     if (qn > 0) {
         if (MAXG == 16 || qG == 16)
-            filter_batch<16>(a, q, qn, pend, lane);
+            filter_batch<16>(a, q, qn, pend, lane, rowbuf);
         else if (MAXG == 32 || qG == 32)
-            filter_batch<32>(a, q, qn, pend, lane);
+            filter_batch<32>(a, q, qn, pend, lane, rowbuf);
         else
-            filter_batch<64>(a, q, qn, pend, lane);
+            filter_batch<64>(a, q, qn, pend, lane, rowbuf);
         wave_sync();
         if (lane == 0)
             for (int i = 0; i < qn; i++) pend[q[i].pend].left -= 1;
@@ -361,6 +394,8 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
     __shared__ QEntry sh_q[F_WPB][F_QCAP];
     __shared__ PendRead sh_pend[F_WPB][F_PCAP];
     __shared__ u64 sh_stats[F_WPB][ST_COUNT];
+    __shared__ u8 sh_tlist[F_WPB][F_TSLOTS];  // slots of the per-read table in use
+    __shared__ u32 sh_tn[F_WPB];             // ... and their number
 
     // wid is wave-uniform; saying so keeps every per-read value (read index,
     // length, E, loop bounds) in scalar registers.
@@ -377,7 +412,10 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
     QEntry *queue = sh_q[wid];
     PendRead *pend = sh_pend[wid];
     u64 *wst = sh_stats[wid];
+    u8 *tlist = sh_tlist[wid];
+    u32 *tn = &sh_tn[wid];
     if (lane < ST_COUNT) wst[lane] = 0;
+    if (lane == 0) *tn = 0;
     // the table starts empty and every read leaves it empty
     for (int t = lane; t < F_TSLOTS; t += 64) {
         tkey[t] = ~0ull;
@@ -537,7 +575,7 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
             }
             if (cnt) {
                 if (!(v & SLOT_MULTI)) {
-                    table_add(tkey, tcnt, cand_key((u32)(v >> 32), (i64)(u32)v - p));
+                    table_add(tkey, tcnt, tlist, tn, cand_key((u32)(v >> 32), (i64)(u32)v - p));
                 } else {  // several occurrences: four loads in flight at a time
                     const u64 st = slot_start(v);
                     for (u32 u0 = 0; u0 < cnt; u0 += 4) {
@@ -546,7 +584,7 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
                         for (int t = 0; t < 4; t++) gp[t] = u0 + t < cnt ? KA(occ)[st + u0 + t] : 0ull;
 #pragma unroll
                         for (int t = 0; t < 4; t++)
-                            if (u0 + t < cnt) table_add(tkey, tcnt, cand_key((u32)(gp[t] >> 32), (i64)(u32)gp[t] - p));
+                            if (u0 + t < cnt) table_add(tkey, tcnt, tlist, tn, cand_key((u32)(gp[t] >> 32), (i64)(u32)gp[t] - p));
                     }
                 }
             }
@@ -570,6 +608,7 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
                 tcnt[t] = 0;
             }
             if (lane == 0) {
+                *tn = 0;
                 KA(fb_list)[atomicAdd(KA(fb_count), 1u)] = (u32)r;
                 KA(ncand)[r] = 0;
             }
@@ -581,13 +620,14 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
         // 5. locations with >= min_hits hits become candidates (the table is
         // emptied as it is read), then top_n by rank
         if (!counted && H > 0) {
-#pragma unroll
-            for (int q = 0; q < F_TSLOTS / 64; q++) {
-                const int t = 64 * q + lane;
-                const u64 key = tkey[t];
-                const u32 c = tcnt[t];
+            const int nd = (int)*tn;  // distinct keys: the listed slots
+            for (int q0 = 0; q0 < nd; q0 += 64) {
+                const bool in = q0 + lane < nd;
+                const int t = in ? tlist[q0 + lane] : 0;
+                const u64 key = in ? tkey[t] : ~0ull;
+                const u32 c = in ? tcnt[t] : 0u;
                 const bool is_c = key != ~0ull && c >= T;
-                if (key != ~0ull) {
+                if (in) {
                     tkey[t] = ~0ull;
                     tcnt[t] = 0;
                 }
@@ -601,6 +641,7 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
             }
         }
         wave_sync();
+        if (lane == 0) *tn = 0;
         if (a.top_n == 0 && C > (int)N) {
             // keep-all with more candidates than staging slots: per-stage finish
             if (lane == 0) {
@@ -650,7 +691,7 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
             // pairs of another group size
             for (int c = 0; c < nc; c++) {
                 if (qn > 0 && (qn == 64 / qG || qG != G))
-                    used = flush_queue<MAXG>(a, queue, qn, qG, pend, used, lane, wst);
+                    used = flush_queue<MAXG>(a, queue, qn, qG, pend, used, lane, wst, tkey);
                 qG = G;
                 if (lane == 0) {
                     u32 si = sel[c];
@@ -671,7 +712,7 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
         cur = nxt;
         wave_sync();
     }
-    used = flush_queue<MAXG>(a, queue, qn, qG, pend, used, lane, wst);
+    used = flush_queue<MAXG>(a, queue, qn, qG, pend, used, lane, wst, tkey);
     if (lane == 0) {
         if (used) wflags |= ERR_INTERNAL;  // every queued read is finalized by now
         if (wflags) atomicOr(KA(flags), wflags);
