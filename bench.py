@@ -280,6 +280,15 @@ def serving_bench(mt, ix, pool, seconds: float, loads=(0.5, 0.8, 0.95), runs: in
             raise errs[0]
         return [r for r in recs if r is not None], st
 
+    def concurrency(st):
+        """Mean number of batches whose kernels ran at once while any ran, and the
+        fraction of that time with two or more (HIP events on the worker streams)."""
+        u = st.get("kernel_ms_union", 0.0)
+        if u <= 0:
+            return None
+        return {"mean_batches_running": round(st["kernel_ms_sum"] / u, 3),
+                "frac_time_two_or_more": round(st["kernel_ms_overlap"] / u, 3)}
+
     def summarize(recs):
         if not recs:
             return None
@@ -296,6 +305,7 @@ def serving_bench(mt, ix, pool, seconds: float, loads=(0.5, 0.8, 0.95), runs: in
     recs, st = run_served(trace(3, 1_000_000, 1.0), paced=False, stop_after=min(seconds, 10.0))
     out["saturated"] = summarize(recs)
     out["saturated"]["server"] = st
+    out["saturated"]["kernel_concurrency"] = concurrency(st)
     out["mem_budget_bytes"] = st["mem_budget_bytes"]
     log(f"[serve] saturated: {out['saturated']}")
     sat_rps = out["saturated"]["reads_per_s"]
@@ -307,6 +317,7 @@ def serving_bench(mt, ix, pool, seconds: float, loads=(0.5, 0.8, 0.95), runs: in
             recs, st = run_served(trace(3 + i + 10 * k, max(20, int(qps * seconds)), qps), paced=True)
             sm = summarize(recs)
             sm["server"] = st
+            sm["kernel_concurrency"] = concurrency(st)
             per.append(sm)
         p50 = [x["p50_ms"] for x in per]
         p99 = [x["p99_ms"] for x in per]

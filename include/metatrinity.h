@@ -383,7 +383,11 @@ int mt_server_destroy(mt_server *server);
  * the reads in them; batches that the memory budget cut short (admission
  * control held reads back until memory of running batches was released);
  * the largest estimated device bytes and the most batches in flight at once;
- * and the budget and batch cap in force (defaults resolved). */
+ * the budget and batch cap in force (defaults resolved); and, from HIP events
+ * recorded on the worker streams around each batch's kernels (after its
+ * upload, before its download), the device time of those kernels summed over
+ * the batches, the time covered by at least one of them, and the time during
+ * which the kernels of two or more batches were running at once (ms). */
 typedef struct mt_server_counters {
     uint64_t batches;
     uint64_t reads;
@@ -393,6 +397,10 @@ typedef struct mt_server_counters {
     uint64_t max_batch_reads;
     uint32_t peak_batches;
     uint32_t reserved;
+    uint64_t timed_batches;
+    double kernel_ms_sum;
+    double kernel_ms_union;
+    double kernel_ms_overlap;
 } mt_server_counters;
 int mt_server_stats(mt_server *server, mt_server_counters *out);
 

@@ -72,7 +72,9 @@ class mt_server_params(C.Structure):
 class mt_server_counters(C.Structure):
     _fields_ = [("batches", C.c_uint64), ("reads", C.c_uint64), ("budget_limited", C.c_uint64),
                 ("peak_inflight_bytes", C.c_uint64), ("mem_budget_bytes", C.c_uint64),
-                ("max_batch_reads", C.c_uint64), ("peak_batches", C.c_uint32), ("reserved", C.c_uint32)]
+                ("max_batch_reads", C.c_uint64), ("peak_batches", C.c_uint32), ("reserved", C.c_uint32),
+                ("timed_batches", C.c_uint64), ("kernel_ms_sum", C.c_double), ("kernel_ms_union", C.c_double),
+                ("kernel_ms_overlap", C.c_double)]
 
 
 class mt_tune_bucket(C.Structure):

@@ -217,6 +217,8 @@ struct mt_server {
     u64 inflight = 0;             // estimated device bytes of the batches in flight
     u32 running = 0;              // batches in flight
     mt_server_counters stats{};   // guarded by mu
+    hipEvent_t ref_ev = nullptr;  // recorded on the control stream at creation: the time origin
+    std::vector<std::pair<float, float>> spans;  // device time of every batch's kernels (ms); guarded by mu
     bool stopping = false;
     std::vector<std::thread> workers;
 
@@ -274,14 +276,16 @@ struct mt_server {
         return true;
     }
 
-    void run_batch(Batch &b, hipStream_t s, Pinned &h_in, Pinned &h_out, std::vector<Piece> &pieces);
+    void run_batch(Batch &b, hipStream_t s, Pinned &h_in, Pinned &h_out, std::vector<Piece> &pieces,
+                   hipEvent_t ev_a, hipEvent_t ev_b);
     void worker();
     // Completes a request whose reads are all classified; counts = its taxon
     // counts already on the host (2 * n_taxa + 1 values; unused on error).
     void finish(Request *r, const u64 *counts);
 };
 
-void mt_server::run_batch(Batch &b, hipStream_t s, Pinned &h_in, Pinned &h_out, std::vector<Piece> &pieces) {
+void mt_server::run_batch(Batch &b, hipStream_t s, Pinned &h_in, Pinned &h_out, std::vector<Piece> &pieces,
+                          hipEvent_t ev_a, hipEvent_t ev_b) {
     using namespace mt;
     const u64 n = b.reads;
     const u32 ns = (u32)b.slices.size();
@@ -314,6 +318,7 @@ void mt_server::run_batch(Batch &b, hipStream_t s, Pinned &h_in, Pinned &h_out, 
     unsigned long long *const *d_cnt = (unsigned long long *const *)(d_in.p + n + 1 + ns + 1);
 
     mt_seqs seqs{(const char *)d_seq.p, d_off, n, b.bases};
+    if (ev_a) MT_HIP(hipEventRecord(ev_a, s));  // the batch's kernels start after its upload
     mt_query_params q = b.q;
     q.mode = MT_MODE_FUSED;
     mt_result res;
@@ -325,6 +330,7 @@ void mt_server::run_batch(Batch &b, hipStream_t s, Pinned &h_in, Pinned &h_out, 
     const u64 nc = res.n_cands;
     for (u32 i = 0; i < ns; i++) MT_HIP(hipStreamWaitEvent(s, b.slices[i].req->zeroed, 0));
     launch_reduce_slots(res, *ix, d_slot, ns, d_cnt, s);
+    if (ev_b) MT_HIP(hipEventRecord(ev_b, s));  // ... and end before its download
 
     // Outputs back to the host in one pinned block.
     const bool with_strand = res.strand.p != nullptr;
@@ -352,6 +358,15 @@ void mt_server::run_batch(Batch &b, hipStream_t s, Pinned &h_in, Pinned &h_out, 
     MT_HIP(hipMemcpyAsync(re, res.read_E.p, n * 2, hipMemcpyDeviceToHost, s));
     MT_HIP(hipMemcpyAsync(ra, res.read_accepted.p, n, hipMemcpyDeviceToHost, s));
     MT_HIP(hipStreamSynchronize(s));
+    if (ev_a && ev_b && ref_ev) {
+        float t0 = 0, t1 = 0;
+        if (hipEventElapsedTime(&t0, ref_ev, ev_a) == hipSuccess && hipEventElapsedTime(&t1, ref_ev, ev_b) == hipSuccess) {
+            std::lock_guard<std::mutex> lk(mu);
+            if (spans.size() < (1u << 20)) spans.emplace_back(t0, t1);
+        } else {
+            (void)hipGetLastError();
+        }
+    }
 
     pieces.resize(ns);
     for (u32 i = 0; i < ns; i++) {
@@ -455,6 +470,12 @@ void mt_server::worker() {
         s = nullptr;
     }
     Pinned h_in, h_out, h_cnt;
+    hipEvent_t ev_a = nullptr, ev_b = nullptr;  // device timestamps around each batch's kernels
+    if (s && (hipEventCreate(&ev_a) != hipSuccess || hipEventCreate(&ev_b) != hipSuccess)) {
+        (void)hipGetLastError();
+        if (ev_a) (void)hipEventDestroy(ev_a);
+        ev_a = ev_b = nullptr;
+    }
     for (;;) {
         Batch b;
         {
@@ -470,7 +491,7 @@ void mt_server::worker() {
         std::string error;
         try {
             if (!s) throw Error(MT_EDEVICE, setup_error);
-            run_batch(b, s, h_in, h_out, pieces);
+            run_batch(b, s, h_in, h_out, pieces, ev_a, ev_b);
         } catch (const Error &e) {
             status = e.status;
             error = e.what();
@@ -525,6 +546,8 @@ void mt_server::worker() {
             finish(closed[i], got ? (const u64 *)(h_cnt.p + i * nt * 8) : nullptr);
     }
 out:
+    if (ev_a) (void)hipEventDestroy(ev_a);
+    if (ev_b) (void)hipEventDestroy(ev_b);
     if (s) (void)hipStreamDestroy(s);
 }
 
@@ -535,10 +558,41 @@ extern "C" int mt_server_stats(mt_server *server, mt_server_counters *out) {
         mt::set_last_error("mt_server_stats: null argument");
         return MT_EINVAL;
     }
-    std::lock_guard<std::mutex> lk(server->mu);
-    *out = server->stats;
-    out->mem_budget_bytes = server->p.mem_budget_bytes;
-    out->max_batch_reads = server->p.max_batch_reads;
+    std::vector<std::pair<float, float>> sp;
+    {
+        std::lock_guard<std::mutex> lk(server->mu);
+        *out = server->stats;
+        out->mem_budget_bytes = server->p.mem_budget_bytes;
+        out->max_batch_reads = server->p.max_batch_reads;
+        sp = server->spans;
+    }
+    // device time of the batches' kernels: their sum, their union, and the
+    // time during which two or more batches' kernels were running at once
+    std::vector<std::pair<float, int>> ev;
+    double sum = 0;
+    for (auto &x : sp) {
+        if (x.second < x.first) continue;
+        sum += x.second - x.first;
+        ev.emplace_back(x.first, 1);
+        ev.emplace_back(x.second, -1);
+    }
+    std::sort(ev.begin(), ev.end(), [](const std::pair<float, int> &a, const std::pair<float, int> &b) {
+        return a.first < b.first || (a.first == b.first && a.second < b.second);
+    });
+    double uni = 0, ovl = 0;
+    int depth = 0;
+    for (size_t i = 0; i < ev.size(); i++) {
+        if (i > 0) {
+            const double dt = ev[i].first - ev[i - 1].first;
+            if (depth >= 1) uni += dt;
+            if (depth >= 2) ovl += dt;
+        }
+        depth += ev[i].second;
+    }
+    out->timed_batches = sp.size();
+    out->kernel_ms_sum = sum;
+    out->kernel_ms_union = uni;
+    out->kernel_ms_overlap = ovl;
     return MT_OK;
 }
 
@@ -570,6 +624,8 @@ extern "C" int mt_server_create(const mt_index *index, const mt_server_params *p
         MT_HIP(hipGetDevice(&sv->device));
         sv->arena.init(p.pinned_arena_bytes);
         MT_HIP(hipStreamCreateWithFlags(&sv->ctl, hipStreamNonBlocking));
+        MT_HIP(hipEventCreate(&sv->ref_ev));
+        MT_HIP(hipEventRecord(sv->ref_ev, sv->ctl));
         for (u32 i = 0; i < p.n_streams; i++) sv->workers.emplace_back([s = sv.get()] { s->worker(); });
     });
     if (rc != MT_OK) {
@@ -580,6 +636,7 @@ extern "C" int mt_server_create(const mt_index *index, const mt_server_params *p
             }
             sv->cv_work.notify_all();
             for (auto &t : sv->workers) t.join();
+            if (sv->ref_ev) (void)hipEventDestroy(sv->ref_ev);
             if (sv->ctl) (void)hipStreamDestroy(sv->ctl);
         }
         return rc;
@@ -723,6 +780,7 @@ extern "C" int mt_server_destroy(mt_server *sv) {
     }
     sv->reqs.clear();
     for (hipEvent_t e : sv->free_events) (void)hipEventDestroy(e);
+    if (sv->ref_ev) (void)hipEventDestroy(sv->ref_ev);
     if (sv->ctl) (void)hipStreamDestroy(sv->ctl);
     delete sv;
     return MT_OK;

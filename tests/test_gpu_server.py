@@ -241,7 +241,13 @@ def test_served_trace_on_500mbp_index_matches_oracle(env, batched_db, batched_or
             t.start()
         for t in ts:
             t.join()
+        st = sv.stats()
     assert not errors, errors
+    # device spans of the batches' kernels: every batch timed; the time covered
+    # plus the time with two or more batches running cannot exceed their sum
+    assert st["timed_batches"] == st["batches"] > 0 and st["reads"] == sum(r.n for r in reqs)
+    assert 0 < st["kernel_ms_union"] <= st["kernel_ms_sum"] + 1e-3
+    assert st["kernel_ms_union"] + st["kernel_ms_overlap"] <= st["kernel_ms_sum"] + 1e-3
     for i, r in enumerate(reqs):
         ref = batched_oracle.classify(r, q["min_hits"], q["top_n"], q["e_mode"], q["e_value"])
         _same(results[i], ref, f"served request {i} ({r.n} reads of {trace[i][2]} bp) vs oracle")
