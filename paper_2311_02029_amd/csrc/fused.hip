@@ -382,7 +382,11 @@ __device__ inline void issue_read_bytes(const FusedArgs &a, u64 r, int lane, Rea
 // MAXG: the widest filter group the launch needs (16 when every read's E is at
 // most 7, 32 when at most 15, 64 in general); narrower instances hold fewer
 // copies of the filter, which leaves the register allocator more room.
-template <int MAXG>
+// REP: the index is repetitive (many k-mers occur in several genomes, as in a
+// database of near-identical strains), so reads whose probes find several
+// occurrences are also counted in registers; without it those reads use the
+// per-read LDS table, and the instance spends no registers on that path.
+template <int MAXG, bool REP>
 __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8))) void k_fused(FusedArgs a) {
     __shared__ u64 sh_h[F_WPB][F_MAX_M];     // k-mer hashes (~0 when invalid); later candidate keys
     __shared__ u64 sh_tkey[F_WPB][F_TSLOTS]; // per-read hash table of (genome, diagonal) keys
@@ -527,9 +531,13 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
         }
 
         // 4. table probes -> seed hits.  When every minimizer fits one round
-        // and each probe found at most one occurrence (the common case), the
-        // hits are counted in registers: one ballot per distinct location;
-        // otherwise they go through the per-read LDS table.
+        // and the hits fit one lane each (at most 64 of them, at most 15 per
+        // probe), they are counted in registers: one ballot per distinct
+        // location; otherwise they go through the per-read LDS table.  With
+        // one occurrence per probe (the usual case) a probe's lane holds its
+        // hit; otherwise every probe lists its hits in the (empty) table at
+        // its prefix offset and lane h takes hit h, the occurrences of all
+        // probes being read in one round trip.
         int H = 0, C = 0, nocc = 0;  // nocc: entries read from the multi-occurrence array
         bool overflow = false, counted = false;
         for (int t0 = 0; t0 < nmin; t0 += 64) {
@@ -545,13 +553,52 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
             const bool single = cnt == 1 && !(v & SLOT_MULTI);
             const u64 sm = ballot64(single);
             const u64 mm = ballot64(cnt != 0 && !single);  // probes with several occurrences
+            bool inreg = false;
+            u64 key = 0, hm = 0;  // this lane's hit and the lanes holding one
             if (t0 == 0 && nmin <= 64 && mm == 0) {
-                const u64 key = single ? cand_key((u32)(v >> 32), (i64)(u32)v - p) : 0ull;
+                key = single ? cand_key((u32)(v >> 32), (i64)(u32)v - p) : 0ull;
+                hm = sm;
                 H = __popcll(sm);
-                for (u64 rem = sm; rem;) {
+                inreg = true;
+            } else if (REP && t0 == 0 && nmin <= 64 && ballot64(cnt > 15u) == 0) {
+                // exclusive prefix sum of cnt over the lanes, bit by bit
+                u32 off = 0, tot = 0;
+#pragma unroll
+                for (int b = 0; b < 4; b++) {
+                    const u64 bm = ballot64((cnt >> b) & 1u);
+                    off += lanes_below(bm, lane) << b;
+                    tot += (u32)__popcll(bm) << b;
+                }
+                if (tot <= 64) {
+                    // per hit: the slot value (one occurrence) or the index of
+                    // the occurrence, and the minimizer position with bit 16
+                    // marking an index
+                    for (u32 u = 0; u < cnt; u++) {
+                        tkey[off + u] = single ? v : slot_start(v) + u;
+                        tcnt[off + u] = (u32)p | (single ? 0u : 0x10000u);
+                    }
+                    wave_sync();
+                    const bool has = lane < (int)tot;
+                    u64 gv = has ? tkey[lane] : 0ull;
+                    const u32 f = has ? tcnt[lane] : 0u;
+                    if (has) {  // the table is left empty again
+                        tkey[lane] = ~0ull;
+                        tcnt[lane] = 0;
+                    }
+                    if (f & 0x10000u) gv = KA(occ)[gv];
+                    key = has ? cand_key((u32)(gv >> 32), (i64)(u32)gv - (i64)(f & 0xffffu)) : 0ull;
+                    hm = ballot64(has);
+                    H = (int)tot;
+                    nocc += (int)tot - __popcll(sm);
+                    inreg = true;
+                }
+            }
+            if (inreg) {
+                const bool mine = REP ? (bool)((hm >> lane) & 1u) : single;
+                for (u64 rem = hm; rem;) {
                     const int ld = __builtin_amdgcn_readfirstlane(__builtin_ctzll(rem));
                     const u64 kl = readlane64(key, ld);
-                    const u64 eq = ballot64(single && key == kl);
+                    const u64 eq = ballot64(mine && key == kl);
                     const u32 c = (u32)__popcll(eq);
                     if (c >= T) {
                         if (lane == 0) {
@@ -880,6 +927,7 @@ struct FusedLaunch {
     u64 total;
     mt_result *res;
     FusedSummary *sum;
+    bool rep;  // repetitive index: the kernel instance with register counting of repeated k-mers
 };
 
 static void enqueue_fused(const FusedLaunch &L, Timer *tm, hipStream_t s) {
@@ -889,12 +937,21 @@ static void enqueue_fused(const FusedLaunch &L, Timer *tm, hipStream_t s) {
     if (tm) tm->mark("check");
     // the widest filter group any read can need: E is fixed, or at most 31 in the kernel
     const u32 maxE = a.e_mode == MT_E_FIXED ? a.e_value : (u32)F_MAX_E;
-    if (maxE <= 7)
-        k_fused<16><<<L.blocks, 64 * F_WPB, 0, s>>>(a);
-    else if (maxE <= 15)
-        k_fused<32><<<L.blocks, 64 * F_WPB, 0, s>>>(a);
-    else
-        k_fused<64><<<L.blocks, 64 * F_WPB, 0, s>>>(a);
+    if (L.rep) {
+        if (maxE <= 7)
+            k_fused<16, true><<<L.blocks, 64 * F_WPB, 0, s>>>(a);
+        else if (maxE <= 15)
+            k_fused<32, true><<<L.blocks, 64 * F_WPB, 0, s>>>(a);
+        else
+            k_fused<64, true><<<L.blocks, 64 * F_WPB, 0, s>>>(a);
+    } else {
+        if (maxE <= 7)
+            k_fused<16, false><<<L.blocks, 64 * F_WPB, 0, s>>>(a);
+        else if (maxE <= 15)
+            k_fused<32, false><<<L.blocks, 64 * F_WPB, 0, s>>>(a);
+        else
+            k_fused<64, false><<<L.blocks, 64 * F_WPB, 0, s>>>(a);
+    }
     if (tm) tm->mark("fused");
     scan_u32(a.ncand, L.res->cand_off.p, L.n, s);
     k_compact_staged<<<grid_for(L.n, 256), 256, 0, s>>>(L.ctl + CTL_GATE, L.res->cand_off.p, L.n, L.N, L.res->cap,
@@ -1032,6 +1089,9 @@ void classify_fused(const mt_index &ix, const mt_query_params &q, const mt_seqs 
     L.total = reads.total;
     L.res = &res;
     L.sum = sum.p;
+    // repetitive: at least one occurrence in eight belongs to a k-mer found in
+    // several places
+    L.rep = ix.n_multi_occ * 8 >= ix.n_minimizers && ix.n_multi_occ > 0;
 
     if (graph) {
         launch_fused_graph(L, s);
