@@ -475,6 +475,11 @@ def main() -> int:
     ap.add_argument("--cpu-all-reads", type=int, default=2_000_000)
     ap.add_argument("--serve-seconds", type=float, default=20.0, help="length of each served trace")
     ap.add_argument("--serve-runs", type=int, default=2, help="traces per offered load")
+    ap.add_argument("--serve-streams", type=int, default=0, help="server worker streams (0: the library default)")
+    ap.add_argument("--serve-max-batch", type=int, default=0,
+                    help="server batch cap in reads (0: the library default)")
+    ap.add_argument("--serve-baseline-s", type=float, default=4.0,
+                    help="seconds of sequential per-request solves on the 80%% trace (0 skips them)")
     ap.add_argument("--only", default="", help="comma list of extras to run (strains_forms, e2e, cpu, "
                                                  "strains_served, batched, uneven, serving); empty: all")
     ap.add_argument("--extra-steps", type=int, default=10, help="timed steps of each extra measurement")
@@ -769,6 +774,8 @@ def main() -> int:
         def serving():
             pool = synth.served_read_pool(bdb)
             return serving_bench(mt, bix, pool, seconds=args.serve_seconds, runs=args.serve_runs,
+                                 n_streams=args.serve_streams, max_batch_reads=args.serve_max_batch,
+                                 baseline_s=args.serve_baseline_s,
                                  workload="requests of U{1..50,000} reads x one length in {100..250} bp (16 lengths), "
                                           "0.5% error, E=ceil(5% of length), min_hits=3, top_n=3, 500 Mbp index "
                                           "resident; Poisson arrivals")
