@@ -460,6 +460,12 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
         PendRead &pr = pend[slot];
         if (lane < F_WORDS) stream[lane] = 0;
         bool bad = false;
+        // the next read's offsets, its start in even lanes and its end in odd
+        // ones: requested before the planes are built and read after them, so
+        // the planes hide the load (a wave-uniform load would be waited for at
+        // once, to move it to scalar registers)
+        u64 noff = 0;
+        if (rn < a.n) noff = a.off[rn + (u64)(lane & 1)];
         wave_sync();
 #pragma unroll
         for (int q = 0; q < 4; q++) {
@@ -476,12 +482,8 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
             }
             if (c < 4 && c > 0) atomicOr(&stream[i >> 4], c << (30 - 2 * (i & 15)));
         }
-        // the next read's offsets (their bytes are requested after the probes)
-        u64 nbeg = 0, nend = 0;
-        if (rn < a.n) {
-            nbeg = a.off[rn];
-            nend = a.off[rn + 1];
-        }
+        // (the next read's bytes are requested after the probes)
+        const u64 nbeg = readlane64(noff, 0), nend = readlane64(noff, 1);
         if (ballot64(bad)) {
             wflags |= ERR_BAD_BYTE;
             if (lane == 0) KA(ncand)[r] = 0;  // the call fails; its compaction still runs
@@ -706,6 +708,7 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
                 u64 kc = hh[cidx];
                 u32 hc = ccnt[cidx];
                 int rank = 0;
+#pragma unroll 4
                 for (int b = 0; b < C; b++) {
                     u32 hb = ccnt[b];
                     rank += hb > hc || (hb == hc && hh[b] < kc);
@@ -735,16 +738,21 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
             }
             wave_sync();
             // one flush site: the queue is flushed when it is full or holds
-            // pairs of another group size
-            for (int c = 0; c < nc; c++) {
+            // pairs of another group size; the candidates that fit are queued
+            // together, one lane each
+            for (int c0 = 0; c0 < nc;) {
                 if (qn > 0 && (qn == 64 / qG || qG != G))
                     used = flush_queue<MAXG>(a, queue, qn, qG, pend, used, lane, wst, tkey);
                 qG = G;
-                if (lane == 0) {
-                    u32 si = sel[c];
-                    queue[qn] = QEntry{hh[si], (u32)(r * N + (u64)c), ccnt[si], (u8)slot, (u8)c};
+                const int room = 64 / G - qn;
+                const int take = nc - c0 < room ? nc - c0 : room;
+                if (lane < take) {
+                    const int c = c0 + lane;
+                    const u32 si = sel[c];
+                    queue[qn + lane] = QEntry{hh[si], (u32)(r * N + (u64)c), ccnt[si], (u8)slot, (u8)c};
                 }
-                qn += 1;
+                qn += take;
+                c0 += take;
                 wave_sync();
             }
         }
