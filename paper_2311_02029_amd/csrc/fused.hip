@@ -445,7 +445,7 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
         if (Ewide > 65534) wflags |= ERR_E_TOO_LARGE;
         const int E = Ewide > 65535 ? 65535 : (int)Ewide;
         if (lane == 0) KA(read_E)[r] = (u16)E;
-        if (m > F_MAX_M || E > F_MAX_E) {
+        if (m > F_MAX_M || E > F_MAX_E || 2 * E + 1 > MAXG) {
             if (lane == 0) {
                 KA(fb_list)[atomicAdd(KA(fb_count), 1u)] = (u32)r;
                 KA(ncand)[r] = 0;  // until the per-stage kernels fill it in
@@ -943,8 +943,13 @@ static void enqueue_fused(const FusedLaunch &L, Timer *tm, hipStream_t s) {
     k_fused_init<<<1, 64, 0, s>>>(L.ctl);
     k_check_reads<<<grid_for(L.n, 256), 256, 0, s>>>(a.off, L.n, L.total, L.ctl + CTL_GATE);
     if (tm) tm->mark("check");
-    // the widest filter group any read can need: E is fixed, or at most 31 in the kernel
-    const u32 maxE = a.e_mode == MT_E_FIXED ? a.e_value : (u32)F_MAX_E;
+    // the widest filter group any read can need: E is fixed, or grows with the
+    // length, which is at most F_MAX_M in the kernel (longer reads, and any read
+    // whose band would not fit the instance's groups, take the per-stage path)
+    u64 maxE = a.e_mode == MT_E_FIXED           ? a.e_value
+               : a.e_mode == MT_E_CEIL_PERMILLE ? ((u64)F_MAX_M * a.e_value + 999) / 1000
+                                                : ((u64)F_MAX_M * a.e_value) / 1000;
+    if (maxE > (u64)F_MAX_E) maxE = F_MAX_E;
     if (L.rep) {
         if (maxE <= 7)
             k_fused<16, true><<<L.blocks, 64 * F_WPB, 0, s>>>(a);
