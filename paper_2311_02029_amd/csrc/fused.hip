@@ -445,7 +445,7 @@ __global__ __launch_bounds__(64 * F_WPB) __attribute__((amdgpu_waves_per_eu(5, 8
         if (Ewide > 65534) wflags |= ERR_E_TOO_LARGE;
         const int E = Ewide > 65535 ? 65535 : (int)Ewide;
         if (lane == 0) KA(read_E)[r] = (u16)E;
-        if (m > F_MAX_M || E > F_MAX_E || 2 * E + 1 > MAXG) {
+        if (m > F_MAX_M || E > F_MAX_E) {  // (2E + 1 <= MAXG here: the launch picks MAXG from the largest E)
             if (lane == 0) {
                 KA(fb_list)[atomicAdd(KA(fb_count), 1u)] = (u32)r;
                 KA(ncand)[r] = 0;  // until the per-stage kernels fill it in
@@ -944,8 +944,9 @@ static void enqueue_fused(const FusedLaunch &L, Timer *tm, hipStream_t s) {
     k_check_reads<<<grid_for(L.n, 256), 256, 0, s>>>(a.off, L.n, L.total, L.ctl + CTL_GATE);
     if (tm) tm->mark("check");
     // the widest filter group any read can need: E is fixed, or grows with the
-    // length, which is at most F_MAX_M in the kernel (longer reads, and any read
-    // whose band would not fit the instance's groups, take the per-stage path)
+    // length, which is at most F_MAX_M in the kernel (longer reads take the
+    // per-stage path), so every fused read's 2E + 1 rows fit the instance's
+    // widest group
     u64 maxE = a.e_mode == MT_E_FIXED           ? a.e_value
                : a.e_mode == MT_E_CEIL_PERMILLE ? ((u64)F_MAX_M * a.e_value + 999) / 1000
                                                 : ((u64)F_MAX_M * a.e_value) / 1000;
