@@ -638,6 +638,11 @@ def main() -> int:
                 out[name] = res
                 log(f"[bench] headline {name}: {res}")
             out[args.mode] = {k: v for k, v in plain.items() if k != "stages_ms"}
+            # every candidate kept (top_n = 0): the same reads, all locations with >= min_hits filtered
+            res, _ = time_form(mt, ix, dreads, dict(q, mode=mode, top_n=0), max(3, args.steps // 4), 1, timing=False)
+            res.pop("stages_ms")
+            out["keep_all_fused"] = res
+            log(f"[bench] headline keep-all: {res}")
             return out
         guarded("forms", forms)
     if want("e2e"):
