@@ -86,8 +86,12 @@ static_assert(std::is_standard_layout<FusedArgs>::value, "FusedArgs fields are r
 // registers the loop needs, and spilled scalar registers cost a vector
 // instruction at every use.  FusedArgs is the kernel's only argument, so it
 // starts the segment.
+//
+// The segment's address exists only in the kernel itself: a function compiled
+// apart from the kernel reads it as zero (and then faults), so this helper and
+// every function that uses it are forced inline.
 template <class T>
-__device__ inline T karg_field(size_t off) {
+__device__ __attribute__((always_inline)) inline T karg_field(size_t off) {
     const __attribute__((address_space(4))) char *base =
         (const __attribute__((address_space(4))) char *)__builtin_amdgcn_kernarg_segment_ptr();
     return *(volatile const __attribute__((address_space(4))) T *)(base + off);
@@ -236,7 +240,7 @@ __device__ inline int lds_run(const u64 *row, int j) {
 }
 
 template <int G>
-__device__ inline void filter_batch(const FusedArgs &a, const QEntry *q, int qn, PendRead *pend, int lane,
+__device__ __attribute__((always_inline)) inline void filter_batch(const FusedArgs &a, const QEntry *q, int qn, PendRead *pend, int lane,
                                     u64 *rowbuf) {
     const int gi = lane / G, lane_g = lane % G;
     if (gi >= qn) return;
@@ -299,7 +303,7 @@ __device__ inline void filter_batch(const FusedArgs &a, const QEntry *q, int qn,
 // Read accept flag and per-taxon counts of a read whose candidates are all
 // filtered: the distinct taxa of its accepted candidates with the smallest
 // count; one taxon is unique, several are multi-mapped.
-__device__ inline void finalize_read(const FusedArgs &a, const PendRead &pr, u64 *wst) {
+__device__ __attribute__((always_inline)) inline void finalize_read(const FusedArgs &a, const PendRead &pr, u64 *wst) {
     const int nc = (int)pr.nc, E = pr.E;
     int best = 0x7fffffff;
     for (int c = 0; c < nc; c++)
@@ -336,7 +340,7 @@ __device__ inline void finalize_read(const FusedArgs &a, const PendRead &pr, u64
 // finalizes every pending read whose last candidate it filtered.  Returns the
 // new set of used pending slots.
 template <int MAXG>
-__device__ inline u32 flush_queue(const FusedArgs &a, QEntry *q, int &qn, int qG, PendRead *pend, u32 used,
+__device__ __attribute__((always_inline)) inline u32 flush_queue(const FusedArgs &a, QEntry *q, int &qn, int qG, PendRead *pend, u32 used,
                                   int lane, u64 *wst, u64 *rowbuf) {
     if (qn > 0) {
         if (MAXG == 16 || qG == 16)
