@@ -104,7 +104,6 @@ void classify_staged(const mt_index &ix, const mt_query_params &q, const mt_seqs
                      mt_result &res, Timer &tm, hipStream_t s);
 void classify_fused(const mt_index &ix, const mt_query_params &q, const mt_seqs &reads, ReadBatch &rb,
                     mt_result &res, Timer &tm, hipStream_t s, bool graph);
-void launch_max_u16(const u16 *v, u64 n, u32 *out, hipStream_t s);
 // The taxon step of a batch that holds several requests: reads
 // [slot_off[s], slot_off[s+1]) add into counts[s] = {unique[n_taxa],
 // multi[n_taxa], unmapped} (device arrays; slot_off and counts on the device).

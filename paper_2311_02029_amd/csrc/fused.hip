@@ -1,22 +1,25 @@
 // Fused seed-count + filter path for short reads (Fig. 1 steps 2b-2d and 3a
 // in one kernel).  One wavefront owns one read at a time:
-//   1. its bytes are loaded one per lane and turned into lo / hi / N bit
-//      planes with ballots (wave-uniform words, held in scalar registers);
-//   2. lane i hashes the k-mer at position i (per 64-position round); hashes
-//      and k-mer values go to a per-wave LDS tile;
+//   1. its bytes (requested while the previous read was counted) become
+//      lo / hi / N bit planes with ballots, kept in a per-read LDS slot, and a
+//      big-endian 2-bit stream in LDS;
+//   2. lane i hashes the k-mer at position i (per 64-position round) into a
+//      per-wave LDS tile;
 //   3. lane s scans window s for its smallest valid (hash, position); picks
 //      are marked in LDS and compacted with ballot + popcount;
 //   4. each minimizer lane probes one 64-byte table bucket (all four slots
-//      loaded at once) and writes its (genome, diagonal) hits to LDS;
-//   5. lane j counts how many hits share hit j's location and whether j is
-//      the first of them; locations with >= min_hits become candidates, and
-//      each candidate's rank in (hits desc, genome, diagonal) order picks the
-//      top_n;
-//   6. each kept candidate is filtered by a group of G lanes (G = 16, 32 or
-//      64 by E), one row d of the band per lane: the row's mismatch words for
-//      the whole read stay in registers and the obstacle walk advances by
-//      ctz of the row bits plus a max over the group;
-//   7. the read's accept flag and its per-taxon unique / multi count.
+//      loaded at once); a read's hits are counted in registers, one ballot
+//      per distinct (genome, diagonal), when they fit one lane each, and in a
+//      per-read LDS hash table otherwise;
+//   5. locations with >= min_hits become candidates, and each candidate's
+//      rank in (hits desc, genome, diagonal) order picks the top_n;
+//   6. the kept candidates join a per-wave queue; a full queue is filtered by
+//      groups of G lanes (G = 16, 32 or 64 by E), one band row d per lane:
+//      the row's mismatch words are built from 64-base reference fetches,
+//      parked in LDS, and the obstacle walk advances by ctz of the row bits
+//      plus a max over the group;
+//   7. a read whose candidates are all filtered gets its accept flag and its
+//      per-taxon unique / multi count.
 // Reads beyond the kernel's limits (longer than 256 bases, E above 31, more
 // than 256 seed hits, or more than 8 candidates when every candidate is kept)
 // are queued and finished by the per-stage kernels, so every read gets the
@@ -27,16 +30,6 @@
 #include "classify.hpp"
 
 namespace mt {
-
-__global__ void k_max_u16(const u16 *__restrict__ v, u64 n, u32 *__restrict__ out) {
-    u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) atomicMax(out, (u32)v[i]);
-}
-
-void launch_max_u16(const u16 *v, u64 n, u32 *out, hipStream_t s) {
-    k_max_u16<<<grid_for(n, 256), 256, 0, s>>>(v, n, out);
-    MT_HIP(hipGetLastError());
-}
 
 constexpr int F_WPB = 4;         // wavefronts per block
 constexpr int F_MAX_M = 256;     // longest read the fused kernel takes
