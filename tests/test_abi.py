@@ -44,6 +44,8 @@ int main(void) {
          offsetof(mt_index_info, k), sizeof(mt_server_params), offsetof(mt_server_params, pinned_arena_bytes),
          sizeof(mt_stats));
   printf("%zu %zu %zu\n", sizeof(mt_tune_bucket), offsetof(mt_tune_bucket, ms), offsetof(mt_tune_bucket, pairs));
+  printf("%zu %zu %zu %zu %zu\n", sizeof(mt_mem_stats), offsetof(mt_mem_stats, hooked), sizeof(mt_server_counters),
+         offsetof(mt_server_counters, timed_batches), offsetof(mt_server_counters, kernel_ms_overlap));
   return 0;
 }''')
     exe = tmp_path / "sizes"
@@ -53,7 +55,9 @@ int main(void) {
             C.sizeof(_abi.mt_index_info), _abi.mt_query_params.mode.offset, _abi.mt_index_info.k.offset,
             C.sizeof(_abi.mt_server_params), _abi.mt_server_params.pinned_arena_bytes.offset,
             C.sizeof(_abi.mt_stats), C.sizeof(_abi.mt_tune_bucket), _abi.mt_tune_bucket.ms.offset,
-            _abi.mt_tune_bucket.pairs.offset]
+            _abi.mt_tune_bucket.pairs.offset, C.sizeof(_abi.mt_mem_stats), _abi.mt_mem_stats.hooked.offset,
+            C.sizeof(_abi.mt_server_counters), _abi.mt_server_counters.timed_batches.offset,
+            _abi.mt_server_counters.kernel_ms_overlap.offset]
     assert got == want
 
 
