@@ -104,3 +104,26 @@ def test_many_strains_every_read(mt, many, mode):
     ref = _check(mt, many, mode, min_hits=3, top_n=3, e_value=7)
     hits = np.diff(ref["cand_offsets"].astype(np.int64))
     assert hits.max() == 3 and int(ref["multi"].sum()) > 0
+
+
+@pytest.mark.parametrize("copies", [15, 16])
+@pytest.mark.parametrize("mode", MODES)
+def test_occurrence_count_boundary(mt, copies, mode):
+    """Identical copies of one genome, so every k-mer occurs exactly `copies`
+    times: at 15 a short read's hits (a few probes x 15 <= 64) are counted in
+    registers, at 16 every read goes to the per-read table; reads of 30-90 bp
+    give hit totals on both sides of 64.  Every read against the oracle."""
+    rng = np.random.default_rng(44)
+    one = synth.make_genomes(rng, 1, 20_000)
+    gen = synth.Genomes(codes=np.tile(one.codes, copies),
+                        offsets=np.arange(copies + 1, dtype=np.uint64) * np.uint64(20_000),
+                        taxon=np.arange(copies, dtype=np.uint32) % 4, n_taxa=4)
+    reads, _ = synth.make_reads(rng, gen, rng.integers(30, 91, 3000), 0.005, 0.0005)
+    ga = gen.ascii()
+    d = dict(reads=reads, ix=mt.Index(ga, 21, 11, taxon=gen.taxon, n_taxa=gen.n_taxa),
+             oix=oracle.Index(ga, 21, 11, taxon=gen.taxon, n_taxa=gen.n_taxa))
+    info = d["ix"].info()
+    assert info["n_multi_occ"] == info["n_minimizers"] > 0  # every k-mer repeated
+    for top_n in (3, 0):
+        ref = _check(mt, d, mode, min_hits=2, top_n=top_n, e_value=3)
+        assert ref["read_accepted"].mean() > 0.8
