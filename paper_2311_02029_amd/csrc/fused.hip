@@ -1208,7 +1208,7 @@ struct ContainArgs {
     const u32 *gate;  // offsets check result: nonzero skips the whole launch
 };
 
-constexpr u64 CF_LDS_GENOMES = 2048;  // 64-bit counters, 16 KB per block
+constexpr u64 CF_LDS_GENOMES = 2048;  // 64-bit counters, at most 16 KB per block
 
 __global__ __launch_bounds__(64 * F_WPB) void k_contain_fused(ContainArgs a) {
     __shared__ u64 sh_h[F_WPB][F_MAX_M];
@@ -1216,7 +1216,7 @@ __global__ __launch_bounds__(64 * F_WPB) void k_contain_fused(ContainArgs a) {
     __shared__ u8 sh_pick[F_WPB][F_MAX_M];
     __shared__ u32 sh_st[F_WPB][F_WORDS];
     __shared__ u64 sh_nb[F_WPB][4];
-    __shared__ unsigned long long cnt[CF_LDS_GENOMES];
+    extern __shared__ unsigned long long cnt[];  // one counter per genome when they fit (sized at launch)
     if (*a.gate) return;  // malformed offsets: the whole grid leaves
     const int lane = threadIdx.x & 63, wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     u64 *hh = sh_h[wid];
@@ -1330,11 +1330,15 @@ void containment(const mt_index &ix, const mt_seqs &reads, u64 *hits, hipStream_
     int dev = 0, cus = 0;
     MT_HIP(hipGetDevice(&dev));
     MT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    const u64 blocks = std::min<u64>(grid_for(n, F_WPB), (u64)std::max(cus, 1) * 8);
+    // the genome counters take only the LDS the index needs, so more blocks fit
+    // a CU (eight wavefronts per SIMD for a few hundred genomes); enough blocks
+    // to fill them
+    const u64 blocks = std::min<u64>(grid_for(n, F_WPB), (u64)std::max(cus, 1) * 32);
+    const size_t lds = ix.n_genomes <= CF_LDS_GENOMES ? ix.n_genomes * sizeof(unsigned long long) : 0;
     ContainArgs a{(const u8 *)reads.seq, reads.offsets, n, ix.k, ix.w, ix.table.p, ix.nbuckets, ix.occ.p,
                   ix.n_genomes, (unsigned long long *)hits, fb_list.p, ctl.p + CTL_FB, ctl.p + CTL_FLAGS,
                   ctl.p + CTL_GATE};
-    k_contain_fused<<<(unsigned)blocks, 64 * F_WPB, 0, s>>>(a);
+    k_contain_fused<<<(unsigned)blocks, 64 * F_WPB, lds, s>>>(a);
     MT_HIP(hipGetLastError());
     u32 h[CTL_WORDS];
     read_back(s, ctl.p, h, sizeof h);
