@@ -90,24 +90,49 @@ MUTANTS = [
 ]
 
 
-@pytest.mark.parametrize("name,orig,mut", MUTANTS, ids=[m[0] for m in MUTANTS])
-def test_pins_catch_planted_mistake(name, orig, mut, tmp_path):
+def _run_pins(lib: str, stop_at_first: bool):
+    """The pin suite against the oracle library at `lib`, in a process of its own
+    (one oracle thread: several of these run at once)."""
+    env = dict(os.environ, ORACLE_LIB=lib, OMP_NUM_THREADS="1")
+    args = [sys.executable, "-m", "pytest", *PIN_FILES, "-q", "-p", "no:cacheprovider"] + (["-x"] if stop_at_first else [])
+    return subprocess.run(args, cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+
+
+@pytest.fixture(scope="module")
+def mutant_runs(tmp_path_factory):
+    """Every mutant built and run against the pins, several at a time: name ->
+    (occurrences of its site in oracle.c, return code of the pin suite)."""
+    from concurrent.futures import ThreadPoolExecutor
+    base = tmp_path_factory.mktemp("mutants")
     src = open(SRC).read()
-    assert src.count(orig) == 1, f"mutation site of '{name}' not found exactly once"
-    mutant_c = tmp_path / "oracle_mutant.c"
-    mutant_c.write_text(src.replace(orig, mut))
-    lib = str(tmp_path / "liboracle_mutant.so")
-    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-o", lib, str(mutant_c), "-lm"])
-    env = dict(os.environ, ORACLE_LIB=lib)
-    r = subprocess.run([sys.executable, "-m", "pytest", *PIN_FILES, "-x", "-q", "-p", "no:cacheprovider"], cwd=ROOT,
-                       env=env, capture_output=True, text=True, timeout=600)
-    assert r.returncode != 0, f"no pin caught the planted mistake '{name}'"
+
+    def one(i_m):
+        i, (name, orig, mut) = i_m
+        sites = src.count(orig)
+        if sites != 1:
+            return name, (sites, None)
+        d = base / f"m{i}"
+        d.mkdir()
+        mutant_c = d / "oracle_mutant.c"
+        mutant_c.write_text(src.replace(orig, mut))
+        lib = str(d / "liboracle_mutant.so")
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-o", lib, str(mutant_c),
+                               "-lm"])
+        return name, (sites, _run_pins(lib, True).returncode)
+
+    with ThreadPoolExecutor(max_workers=max(1, min(8, os.cpu_count() or 1))) as ex:
+        return dict(ex.map(one, enumerate(MUTANTS)))
+
+
+@pytest.mark.parametrize("name,orig,mut", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_catch_planted_mistake(name, orig, mut, mutant_runs):
+    sites, rc = mutant_runs[name]
+    assert sites == 1, f"mutation site of '{name}' not found exactly once"
+    assert rc != 0, f"no pin caught the planted mistake '{name}'"
 
 
 def test_unmutated_copy_passes_the_pins(tmp_path):
     lib = str(tmp_path / "liboracle_copy.so")
     oracle.build(lib)
-    env = dict(os.environ, ORACLE_LIB=lib)
-    r = subprocess.run([sys.executable, "-m", "pytest", *PIN_FILES, "-q", "-p", "no:cacheprovider"], cwd=ROOT,
-                       env=env, capture_output=True, text=True, timeout=600)
+    r = _run_pins(lib, False)
     assert r.returncode == 0, r.stdout[-2000:]
