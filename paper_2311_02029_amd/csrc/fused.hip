@@ -1232,11 +1232,37 @@ __global__ __launch_bounds__(64 * F_WPB) void k_contain_fused(ContainArgs a) {
     const u32 k = a.k;
     const u64 kmask = (1ull << k) - 1;
     u32 wflags = 0;
-    for (u64 r = (u64)blockIdx.x * F_WPB + wid; r < a.n; r += (u64)gridDim.x * F_WPB) {
+    const u64 stride = (u64)gridDim.x * F_WPB;
+    u64 r = (u64)blockIdx.x * F_WPB + wid;
+    // the read in hand: its length and its bytes, one per lane per 64-base
+    // round (the next read's are requested while this one is probed)
+    int m = 0;
+    u32 b[4];
+    if (r < a.n) {
         const u64 beg = a.off[r];
-        const int m = (int)(a.off[r + 1] - beg);
+        m = (int)(a.off[r + 1] - beg);
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const int i = 64 * q + lane;
+            b[q] = (m <= F_MAX_M && i < m) ? (u32)a.seq[beg + i] : (u32)'N';
+        }
+    }
+    for (; r < a.n; r += stride) {
+        const u64 rn = r + stride;
+        // the next read's offsets, its start in even lanes and its end in odd
+        // ones (read after the minimizers; a wave-uniform load would be waited
+        // for at once)
+        u64 noff = 0;
+        if (rn < a.n) noff = a.off[rn + (u64)(lane & 1)];
         if (m > F_MAX_M) {
             if (lane == 0) a.fb_list[atomicAdd(a.fb_count, 1u)] = (u32)r;
+            const u64 nbeg = readlane64(noff, 0);
+            m = (int)(readlane64(noff, 1) - nbeg);
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const int i = 64 * q + lane;
+                b[q] = (rn < a.n && m <= F_MAX_M && i < m) ? (u32)a.seq[nbeg + i] : (u32)'N';
+            }
             continue;
         }
         // 1. N plane and big-endian 2-bit stream
@@ -1246,16 +1272,16 @@ __global__ __launch_bounds__(64 * F_WPB) void k_contain_fused(ContainArgs a) {
 #pragma unroll
         for (int q = 0; q < 4; q++) {
             const int i = 64 * q + lane;
-            const u32 c = i < m ? base_code(a.seq[beg + i]) : 4u;
+            const u32 c = i < m ? base_code(b[q]) : 4u;
             bad |= c == 5;
             const u64 nb = ballot64(c >= 4);
             if (lane == 0) nbp[q] = nb;
             if (c < 4 && c > 0) atomicOr(&stream[i >> 4], c << (30 - 2 * (i & 15)));
         }
         if (ballot64(bad)) {
-            wflags |= ERR_BAD_BYTE;  // the call fails
+            wflags |= ERR_BAD_BYTE;  // the call fails; the grid still reads no further bytes
             wave_sync();
-            continue;
+            break;
         }
         wave_sync();
         // 2. k-mer hashes (~0 for k-mers with an N)
@@ -1294,6 +1320,17 @@ __global__ __launch_bounds__(64 * F_WPB) void k_contain_fused(ContainArgs a) {
                 nmin += __popcll(cm);
             }
             wave_sync();
+        }
+        // the next read's bytes, requested ahead of the probes
+        {
+            const u64 nbeg = readlane64(noff, 0);
+            const int nm = (int)(readlane64(noff, 1) - nbeg);
+#pragma unroll
+            for (int q = 0; q < 4; q++) {
+                const int i = 64 * q + lane;
+                b[q] = (rn < a.n && nm <= F_MAX_M && i < nm) ? (u32)a.seq[nbeg + i] : (u32)'N';
+            }
+            m = rn < a.n ? nm : 0;
         }
         // 4. one probe per minimizer; one hit per occurrence to its genome
         for (int t0 = 0; t0 < nmin; t0 += 64) {

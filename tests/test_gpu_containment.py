@@ -106,3 +106,21 @@ def test_select_genomes_exact(mt):
         sel, mx = mt.select_genomes(torch.from_numpy(arr.view(np.int64)).cuda(), num, den)
         osel, omx = oracle.select_genomes(arr, num, den)
         assert mx == omx and np.array_equal(sel.cpu().numpy().astype(np.uint32), osel), (h[:5], num, den)
+
+
+def test_containment_invalid_byte_fails_and_index_still_serves(mt):
+    """A read with a byte outside ACGTN (among short, long and empty reads) makes
+    the call fail with MT_EINVAL; the same index then counts a clean batch
+    exactly like the oracle."""
+    rnd = random.Random(5)
+    genomes, reads = _case(rnd, 4, 3000, 400, 20)
+    ix = mt.Index(synth.SeqSet.from_list(genomes), 15, 10)
+    bad = list(reads)
+    i = next(i for i in range(137, len(reads)) if 30 <= len(reads[i]) <= 256)  # a read the fused kernel takes
+    bad[i] = bad[i][:20] + "*" + bad[i][21:]
+    with pytest.raises(mt.MTError) as e:
+        ix.containment(mt.to_device(synth.SeqSet.from_list(bad)))
+    assert e.value.status == -1
+    got = ix.containment(mt.to_device(synth.SeqSet.from_list(reads))).cpu().numpy().view(np.uint64)
+    want = oracle.Index(synth.SeqSet.from_list(genomes), 15, 10).containment(synth.SeqSet.from_list(reads))
+    assert np.array_equal(got, want)
