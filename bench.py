@@ -801,6 +801,15 @@ def main() -> int:
                                                         "useful_ops_frac": round(float(uo[bk == b].sum()) /
                                                                                  (ms / 1e3 * VALU_LANE_OPS_PEAK), 4)}
                         row["per_stage_filter"] = per
+                        # the index gather alone (per-stage k_lookup): per read minimizer its 8 B key in, its
+                        # 16 B table slot, 8 B value and 4 B count out
+                        lk = res["stages_ms"].get("lookup")
+                        if lk and st.get("n_minimizers"):
+                            gb = 36 * int(st["n_minimizers"]) / (lk / 1e3) / 1e9
+                            row["per_stage_lookup_roofline"] = {
+                                "kernel": "k_lookup", "bound": "hbm", "achieved": round(gb, 1), "unit": "GB/s",
+                                "frac": round(gb / HBM_PEAK_GBS, 4), "lookups": int(st["n_minimizers"]),
+                                "ms": lk, "model": "36 B per lookup: 8 B key in, 16 B slot, 12 B out"}
                 row["fused_over_per_stage"] = round(row["per_stage"]["ms_per_step"] / row["fused"]["ms_per_step"], 3)
                 out["E_sweep"][str(E)] = row
                 log(f"[bench] batched E={E}: fused {row['fused']['ms_per_step']} ms, per-stage "
